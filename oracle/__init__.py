@@ -1,0 +1,201 @@
+"""Python access to the CPU FP64 oracle -- TEST INFRASTRUCTURE ONLY.
+
+Loads ``liboracle.so`` (built from ``oracle.c`` with gcc) through ctypes.
+Only the tests, the smoke check and the benchmark's CPU-baseline leg use
+this package; the GPU library never imports it and shares no code with it.
+See ``oracle.c`` for the definitions each function follows.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OK, INVALID_ARG, NOT_LOWER, UNSORTED_OR_DUP, MISSING_DIAG, ZERO_DIAG, BAD_ROWSET, \
+    BUFFER_TOO_SMALL = 0, -1, -2, -3, -4, -5, -6, -7
+
+STATUS_NAMES = {OK: "OK", INVALID_ARG: "INVALID_ARG", NOT_LOWER: "NOT_LOWER",
+                UNSORTED_OR_DUP: "UNSORTED_OR_DUP", MISSING_DIAG: "MISSING_DIAG",
+                ZERO_DIAG: "ZERO_DIAG", BAD_ROWSET: "BAD_ROWSET",
+                BUFFER_TOO_SMALL: "BUFFER_TOO_SMALL"}
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so (plain gcc, no fused multiply-add)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Stats(C.Structure):
+    _fields_ = [("num_levels", C.c_int32), ("thin_count", C.c_int32),
+                ("S1", C.c_uint64), ("S2_lo", C.c_uint64), ("S2_hi", C.c_uint64),
+                ("cv", C.c_double), ("cv_rows", C.c_double), ("alc", C.c_double),
+                ("arl", C.c_double), ("air", C.c_double), ("thin_threshold", C.c_double)]
+
+
+_lib = None
+
+
+def _L():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        P = C.c_void_p
+        _lib.orc_validate.argtypes = [C.c_int32, P, P, P, P]
+        _lib.orc_validate.restype = C.c_int
+        _lib.orc_analyze.argtypes = [C.c_int32, P, P, P, P, P, P, P, C.POINTER(_Stats)]
+        _lib.orc_analyze.restype = C.c_int32
+        _lib.orc_rewrite.argtypes = [C.c_int32, P, P, P, P, C.c_int32, P, P, C.c_int32, P,
+                                     C.c_int64, P, P, P, C.c_int64, P, C.c_int64, P, P, P,
+                                     C.c_int64, P]
+        _lib.orc_rewrite.restype = C.c_int
+        _lib.orc_solve.argtypes = [C.c_int32, P, P, P, C.c_int32, P, C.c_int64, P, C.c_int64]
+        _lib.orc_solve.restype = None
+        _lib.orc_solve_transpose.argtypes = _lib.orc_solve.argtypes
+        _lib.orc_solve_transpose.restype = None
+        _lib.orc_grad_vals.argtypes = [C.c_int32, P, P, C.c_int32, P, C.c_int64, P,
+                                       C.c_int64, P]
+        _lib.orc_grad_vals.restype = None
+    return _lib
+
+
+def _p(a: np.ndarray | None):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+@dataclass
+class Analysis:
+    level: np.ndarray      # int32 [n]
+    rows: np.ndarray       # int32 [D]
+    cost: np.ndarray       # int64 [D]
+    perm: np.ndarray       # int32 [n]
+    level_ptr: np.ndarray  # int32 [D+1]
+    num_levels: int
+    S1: int
+    S2: int
+    cv: float
+    cv_rows: float
+    alc: float
+    arl: float
+    air: float
+    thin_threshold: float
+    thin_count: int
+
+
+def validate(n, rowptr, colidx, vals=None) -> tuple[int, int]:
+    bad = np.zeros(1, dtype=np.int32)
+    vals = None if vals is None else _f64(vals)
+    st = _L().orc_validate(n, _p(_i32(rowptr)), _p(_i32(colidx)), _p(vals), _p(bad))
+    return int(st), int(bad[0])
+
+
+def analyze(n, rowptr, colidx) -> Analysis:
+    rowptr = _i32(rowptr)
+    colidx = _i32(colidx)
+    level = np.zeros(max(n, 1), dtype=np.int32)
+    rows = np.zeros(max(n, 1), dtype=np.int32)
+    cost = np.zeros(max(n, 1), dtype=np.int64)
+    perm = np.zeros(max(n, 1), dtype=np.int32)
+    lptr = np.zeros(n + 1, dtype=np.int32)
+    st = _Stats()
+    D = _L().orc_analyze(n, _p(rowptr), _p(colidx), _p(level), _p(rows), _p(cost),
+                         _p(perm), _p(lptr), C.byref(st))
+    return Analysis(level[:n], rows[:D], cost[:D], perm[:n], lptr[:D + 1], int(D),
+                    int(st.S1), int(st.S2_lo) | (int(st.S2_hi) << 64), st.cv, st.cv_rows,
+                    st.alc, st.arl, st.air, st.thin_threshold, int(st.thin_count))
+
+
+@dataclass
+class Rewritten:
+    rowptr: np.ndarray
+    colidx: np.ndarray
+    vals: np.ndarray
+    Bp: np.ndarray          # (k, n)
+    c_ptr: np.ndarray       # int32 [m+1]
+    c_col: np.ndarray
+    c_val: np.ndarray
+    skipped: int
+
+
+def rewrite(n, rowptr, colidx, vals, level, rows, targets=None, B=None) -> Rewritten:
+    rowptr, colidx, vals, level = _i32(rowptr), _i32(colidx), _f64(vals), _i32(level)
+    rows = _i32(rows)
+    targets = None if targets is None else _i32(targets)
+    m = rows.shape[0]
+    if B is None:
+        B = np.zeros((0, n))
+    B = _f64(B)
+    k = B.shape[0]
+    sizes = np.zeros(3, dtype=np.int64)
+    lib = _L()
+    st = lib.orc_rewrite(n, _p(rowptr), _p(colidx), _p(vals), _p(level), m, _p(rows),
+                         _p(targets), k, _p(B), n, None, None, None, 0, None, n, None,
+                         None, None, 0, _p(sizes))
+    if st not in (OK, BUFFER_TOO_SMALL):
+        raise ValueError("oracle rewrite: " + STATUS_NAMES.get(st, str(st)))
+    nnz, nc = int(sizes[0]), int(sizes[1])
+    orp = np.zeros(n + 1, dtype=np.int32)
+    oci = np.zeros(max(nnz, 1), dtype=np.int32)
+    ov = np.zeros(max(nnz, 1), dtype=np.float64)
+    Bp = np.zeros((k, n), dtype=np.float64)
+    cp = np.zeros(m + 1, dtype=np.int32)
+    cc = np.zeros(max(nc, 1), dtype=np.int32)
+    cv = np.zeros(max(nc, 1), dtype=np.float64)
+    st = lib.orc_rewrite(n, _p(rowptr), _p(colidx), _p(vals), _p(level), m, _p(rows),
+                         _p(targets), k, _p(B), n, _p(orp), _p(oci), _p(ov), nnz, _p(Bp), n,
+                         _p(cp), _p(cc), _p(cv), nc, _p(sizes))
+    if st != OK:
+        raise ValueError("oracle rewrite: " + STATUS_NAMES.get(st, str(st)))
+    return Rewritten(orp, oci[:nnz], ov[:nnz], Bp, cp, cc[:nc], cv[:nc], int(sizes[2]))
+
+
+def solve(n, rowptr, colidx, vals, B) -> np.ndarray:
+    """X = L^{-1} B; B has shape (k, n) (column-major n x k)."""
+    B = _f64(np.atleast_2d(B))
+    X = np.zeros_like(B)
+    _L().orc_solve(n, _p(_i32(rowptr)), _p(_i32(colidx)), _p(_f64(vals)), B.shape[0],
+                   _p(B), n, _p(X), n)
+    return X
+
+
+def solve_transpose(n, rowptr, colidx, vals, G) -> np.ndarray:
+    """Y = L^{-T} G; G has shape (k, n)."""
+    G = _f64(np.atleast_2d(G))
+    Y = np.zeros_like(G)
+    _L().orc_solve_transpose(n, _p(_i32(rowptr)), _p(_i32(colidx)), _p(_f64(vals)),
+                             G.shape[0], _p(G), n, _p(Y), n)
+    return Y
+
+
+def grad_vals(n, rowptr, colidx, Y, X) -> np.ndarray:
+    Y = _f64(np.atleast_2d(Y))
+    X = _f64(np.atleast_2d(X))
+    out = np.zeros(int(rowptr[-1]), dtype=np.float64)
+    _L().orc_grad_vals(n, _p(_i32(rowptr)), _p(_i32(colidx)), Y.shape[0], _p(Y), n, _p(X),
+                       n, _p(out))
+    return out
+
+
+def adjoint(n, rowptr, colidx, vals, X, G) -> tuple[np.ndarray, np.ndarray]:
+    """Gradients of sum(G * X) with X = L^{-1} B: (grad_B, grad_vals)."""
+    Y = solve_transpose(n, rowptr, colidx, vals, G)
+    return Y, grad_vals(n, rowptr, colidx, Y, X)
