@@ -1,0 +1,262 @@
+/*
+ * rwtrsv -- sparse triangular solve on equation-rewritten dependency DAGs,
+ * with the level-set analysis that scores each rewrite.  MI355X (gfx950).
+ *
+ * The problem (paper Section 2.1): solve L X = B for a sparse lower
+ * triangular L stored in CSR.  Row i is a node of a dependency DAG, each
+ * off-diagonal entry L_ij an edge j -> i.  The level-set method groups rows
+ * into levels (longest path from a source) that can be solved in parallel,
+ * one level after another.  Equation rewriting (Section 2.2) replaces a
+ * row's dependency on row j by row j's own equation, which moves the row to
+ * an earlier level; the result is again a lower triangular CSR matrix L'
+ * with a patched right-hand side B' and the same solution X.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Matrices: int32 rowptr[n+1], int32 colidx[nnz], values FP64 or FP32.
+ *    Inside a row the columns strictly ascend and the diagonal is the last
+ *    entry (rwt_validate checks this).  nnz < 2^31.
+ *  - Dense blocks of k right-hand sides: column-major n x k, leading
+ *    dimension ld >= n, same value type as the matrix.
+ *  - Every pointer argument named d_* (and every pointer inside rwt_csr) is
+ *    device memory; h_* is host memory.  The library never allocates device
+ *    memory: the caller passes a workspace of at least the size returned by
+ *    the matching *_ws query and keeps it alive while a plan uses it.
+ *  - Every call is ordered on the given HIP stream.  Calls that return
+ *    host data (h_* outputs) synchronize that stream before returning.
+ *  - Return value: RWT_OK or a negative rwt_status; rwt_last_error_string()
+ *    (thread-local) describes the last failure of the calling thread.
+ *    No call launches any kernel after detecting an argument error.
+ */
+#ifndef RWTRSV_H
+#define RWTRSV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* rwt_stream_t;   /* hipStream_t; NULL = default stream */
+
+typedef enum {
+    RWT_OK = 0,
+    RWT_ERR_INVALID_ARG = -1,      /* null pointer, negative size, bad rowptr, ld < n */
+    RWT_ERR_NOT_LOWER = -2,        /* an entry lies above the diagonal or col < 0 */
+    RWT_ERR_UNSORTED_OR_DUP = -3,  /* columns of a row not strictly ascending */
+    RWT_ERR_MISSING_DIAG = -4,     /* a row's last entry is not its diagonal */
+    RWT_ERR_ZERO_DIAG = -5,        /* a stored diagonal equals zero */
+    RWT_ERR_BAD_ROWSET = -6,       /* rewrite rows unsorted/duplicate/out of range, target < 0 */
+    RWT_ERR_BUFFER_TOO_SMALL = -7, /* workspace or output capacity below what is needed */
+    RWT_ERR_TOO_LARGE = -8,        /* sizes beyond the int32 index range or an internal limit */
+    RWT_ERR_DEADLOCK = -9,         /* a bounded device wait expired (watchdog) */
+    RWT_ERR_HIP = -10              /* HIP runtime error, see rwt_last_hip_error() */
+} rwt_status;
+
+typedef enum { RWT_F64 = 0, RWT_F32 = 1 } rwt_dtype;
+
+/* A CSR view.  vals may be NULL for calls that use the pattern only. */
+typedef struct {
+    int32_t n;
+    int32_t pad_;
+    int64_t nnz;
+    const int32_t* rowptr;   /* device, n+1 */
+    const int32_t* colidx;   /* device, nnz */
+    const void* vals;        /* device, nnz, type dt (nullable) */
+    rwt_dtype dt;
+    int32_t pad2_;
+} rwt_csr;
+
+/* Level statistics (Section 4.1 and Table 1: level count, per-level cost,
+ * coefficient of variation of level costs and of level node counts, and
+ * the ALC / ARL / AIR features of Section 3).
+ * cost of a row = 2*nnz_row - 1 (one multiply and one subtract per
+ * dependency and one division); S1 = sum of level costs = 2*nnz - n;
+ * S2 = sum of squared level costs (exact, 128 bit);
+ * cv = sqrt(D*S2 - S1^2)/S1 with the radicand exact before one rounding;
+ * thin_threshold = ALC*(1 + max(0, 1 - cv)) (alpha = 1); thin_count =
+ * number of levels with cost < thin_threshold. */
+typedef struct {
+    int32_t num_levels;
+    int32_t thin_count;
+    uint64_t S1;
+    uint64_t S2_lo;
+    uint64_t S2_hi;
+    double cv;
+    double cv_rows;
+    double alc;
+    double arl;
+    double air;
+    double thin_threshold;
+    int32_t max_level_rows;   /* rows on the widest level */
+    int32_t pad_;
+} rwt_level_stats;
+
+const char* rwt_last_error_string(void);
+int rwt_last_hip_error(void);
+const char* rwt_version(void);
+
+/* ------------------------------------------------------------------------
+ * Validation (CSR interchange format of Section 2.2).  Reports the error of
+ * the lowest offending row (*h_bad_row, -1 when none or not row-specific);
+ * inside the row the first offending entry decides, an entry above the
+ * diagonal beating an out-of-order one; ZERO_DIAG is checked only when
+ * L->vals is not NULL.  Workspace: rwt_validate_ws bytes.  Synchronizes.
+ * ---------------------------------------------------------------------- */
+size_t rwt_validate_ws(void);
+rwt_status rwt_validate(const rwt_csr* L, void* d_ws, size_t ws_bytes,
+                        int32_t* h_bad_row, rwt_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Level-set analysis (Section 2.1: rows of one level are independent; the
+ * level of row i is 0 without dependencies, else 1 + the largest level of
+ * its dependencies).  Outputs (device, caller-allocated):
+ *   d_level[n]        level of each row
+ *   d_perm[n]         rows ordered by (level, row)
+ *   d_level_ptr[n+1]  offsets of each level in d_perm (first D+1 used)
+ *   d_rows[n]         rows per level (first D used)
+ *   d_cost[n]         int64 cost per level (first D used)
+ *   d_stats           statistics, device copy (always written)
+ *   h_stats           host copy (nullable; non-NULL synchronizes)
+ * Workspace: rwt_analyze_ws(L) bytes.  The pattern is assumed valid.
+ * ---------------------------------------------------------------------- */
+rwt_status rwt_analyze_ws(const rwt_csr* L, size_t* h_bytes);
+rwt_status rwt_analyze(const rwt_csr* L, void* d_ws, size_t ws_bytes,
+                       int32_t* d_level, int32_t* d_perm, int32_t* d_level_ptr,
+                       int32_t* d_rows, int64_t* d_cost, rwt_level_stats* d_stats,
+                       rwt_level_stats* h_stats, rwt_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Equation rewriting (Section 2.2; the rewriting list of <node, source
+ * level, target level> triplets of Algorithm 1).  For each rewritten row r
+ * with target level t, every dependency j with level[j] >= t is replaced by
+ * row j's equation: row r -= c*row j with c = (current entry at j)/L_jj,
+ * and B'[r,:] -= c*B[j,:].  Substitutions introduced by this are applied in
+ * turn, always taking the largest such column first, until every remaining
+ * dependency lies below level t.  The substituted rows are those of the
+ * input L (the whole set is applied at once).  Entries that cancel to zero
+ * stay in the pattern.  Rows outside the set are copied.
+ *
+ * Row set: d_set_rows[m] strictly ascending, d_targets[m] (NULL: level-1).
+ * A row on level 0 or with target >= its level is copied unchanged and
+ * counted in sizes[2].  d_level must be the analysis of L.
+ *
+ * rwt_rewrite_symbolic computes d_rowptr_out[n+1] (L') and d_cptr_out[m+1]
+ * (offsets of each set row's substitutions) and returns on the host
+ * h_sizes[0] = nnz(L'), h_sizes[1] = number of substitutions,
+ * h_sizes[2] = set rows left unchanged (synchronizes).
+ * rwt_rewrite_numeric fills Lp->colidx/vals (capacity h_sizes[0]),
+ * d_Bp (n x k, ldbp; may not alias d_B) and the multipliers:
+ * d_crow/d_ccol/d_cval[h_sizes[1]]: substitution e subtracted
+ * d_cval[e] * (row d_ccol[e]) from row d_crow[e]; so L' = M L and B' = M B
+ * with M = I - C.  Multiplier arrays may be NULL.  Lp->rowptr must be the
+ * d_rowptr_out of the symbolic call.  Workspace: rwt_rewrite_ws bytes
+ * (same workspace, untouched in between, for both calls).
+ * ---------------------------------------------------------------------- */
+rwt_status rwt_rewrite_ws(const rwt_csr* L, int32_t m, size_t* h_bytes);
+rwt_status rwt_rewrite_symbolic(const rwt_csr* L, const int32_t* d_level,
+                                const int32_t* d_set_rows, const int32_t* d_targets,
+                                int32_t m, void* d_ws, size_t ws_bytes,
+                                int32_t* d_rowptr_out, int32_t* d_cptr_out,
+                                int64_t* h_sizes, rwt_stream_t stream);
+rwt_status rwt_rewrite_numeric(const rwt_csr* L, const int32_t* d_level,
+                               const int32_t* d_set_rows, const int32_t* d_targets,
+                               int32_t m, const void* d_B, int32_t k, int64_t ldb,
+                               const rwt_csr* Lp, void* d_Bp, int64_t ldbp,
+                               int32_t* d_crow, int32_t* d_ccol, void* d_cval,
+                               void* d_ws, size_t ws_bytes, rwt_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Solve plans.  A plan holds the analysis of one matrix, the transposed
+ * pattern for the adjoint, and the execution schedule:
+ *   RWT_ALGO_LEVEL    level-scheduled: the rows of a level in parallel, a
+ *                     device-wide barrier between levels (Section 2.1);
+ *                     runs of narrow levels go to one workgroup with the x
+ *                     values of the run staged in LDS;
+ *   RWT_ALGO_SYNCFREE synchronization-free (Section 7): row blocks claimed
+ *                     in row order, each block solved level by level in
+ *                     LDS, waiting on per-row readiness in HBM for
+ *                     dependencies outside the block;
+ *   RWT_ALGO_AUTO     autotuned: both candidates are timed once on the
+ *                     plan's matrix and the faster kept.
+ * The plan keeps pointers to L (pattern and values): the caller keeps them
+ * alive and may change the values between solves.  The plan's device
+ * state lives in the caller's workspace (rwt_plan_ws bytes).
+ * ---------------------------------------------------------------------- */
+typedef enum { RWT_ALGO_AUTO = 0, RWT_ALGO_LEVEL = 1, RWT_ALGO_SYNCFREE = 2 } rwt_algo;
+
+typedef struct {
+    rwt_algo algo;            /* forward and transposed solves */
+    int32_t block_rows;       /* sync-free rows per block (0: choose) */
+    int32_t lanes_per_row;    /* 0: choose from the mean row length; else 1..64, power of 2 */
+    int32_t narrow_rows;      /* level-scheduled: levels up to this many rows run on one workgroup (-1: choose) */
+    int32_t kmax;             /* largest number of right-hand sides solved at once (>=1) */
+    int32_t watchdog_ms;      /* bound on any device wait (0: 2000 ms) */
+} rwt_plan_opts;
+
+typedef struct rwt_plan rwt_plan;
+
+typedef struct {
+    rwt_level_stats stats;
+    rwt_algo algo_fwd;
+    rwt_algo algo_bwd;
+    int32_t block_rows;
+    int32_t lanes_per_row;
+    int32_t narrow_rows;
+    int32_t num_blocks;
+    int32_t grid;             /* workgroups of the persistent launches */
+    int32_t pad_;
+    double tuned_ms_level;    /* autotuner measurements (0 when not tuned) */
+    double tuned_ms_syncfree;
+} rwt_plan_info;
+
+rwt_status rwt_plan_ws(const rwt_csr* L, const rwt_plan_opts* opts, size_t* h_bytes);
+rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opts, void* d_ws,
+                           size_t ws_bytes, rwt_plan** out, rwt_stream_t stream);
+rwt_status rwt_plan_get_info(const rwt_plan* plan, rwt_plan_info* h_info);
+/* device arrays owned by the plan's workspace: level[n], perm[n], level_ptr[D+1] */
+rwt_status rwt_plan_levels(const rwt_plan* plan, const int32_t** d_level,
+                           const int32_t** d_perm, const int32_t** d_level_ptr);
+rwt_status rwt_plan_destroy(rwt_plan* plan);
+
+/* Forward solve L X = B (Section 2.1).  k <= kmax.  d_X may equal d_B
+ * (in place).  A watchdog expiry returns RWT_ERR_DEADLOCK (synchronizing
+ * only when it must report). */
+rwt_status rwt_solve(const rwt_plan* plan, const void* d_B, int32_t k, int64_t ldb,
+                     void* d_X, int64_t ldx, rwt_stream_t stream);
+
+/* Transposed solve L^T Y = G (the adjoint: upper triangular, levels taken
+ * in reverse order).  d_Y may equal d_G. */
+rwt_status rwt_solve_transpose(const rwt_plan* plan, const void* d_G, int32_t k, int64_t ldg,
+                               void* d_Y, int64_t ldy, rwt_stream_t stream);
+
+/* Device error word of the last solve on this plan (RWT_OK or
+ * RWT_ERR_DEADLOCK).  Synchronizes the stream. */
+rwt_status rwt_plan_check(const rwt_plan* plan, rwt_stream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Adjoint helpers.  With X = L^{-1} B, G = dLoss/dX and the rewritten system
+ * L' = M L, B' = M B (M = I - C):  Y = L'^{-T} G, grad_B = M^T Y = Y - C^T Y
+ * and grad_L = -grad_B X^T restricted to L's pattern.
+ *
+ * rwt_apply_MT: d_out = d_Y - C^T d_Y for the multipliers of a rewrite
+ * (nC entries d_crow/d_ccol/d_cval, grouped by d_crow ascending as written
+ * by rwt_rewrite_numeric).  Deterministic (no atomics): the workspace
+ * (rwt_apply_MT_ws bytes) holds C^T, built by the call.  d_out may not alias
+ * d_Y.
+ * rwt_grad_vals: d_gvals[p] = -sum_q d_gB[row_p, q] * d_X[col_p, q] for every
+ * stored entry p of the pattern of L (diagonal included).
+ * ---------------------------------------------------------------------- */
+rwt_status rwt_apply_MT_ws(int32_t n, int64_t nC, size_t* h_bytes);
+rwt_status rwt_apply_MT(int32_t n, int64_t nC, const int32_t* d_crow, const int32_t* d_ccol,
+                        const void* d_cval, rwt_dtype dt, const void* d_Y, int32_t k, int64_t ldy,
+                        void* d_out, int64_t ldo, void* d_ws, size_t ws_bytes,
+                        rwt_stream_t stream);
+rwt_status rwt_grad_vals(const rwt_csr* L, const void* d_gB, int64_t ldg, const void* d_X,
+                         int64_t ldx, int32_t k, void* d_gvals, rwt_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RWTRSV_H */

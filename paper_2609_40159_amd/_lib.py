@@ -1,0 +1,119 @@
+"""ctypes declarations for librwtrsv.so (the C ABI in include/rwtrsv.h).
+
+Argument marshalling only: every step of the solve path runs in the HIP
+library.  Importing this module fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librwtrsv.so")
+
+OK = 0
+STATUS = {
+    0: "OK", -1: "INVALID_ARG", -2: "NOT_LOWER", -3: "UNSORTED_OR_DUP", -4: "MISSING_DIAG",
+    -5: "ZERO_DIAG", -6: "BAD_ROWSET", -7: "BUFFER_TOO_SMALL", -8: "TOO_LARGE", -9: "DEADLOCK",
+    -10: "HIP",
+}
+F64, F32 = 0, 1
+ALGO = {"auto": 0, "level": 1, "syncfree": 2}
+ALGO_NAME = {v: k for k, v in ALGO.items()}
+
+
+class RwtError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+
+
+class Csr(C.Structure):
+    _fields_ = [("n", C.c_int32), ("pad_", C.c_int32), ("nnz", C.c_int64),
+                ("rowptr", C.c_void_p), ("colidx", C.c_void_p), ("vals", C.c_void_p),
+                ("dt", C.c_int32), ("pad2_", C.c_int32)]
+
+
+class LevelStats(C.Structure):
+    _fields_ = [("num_levels", C.c_int32), ("thin_count", C.c_int32), ("S1", C.c_uint64),
+                ("S2_lo", C.c_uint64), ("S2_hi", C.c_uint64), ("cv", C.c_double),
+                ("cv_rows", C.c_double), ("alc", C.c_double), ("arl", C.c_double),
+                ("air", C.c_double), ("thin_threshold", C.c_double),
+                ("max_level_rows", C.c_int32), ("pad_", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        d = {f: getattr(self, f) for f, _ in self._fields_ if not f.startswith("pad")}
+        d["S2"] = int(self.S2_lo) | (int(self.S2_hi) << 64)
+        return d
+
+
+class PlanOpts(C.Structure):
+    _fields_ = [("algo", C.c_int32), ("block_rows", C.c_int32), ("lanes_per_row", C.c_int32),
+                ("narrow_rows", C.c_int32), ("kmax", C.c_int32), ("watchdog_ms", C.c_int32)]
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [("stats", LevelStats), ("algo_fwd", C.c_int32), ("algo_bwd", C.c_int32),
+                ("block_rows", C.c_int32), ("lanes_per_row", C.c_int32),
+                ("narrow_rows", C.c_int32), ("num_blocks", C.c_int32), ("grid", C.c_int32),
+                ("pad_", C.c_int32), ("tuned_ms_level", C.c_double),
+                ("tuned_ms_syncfree", C.c_double)]
+
+
+P = C.c_void_p
+I32 = C.c_int32
+I64 = C.c_int64
+SZ = C.c_size_t
+
+# name -> (restype, argtypes); every symbol include/rwtrsv.h declares
+SIGNATURES = {
+    "rwt_last_error_string": (C.c_char_p, []),
+    "rwt_last_hip_error": (C.c_int, []),
+    "rwt_version": (C.c_char_p, []),
+    "rwt_validate_ws": (SZ, []),
+    "rwt_validate": (C.c_int, [C.POINTER(Csr), P, SZ, C.POINTER(I32), P]),
+    "rwt_analyze_ws": (C.c_int, [C.POINTER(Csr), C.POINTER(SZ)]),
+    "rwt_analyze": (C.c_int, [C.POINTER(Csr), P, SZ, P, P, P, P, P, P, C.POINTER(LevelStats), P]),
+    "rwt_rewrite_ws": (C.c_int, [C.POINTER(Csr), I32, C.POINTER(SZ)]),
+    "rwt_rewrite_symbolic": (C.c_int, [C.POINTER(Csr), P, P, P, I32, P, SZ, P, P,
+                                       C.POINTER(I64), P]),
+    "rwt_rewrite_numeric": (C.c_int, [C.POINTER(Csr), P, P, P, I32, P, I32, I64,
+                                      C.POINTER(Csr), P, I64, P, P, P, P, SZ, P]),
+    "rwt_plan_ws": (C.c_int, [C.POINTER(Csr), C.POINTER(PlanOpts), C.POINTER(SZ)]),
+    "rwt_plan_create": (C.c_int, [C.POINTER(Csr), C.POINTER(PlanOpts), P, SZ, C.POINTER(P), P]),
+    "rwt_plan_get_info": (C.c_int, [P, C.POINTER(PlanInfo)]),
+    "rwt_plan_levels": (C.c_int, [P, C.POINTER(P), C.POINTER(P), C.POINTER(P)]),
+    "rwt_plan_destroy": (C.c_int, [P]),
+    "rwt_solve": (C.c_int, [P, P, I32, I64, P, I64, P]),
+    "rwt_solve_transpose": (C.c_int, [P, P, I32, I64, P, I64, P]),
+    "rwt_plan_check": (C.c_int, [P, P]),
+    "rwt_apply_MT_ws": (C.c_int, [I32, I64, C.POINTER(SZ)]),
+    "rwt_apply_MT": (C.c_int, [I32, I64, P, P, P, I32, P, I32, I64, P, I64, P, SZ, P]),
+    "rwt_grad_vals": (C.c_int, [C.POINTER(Csr), P, I64, P, I64, I32, P, P]),
+}
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with paper_2609_40159_amd.build.build() "
+            "(there is no fallback implementation)")
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(status: int) -> None:
+    if status != OK:
+        msg = load().rwt_last_error_string().decode(errors="replace")
+        raise RwtError(status, msg)

@@ -1,0 +1,320 @@
+"""Python surface of the HIP library: analyze, rewrite, solve plans, adjoint.
+
+PyTorch provides device memory and streams; every computation runs in
+librwtrsv.so.  Dense blocks of k right-hand sides are torch tensors of shape
+(k, n) (column q contiguous, i.e. column-major n x k with leading dimension
+n) or of shape (n,) for a single right-hand side.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import RwtError, check
+
+__all__ = ["CSRMatrix", "LevelInfo", "validate", "analyze", "rewrite", "Rewrite", "Rewriter", "Plan",
+           "apply_MT", "grad_vals", "RwtError"]
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dt(dtype: torch.dtype) -> int:
+    if dtype == torch.float64:
+        return _lib.F64
+    if dtype == torch.float32:
+        return _lib.F32
+    raise TypeError(f"unsupported value type {dtype}")
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+@dataclass
+class CSRMatrix:
+    """Lower-triangular CSR on the GPU (diagonal last in each row)."""
+    rowptr: torch.Tensor   # int32 [n+1]
+    colidx: torch.Tensor   # int32 [nnz]
+    vals: torch.Tensor | None   # float64/float32 [nnz]
+
+    @property
+    def n(self) -> int:
+        return self.rowptr.numel() - 1
+
+    @property
+    def nnz(self) -> int:
+        return self.colidx.numel()
+
+    @property
+    def device(self):
+        return self.rowptr.device
+
+    @property
+    def dtype(self):
+        return self.vals.dtype if self.vals is not None else torch.float64
+
+    @classmethod
+    def from_arrays(cls, rowptr, colidx, vals=None, device="cuda", dtype=torch.float64):
+        rp = torch.as_tensor(rowptr, dtype=torch.int32).to(device).contiguous()
+        ci = torch.as_tensor(colidx, dtype=torch.int32).to(device).contiguous()
+        v = None if vals is None else torch.as_tensor(vals).to(device=device, dtype=dtype).contiguous()
+        return cls(rp, ci, v)
+
+    def view(self) -> _lib.Csr:
+        c = _lib.Csr()
+        c.n = self.n
+        c.nnz = self.nnz
+        c.rowptr = self.rowptr.data_ptr()
+        c.colidx = self.colidx.data_ptr() if self.nnz else None
+        c.vals = self.vals.data_ptr() if self.vals is not None and self.nnz else None
+        c.dt = _dt(self.dtype)
+        return c
+
+    def with_vals(self, vals: torch.Tensor) -> "CSRMatrix":
+        return CSRMatrix(self.rowptr, self.colidx, vals)
+
+
+def validate(L: CSRMatrix) -> tuple[str, int]:
+    """(status name, offending row or -1)."""
+    lib = _lib.load()
+    ws = _workspace(lib.rwt_validate_ws(), L.device)
+    bad = C.c_int32(-1)
+    st = lib.rwt_validate(C.byref(L.view()), _ptr(ws), ws.numel(), C.byref(bad), _stream())
+    return _lib.STATUS.get(st, str(st)), int(bad.value)
+
+
+@dataclass
+class LevelInfo:
+    level: torch.Tensor       # int32 [n]
+    perm: torch.Tensor        # int32 [n]
+    level_ptr: torch.Tensor   # int32 [D+1]
+    rows: torch.Tensor        # int32 [D]
+    cost: torch.Tensor        # int64 [D]
+    stats: dict
+    device_stats: torch.Tensor  # raw device copy of the statistics struct
+
+    @property
+    def num_levels(self) -> int:
+        return int(self.stats["num_levels"])
+
+
+def analyze(L: CSRMatrix) -> LevelInfo:
+    """Level-set analysis (levels, (level,row) order, per-level rows/cost, CV...)."""
+    lib = _lib.load()
+    n = L.n
+    dev = L.device
+    sz = C.c_size_t(0)
+    check(lib.rwt_analyze_ws(C.byref(L.view()), C.byref(sz)))
+    ws = _workspace(sz.value, dev)
+    level = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    perm = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    lptr = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    rows = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    cost = torch.empty(max(n, 1), dtype=torch.int64, device=dev)
+    dstats = torch.empty(C.sizeof(_lib.LevelStats), dtype=torch.uint8, device=dev)
+    hs = _lib.LevelStats()
+    check(lib.rwt_analyze(C.byref(L.view()), _ptr(ws), ws.numel(), _ptr(level), _ptr(perm),
+                          _ptr(lptr), _ptr(rows), _ptr(cost), _ptr(dstats), C.byref(hs),
+                          _stream()))
+    D = int(hs.num_levels)
+    return LevelInfo(level[:n], perm[:n], lptr[:D + 1], rows[:D], cost[:D], hs.as_dict(), dstats)
+
+
+@dataclass
+class Rewrite:
+    L: CSRMatrix              # rewritten matrix L'
+    B: torch.Tensor | None    # B' (k, n)
+    crow: torch.Tensor        # substitution e: row crow[e] -= cval[e] * row ccol[e]
+    ccol: torch.Tensor
+    cval: torch.Tensor
+    cptr: torch.Tensor        # offsets of each set row's substitutions
+    skipped: int
+
+
+def _block(B: torch.Tensor | None, n: int, dtype) -> tuple[torch.Tensor | None, int]:
+    if B is None:
+        return None, 0
+    if B.dim() == 1:
+        B = B.reshape(1, -1)
+    if B.shape[-1] != n or B.dtype != dtype or not B.is_contiguous():
+        raise ValueError(f"dense block must be a contiguous (k, {n}) tensor of {dtype}")
+    return B, B.shape[0]
+
+
+class Rewriter:
+    """Symbolic rewrite of a row set, kept so the numeric part can be re-run
+    for new values or right-hand sides into the same L' buffers."""
+
+    def __init__(self, L: CSRMatrix, level: torch.Tensor, rows, targets=None):
+        lib = _lib.load()
+        self._lib = lib
+        n = L.n
+        dev = L.device
+        self.L = L
+        self.level = level
+        self.rows = torch.as_tensor(rows, dtype=torch.int32).to(dev).contiguous()
+        self.m = self.rows.numel()
+        self.targets = (None if targets is None else
+                        torch.as_tensor(targets, dtype=torch.int32).to(dev).contiguous())
+        sz = C.c_size_t(0)
+        check(lib.rwt_rewrite_ws(C.byref(L.view()), self.m, C.byref(sz)))
+        self.ws = _workspace(sz.value, dev)
+        rowptr = torch.empty(n + 1, dtype=torch.int32, device=dev)
+        self.cptr = torch.empty(self.m + 1, dtype=torch.int32, device=dev)
+        sizes = (C.c_int64 * 3)()
+        check(lib.rwt_rewrite_symbolic(C.byref(L.view()), _ptr(level), _ptr(self.rows),
+                                       _ptr(self.targets), self.m, _ptr(self.ws), self.ws.numel(),
+                                       _ptr(rowptr), _ptr(self.cptr), sizes, _stream()))
+        self.nnz, self.nc, self.skipped = int(sizes[0]), int(sizes[1]), int(sizes[2])
+        colidx = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=dev)
+        vals = torch.empty(max(self.nnz, 1), dtype=L.dtype, device=dev)
+        self.Lp = CSRMatrix(rowptr, colidx[:self.nnz], vals[:self.nnz])
+        self._colidx, self._vals = colidx, vals
+        self.crow = torch.empty(max(self.nc, 1), dtype=torch.int32, device=dev)
+        self.ccol = torch.empty(max(self.nc, 1), dtype=torch.int32, device=dev)
+        self.cval = torch.empty(max(self.nc, 1), dtype=L.dtype, device=dev)
+
+    def numeric(self, vals: torch.Tensor | None = None,
+                B: torch.Tensor | None = None) -> torch.Tensor | None:
+        """Fill L' values (in place) and the multipliers; return B' for B."""
+        L = self.L if vals is None else self.L.with_vals(vals.contiguous())
+        n = L.n
+        B2, k = _block(B, n, L.dtype)
+        Bp = torch.empty((k, n), dtype=L.dtype, device=L.device) if B2 is not None else None
+        lpv = _lib.Csr()
+        lpv.n = n
+        lpv.nnz = self.nnz
+        lpv.rowptr = self.Lp.rowptr.data_ptr()
+        lpv.colidx = self._colidx.data_ptr()
+        lpv.vals = self._vals.data_ptr()
+        lpv.dt = _dt(L.dtype)
+        check(self._lib.rwt_rewrite_numeric(
+            C.byref(L.view()), _ptr(self.level), _ptr(self.rows), _ptr(self.targets), self.m,
+            _ptr(B2), k, n, C.byref(lpv), _ptr(Bp), n, _ptr(self.crow), _ptr(self.ccol),
+            _ptr(self.cval), _ptr(self.ws), self.ws.numel(), _stream()))
+        if Bp is None:
+            return None
+        return Bp.reshape(B.shape)
+
+    def result(self, Bp=None) -> "Rewrite":
+        nc = self.nc
+        return Rewrite(self.Lp, Bp, self.crow[:nc], self.ccol[:nc], self.cval[:nc], self.cptr,
+                       self.skipped)
+
+
+def rewrite(L: CSRMatrix, level: torch.Tensor, rows, targets=None,
+            B: torch.Tensor | None = None) -> Rewrite:
+    """Equation rewriting of the given rows (targets default to level - 1)."""
+    rw = Rewriter(L, level, rows, targets)
+    Bp = rw.numeric(None, B)
+    return rw.result(Bp)
+
+
+class Plan:
+    """Analysis + schedule of one matrix; solves L X = B and L^T Y = G."""
+
+    def __init__(self, L: CSRMatrix, algo: str = "auto", kmax: int = 1, block_rows: int = 0,
+                 lanes_per_row: int = 0, narrow_rows: int = -1, watchdog_ms: int = 0):
+        lib = _lib.load()
+        self.L = L
+        self._lib = lib
+        o = _lib.PlanOpts()
+        o.algo = _lib.ALGO[algo]
+        o.block_rows = block_rows
+        o.lanes_per_row = lanes_per_row
+        o.narrow_rows = narrow_rows
+        o.kmax = kmax
+        o.watchdog_ms = watchdog_ms
+        self.opts = o
+        sz = C.c_size_t(0)
+        check(lib.rwt_plan_ws(C.byref(L.view()), C.byref(o), C.byref(sz)))
+        self.ws = _workspace(sz.value, L.device)
+        h = C.c_void_p()
+        check(lib.rwt_plan_create(C.byref(L.view()), C.byref(o), _ptr(self.ws), self.ws.numel(),
+                                  C.byref(h), _stream()))
+        self._h = h
+        self.kmax = kmax
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.rwt_plan_destroy(h)
+            self._h = None
+
+    @property
+    def info(self) -> dict:
+        inf = _lib.PlanInfo()
+        check(self._lib.rwt_plan_get_info(self._h, C.byref(inf)))
+        d = {f: getattr(inf, f) for f, _ in inf._fields_ if f not in ("stats", "pad_")}
+        d["algo_fwd"] = _lib.ALGO_NAME[d["algo_fwd"]]
+        d["algo_bwd"] = _lib.ALGO_NAME[d["algo_bwd"]]
+        d["stats"] = inf.stats.as_dict()
+        return d
+
+    def levels(self) -> tuple[torch.Tensor, torch.Tensor, torch.Tensor]:
+        """(level[n], perm[n], level_ptr[D+1]) views into the plan's workspace."""
+        a, b, c = C.c_void_p(), C.c_void_p(), C.c_void_p()
+        check(self._lib.rwt_plan_levels(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        n = self.L.n
+        D = self.info["stats"]["num_levels"]
+        base = self.ws.data_ptr()
+
+        def view(ptr, count):
+            off = ptr.value - base
+            return self.ws[off:off + 4 * count].view(torch.int32)
+        return view(a, n), view(b, n), view(c, D + 1)
+
+    def _run(self, fn, B: torch.Tensor, out: torch.Tensor | None):
+        B2, k = _block(B, self.L.n, self.L.dtype)
+        X = torch.empty_like(B2) if out is None else out
+        if X.shape != B2.shape or not X.is_contiguous():
+            raise ValueError("output must match the right-hand side block")
+        check(fn(self._h, _ptr(B2), k, self.L.n, _ptr(X), self.L.n, _stream()))
+        return X.reshape(B.shape)
+
+    def solve(self, B: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        return self._run(self._lib.rwt_solve, B, out)
+
+    def solve_transpose(self, G: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        return self._run(self._lib.rwt_solve_transpose, G, out)
+
+    def check(self) -> None:
+        """Raise if a device wait expired in the last solve (synchronizes)."""
+        check(self._lib.rwt_plan_check(self._h, _stream()))
+
+
+def apply_MT(rw: Rewrite, Y: torch.Tensor) -> torch.Tensor:
+    """Y - C^T Y for the multipliers of a rewrite (grad_B of the rewritten system)."""
+    lib = _lib.load()
+    n = rw.L.n
+    Y2, k = _block(Y, n, rw.L.dtype)
+    nc = rw.crow.numel()
+    sz = C.c_size_t(0)
+    check(lib.rwt_apply_MT_ws(n, nc, C.byref(sz)))
+    ws = _workspace(sz.value, Y.device)
+    out = torch.empty_like(Y2)
+    check(lib.rwt_apply_MT(n, nc, _ptr(rw.crow), _ptr(rw.ccol), _ptr(rw.cval), _dt(rw.L.dtype),
+                           _ptr(Y2), k, n, _ptr(out), n, _ptr(ws), ws.numel(), _stream()))
+    return out.reshape(Y.shape)
+
+
+def grad_vals(L: CSRMatrix, gB: torch.Tensor, X: torch.Tensor) -> torch.Tensor:
+    """-sum_q gB[row_p, q] * X[col_p, q] on every stored entry of L."""
+    lib = _lib.load()
+    gB2, k = _block(gB, L.n, L.dtype)
+    X2, k2 = _block(X, L.n, L.dtype)
+    if k != k2:
+        raise ValueError("gB and X must have the same number of columns")
+    out = torch.empty(L.nnz, dtype=L.dtype, device=L.device)
+    check(lib.rwt_grad_vals(C.byref(L.view()), _ptr(gB2), L.n, _ptr(X2), L.n, k, _ptr(out),
+                            _stream()))
+    return out

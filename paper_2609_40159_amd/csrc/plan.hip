@@ -1,0 +1,511 @@
+// Solve plans: analysis + transposed pattern + schedules + autotuning, and
+// the solve entry points.
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "prim.hpp"
+#include "solve.hpp"
+
+namespace rwt {
+
+namespace {
+
+// keys for grouping the level-ordered rows by row block (stable)
+__global__ void k_block_keys(const int32_t* perm, int32_t n, int32_t R, uint32_t* keys,
+                             int32_t* vals) {
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t st = (int64_t)gridDim.x * blockDim.x;
+    for (; q < n; q += st) {
+        int32_t i = perm[q];
+        keys[q] = (uint32_t)(i / R);
+        vals[q] = i;
+    }
+}
+
+// a step starts at each block start and wherever the level changes
+__global__ void k_step_flags(const int32_t* bperm, const int32_t* level, int32_t n, int32_t R,
+                             int32_t* flag) {
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t st = (int64_t)gridDim.x * blockDim.x;
+    for (; q < n; q += st)
+        flag[q] = (q % R == 0 || level[bperm[q]] != level[bperm[q - 1]]) ? 1 : 0;
+}
+
+__global__ void k_step_pos(const int32_t* flag, const int32_t* pos, int32_t n, int32_t R,
+                           int32_t nblocks, int32_t* step_pos, int32_t* blk_step) {
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t st = (int64_t)gridDim.x * blockDim.x;
+    for (; q < n; q += st) {
+        if (flag[q]) step_pos[pos[q]] = (int32_t)q;
+        if (q % R == 0) blk_step[q / R] = pos[q];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        step_pos[pos[n]] = n;
+        blk_step[nblocks] = pos[n];
+    }
+}
+
+template <typename T>
+__global__ void k_fill_val(T* p, int64_t n, T v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t st = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += st) p[i] = v;
+}
+
+template <typename T>
+__global__ void k_copy_block(const T* src, int64_t lds, T* dst, int64_t ldd, int32_t n, int32_t k) {
+    int64_t total = (int64_t)n * k;
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t st = (int64_t)gridDim.x * blockDim.x;
+    for (; t < total; t += st) {
+        int64_t q = t / n, i = t - q * n;
+        dst[i + q * ldd] = src[i + q * lds];
+    }
+}
+
+int pow2_floor(int v) {
+    int p = 1;
+    while (p * 2 <= v) p *= 2;
+    return p;
+}
+
+}  // namespace
+
+rwt_status copy_block(const void* src, int64_t lds, void* dst, int64_t ldd, int32_t n, int32_t k,
+                      rwt_dtype dt, hipStream_t s) {
+    int64_t total = (int64_t)n * k;
+    if (total == 0) return RWT_OK;
+    const unsigned g = blocks_for(total, 256, 8192);
+    if (dt == RWT_F64)
+        hipLaunchKernelGGL(k_copy_block<double>, dim3(g), dim3(256), 0, s,
+                           static_cast<const double*>(src), lds, static_cast<double*>(dst), ldd, n, k);
+    else
+        hipLaunchKernelGGL(k_copy_block<float>, dim3(g), dim3(256), 0, s,
+                           static_cast<const float*>(src), lds, static_cast<float*>(dst), ldd, n, k);
+    RWT_LAUNCHED();
+    return RWT_OK;
+}
+
+}  // namespace rwt
+
+using namespace rwt;
+
+struct rwt_plan {
+    rwt_csr L;
+    rwt_plan_opts opts;
+    rwt_level_stats stats;
+    int32_t D = 0;
+    Ctrl* ctrl = nullptr;
+    int32_t* level = nullptr;
+    int32_t* perm = nullptr;
+    int32_t* level_ptr = nullptr;
+    Csc csc;
+    int32_t* seg = nullptr;
+    int32_t nseg = 0;
+    int32_t R = 0;
+    int32_t nblocks = 0;
+    int32_t* bperm = nullptr;
+    int32_t* step_pos = nullptr;
+    int32_t* blk_step = nullptr;
+    void* xtmp = nullptr;     // n * kmax values
+    void* xtmp2 = nullptr;    // n values (autotuning)
+    Algo fwd = Algo::SyncFree;
+    Algo bwd = Algo::SyncFree;
+    int32_t lanes = 4;
+    int cus = 256;
+    double tuned_level = 0, tuned_sf = 0;
+};
+
+namespace {
+
+struct PlanLayout {
+    size_t bytes;
+};
+
+int default_block_rows(const rwt_plan_opts& o, rwt_dtype dt) {
+    int kmax = o.kmax > 0 ? o.kmax : 1;
+    // LDS for the block's x values: at most 48 KB per workgroup
+    int cap = 49152 / (kmax * (int)dtype_size(dt));
+    int R = o.block_rows > 0 ? o.block_rows : 4096;
+    if (R > cap) R = cap;
+    if (R < 1) R = 1;
+    return R;
+}
+
+int default_lanes(int64_t nnz, int32_t n) {
+    double mean = n > 0 ? (double)(nnz - n) / n : 0.0;
+    int G = 1;
+    while (G < 64 && G < mean) G *= 2;
+    if (G < 2) G = 2;
+    return G;
+}
+
+// Carve the plan's device state; with base == nullptr only sizes are computed.
+struct PlanPtrs {
+    Ctrl* ctrl;
+    Ctrl* actrl;
+    int32_t *level, *perm, *level_ptr, *rows;
+    int64_t* cost;
+    rwt_level_stats* dstats;
+    Csc csc;
+    int32_t* seg;
+    int32_t *bperm, *step_pos, *blk_step;
+    void* xtmp;
+    void* xtmp2;
+    void* scratch;
+    size_t scratch_bytes;
+};
+
+size_t carve_plan(void* base, const rwt_csr& L, int R, int kmax, PlanPtrs* p) {
+    const int32_t n = L.n;
+    const int64_t noff = L.nnz - n > 0 ? L.nnz - n : 1;
+    const int32_t nblocks = (n + R - 1) / R;
+    const size_t s = dtype_size(L.dt);
+    Carver cv(base);
+    p->ctrl = cv.take<Ctrl>(1);
+    p->actrl = cv.take<Ctrl>(1);
+    p->level = cv.take<int32_t>(n);
+    p->perm = cv.take<int32_t>(n);
+    p->level_ptr = cv.take<int32_t>(n + 1);
+    p->rows = cv.take<int32_t>(n);
+    p->cost = cv.take<int64_t>(n);
+    p->dstats = cv.take<rwt_level_stats>(1);
+    p->csc.ptr = cv.take<int32_t>(n + 1);
+    p->csc.row = cv.take<int32_t>(noff);
+    p->csc.map = cv.take<int32_t>(noff);
+    p->seg = cv.take<int32_t>(3 * (size_t)n + 3);
+    p->bperm = cv.take<int32_t>(n);
+    p->step_pos = cv.take<int32_t>(n + 1);
+    p->blk_step = cv.take<int32_t>(nblocks + 1);
+    p->xtmp = cv.take<char>((size_t)n * kmax * s);
+    p->xtmp2 = cv.take<char>((size_t)n * s);
+    // scratch shared by the construction steps
+    size_t sched = 0;
+    {
+        Carver sc(nullptr);
+        sc.take<uint32_t>(n);
+        sc.take<uint32_t>(n);
+        sc.take<int32_t>(n);
+        sc.take<int32_t>(n + 1);
+        sc.take<char>(radix_ws(n));
+        sc.take<char>(scan_ws(n));
+        sched = sc.used();
+    }
+    size_t scr = std::max(std::max(csc_ws(n, L.nnz), levels_ws(n, L.nnz)), sched);
+    p->scratch = cv.take<char>(scr);
+    p->scratch_bytes = scr;
+    return cv.used();
+}
+
+rwt_status check_opts(const rwt_csr* L, const rwt_plan_opts* o) {
+    RWT_REQUIRE(L != nullptr && o != nullptr, RWT_ERR_INVALID_ARG, "null argument");
+    RWT_REQUIRE(L->n >= 0 && L->nnz >= L->n, RWT_ERR_INVALID_ARG, "bad sizes");
+    RWT_REQUIRE(L->nnz < (int64_t(1) << 31), RWT_ERR_TOO_LARGE, "nnz must be < 2^31");
+    RWT_REQUIRE(L->rowptr && L->colidx && L->vals, RWT_ERR_INVALID_ARG,
+                "a plan needs pattern and values");
+    RWT_REQUIRE(L->dt == RWT_F64 || L->dt == RWT_F32, RWT_ERR_INVALID_ARG, "bad dtype");
+    RWT_REQUIRE(o->algo >= RWT_ALGO_AUTO && o->algo <= RWT_ALGO_SYNCFREE, RWT_ERR_INVALID_ARG,
+                "bad algorithm");
+    RWT_REQUIRE(o->kmax >= 0 && o->kmax <= 4096, RWT_ERR_INVALID_ARG, "kmax out of range");
+    RWT_REQUIRE(o->lanes_per_row == 0 ||
+                    (o->lanes_per_row >= 1 && o->lanes_per_row <= 64 &&
+                     (o->lanes_per_row & (o->lanes_per_row - 1)) == 0),
+                RWT_ERR_INVALID_ARG, "lanes_per_row must be 0 or a power of two <= 64");
+    RWT_REQUIRE(o->block_rows >= 0, RWT_ERR_INVALID_ARG, "negative block_rows");
+    return RWT_OK;
+}
+
+SolveArgs make_args(const rwt_plan* p) {
+    SolveArgs a;
+    memset(&a, 0, sizeof a);
+    a.n = p->L.n;
+    a.rowptr = p->L.rowptr;
+    a.colidx = p->L.colidx;
+    a.vals = p->L.vals;
+    a.cptr = p->csc.ptr;
+    a.crow = p->csc.row;
+    a.cmap = p->csc.map;
+    a.perm = p->perm;
+    a.level_ptr = p->level_ptr;
+    a.seg = p->seg;
+    a.nseg = p->nseg;
+    a.block_rows = p->R;
+    a.nblocks = p->nblocks;
+    a.bperm = p->bperm;
+    a.step_pos = p->step_pos;
+    a.blk_step = p->blk_step;
+    a.lanes = p->lanes;
+    a.ctrl = p->ctrl;
+    a.ticks = watchdog_ticks(p->opts.watchdog_ms);
+    return a;
+}
+
+rwt_status run_solve(const rwt_plan* p, bool transposed, Algo algo, const void* B, int32_t k,
+                     int64_t ldb, void* X, int64_t ldx, hipStream_t s) {
+    SolveArgs a = make_args(p);
+    a.k = k;
+    a.X = X;
+    a.ldx = ldx;
+    if (B == X) {
+        RWT_TRY(copy_block(B, ldb, p->xtmp, p->L.n, p->L.n, k, p->L.dt, s));
+        a.B = p->xtmp;
+        a.ldb = p->L.n;
+    } else {
+        a.B = B;
+        a.ldb = ldb;
+    }
+    RWT_TRY(solve_prepare(a, p->L.dt, s));
+    size_t lds = algo == Algo::SyncFree ? (size_t)syncfree_lds_bytes(p->R, k, p->L.dt) : 0;
+    unsigned grid = solve_grid(algo, p->L.dt, transposed, k, lds, p->cus);
+    return solve_launch(a, p->L.dt, algo, transposed, grid, s);
+}
+
+double time_solve(rwt_plan* p, Algo algo, hipStream_t s, int reps) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return 1e30;
+    if (hipEventCreate(&e1) != hipSuccess) { hipEventDestroy(e0); return 1e30; }
+    double best = 1e30;
+    for (int r = 0; r < reps; ++r) {
+        hipEventRecord(e0, s);
+        rwt_status st = run_solve(p, false, algo, p->xtmp, 1, p->L.n, p->xtmp2, p->L.n, s);
+        hipEventRecord(e1, s);
+        if (st != RWT_OK || hipEventSynchronize(e1) != hipSuccess) { best = 1e30; break; }
+        float ms = 0;
+        hipEventElapsedTime(&ms, e0, e1);
+        Ctrl hc;
+        if (hipMemcpy(&hc, p->ctrl, sizeof hc, hipMemcpyDeviceToHost) != hipSuccess || hc.err != 0) {
+            best = 1e30;
+            break;
+        }
+        if (r > 0 && ms < best) best = ms;   // the first run warms up
+        if (reps == 1) best = ms;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return best;
+}
+
+}  // namespace
+
+extern "C" rwt_status rwt_plan_ws(const rwt_csr* L, const rwt_plan_opts* opts, size_t* h_bytes) {
+    RWT_TRY(check_opts(L, opts));
+    RWT_REQUIRE(h_bytes != nullptr, RWT_ERR_INVALID_ARG, "h_bytes is NULL");
+    PlanPtrs pp;
+    int kmax = opts->kmax > 0 ? opts->kmax : 1;
+    *h_bytes = carve_plan(nullptr, *L, default_block_rows(*opts, L->dt), kmax, &pp);
+    return RWT_OK;
+}
+
+extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opts, void* d_ws,
+                                      size_t ws_bytes, rwt_plan** out, rwt_stream_t stream) {
+    RWT_TRY(check_opts(L, opts));
+    RWT_REQUIRE(out != nullptr, RWT_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    const int kmax = opts->kmax > 0 ? opts->kmax : 1;
+    const int R = default_block_rows(*opts, L->dt);
+    PlanPtrs pp;
+    const size_t need = carve_plan(nullptr, *L, R, kmax, &pp);
+    RWT_REQUIRE(d_ws != nullptr && ws_bytes >= need, RWT_ERR_BUFFER_TOO_SMALL,
+                "plan workspace must hold %zu bytes", need);
+    carve_plan(d_ws, *L, R, kmax, &pp);
+    hipStream_t s = hs(stream);
+    rwt_plan* p = new (std::nothrow) rwt_plan();
+    RWT_REQUIRE(p != nullptr, RWT_ERR_INVALID_ARG, "out of host memory");
+    p->L = *L;
+    p->opts = *opts;
+    p->opts.kmax = kmax;
+    p->R = R;
+    p->nblocks = (L->n + R - 1) / R;
+    p->ctrl = pp.ctrl;
+    p->level = pp.level;
+    p->perm = pp.perm;
+    p->level_ptr = pp.level_ptr;
+    p->csc = pp.csc;
+    p->seg = pp.seg;
+    p->bperm = pp.bperm;
+    p->step_pos = pp.step_pos;
+    p->blk_step = pp.blk_step;
+    p->xtmp = pp.xtmp;
+    p->xtmp2 = pp.xtmp2;
+    p->lanes = opts->lanes_per_row > 0 ? opts->lanes_per_row : default_lanes(L->nnz, L->n);
+    DeviceInfo di;
+    rwt_status st = device_info(&di);
+    if (st != RWT_OK) { delete p; return st; }
+    p->cus = di.cus;
+    memset(&p->stats, 0, sizeof p->stats);
+    const int32_t n = L->n;
+    auto fail = [&](rwt_status e) {
+        delete p;
+        return e;
+    };
+    if (n == 0) {
+        *out = p;
+        return RWT_OK;
+    }
+    // the pattern and diagonal are checked before any kernel indexes with them
+    if ((st = validate_device(*L, true, pp.actrl, nullptr, s)) != RWT_OK) return fail(st);
+    // analysis
+    if ((st = build_csc(*L, p->csc, pp.scratch, s)) != RWT_OK) return fail(st);
+    LevelOut lo{pp.level, pp.perm, pp.level_ptr, pp.rows, pp.cost, pp.dstats};
+    if ((st = compute_levels(*L, p->csc, lo, pp.actrl, pp.scratch, s, opts->watchdog_ms)) != RWT_OK)
+        return fail(st);
+    Ctrl hc;
+    if (hipMemcpyAsync(&hc, pp.actrl, sizeof hc, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&p->stats, pp.dstats, sizeof p->stats, hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        set_hip_error(hipGetLastError(), "plan analysis readback");
+        return fail(RWT_ERR_HIP);
+    }
+    if (hc.err != 0) {
+        set_error("levelization watchdog expired");
+        return fail(RWT_ERR_DEADLOCK);
+    }
+    if (hc.l1 != n) {
+        set_error("only %lld of %d rows reached: pattern not lower triangular", (long long)hc.l1, n);
+        return fail(RWT_ERR_NOT_LOWER);
+    }
+    p->D = p->stats.num_levels;
+    // level segments: runs of narrow levels go to one workgroup
+    std::vector<int32_t> rows(p->D);
+    if (hipMemcpy(rows.data(), pp.rows, sizeof(int32_t) * p->D, hipMemcpyDeviceToHost) != hipSuccess) {
+        set_hip_error(hipGetLastError(), "level sizes readback");
+        return fail(RWT_ERR_HIP);
+    }
+    // default: a level that one workgroup finishes in up to 4 rounds
+    const int narrow = opts->narrow_rows >= 0 ? opts->narrow_rows : 4 * (256 / p->lanes);
+    p->opts.narrow_rows = narrow;
+    std::vector<int32_t> seg;
+    for (int32_t l = 0; l < p->D;) {
+        if (rows[l] <= narrow) {
+            int32_t e = l;
+            while (e < p->D && rows[e] <= narrow) ++e;
+            seg.insert(seg.end(), {l, e, 1});
+            l = e;
+        } else {
+            seg.insert(seg.end(), {l, l + 1, 0});
+            ++l;
+        }
+    }
+    p->nseg = (int32_t)(seg.size() / 3);
+    if (hipMemcpyAsync(p->seg, seg.data(), sizeof(int32_t) * seg.size(), hipMemcpyHostToDevice, s) !=
+        hipSuccess) {
+        set_hip_error(hipGetLastError(), "segment upload");
+        return fail(RWT_ERR_HIP);
+    }
+    // sync-free blocks: rows grouped by block, each block in (level, row) order
+    {
+        Carver sc(pp.scratch);
+        uint32_t* keys = sc.take<uint32_t>(n);
+        uint32_t* tkeys = sc.take<uint32_t>(n);
+        int32_t* tvals = sc.take<int32_t>(n);
+        int32_t* pos = sc.take<int32_t>(n + 1);
+        void* rws = sc.take<char>(radix_ws(n));
+        void* sws = sc.take<char>(scan_ws(n));
+        const unsigned g = blocks_for(n, 256, 8192);
+        hipLaunchKernelGGL(k_block_keys, dim3(g), dim3(256), 0, s, p->perm, n, R, keys, p->bperm);
+        if (hipGetLastError() != hipSuccess) return fail(RWT_ERR_HIP);
+        if ((st = radix_sort(keys, p->bperm, tkeys, tvals, n, bits_for((uint64_t)(p->nblocks - 1)),
+                             rws, s)) != RWT_OK)
+            return fail(st);
+        int32_t* flag = reinterpret_cast<int32_t*>(keys);   // keys no longer needed
+        hipLaunchKernelGGL(k_step_flags, dim3(g), dim3(256), 0, s, p->bperm, p->level, n, R, flag);
+        if ((st = scan_exclusive(flag, pos, n, sws, s)) != RWT_OK) return fail(st);
+        hipLaunchKernelGGL(k_step_pos, dim3(g), dim3(256), 0, s, flag, pos, n, R, p->nblocks,
+                           p->step_pos, p->blk_step);
+        if (hipGetLastError() != hipSuccess) return fail(RWT_ERR_HIP);
+    }
+    // algorithm choice
+    p->fwd = p->bwd = opts->algo == RWT_ALGO_LEVEL ? Algo::Level : Algo::SyncFree;
+    if (opts->algo == RWT_ALGO_AUTO) {
+        const unsigned g = blocks_for(n, 256, 8192);
+        if (L->dt == RWT_F64)
+            hipLaunchKernelGGL(k_fill_val<double>, dim3(g), dim3(256), 0, s,
+                               static_cast<double*>(p->xtmp), (int64_t)n, 1.0);
+        else
+            hipLaunchKernelGGL(k_fill_val<float>, dim3(g), dim3(256), 0, s,
+                               static_cast<float*>(p->xtmp), (int64_t)n, 1.0f);
+        p->tuned_level = time_solve(p, Algo::Level, s, 3);
+        p->tuned_sf = time_solve(p, Algo::SyncFree, s, 3);
+        if (p->tuned_level >= 1e30 && p->tuned_sf >= 1e30) {
+            set_error("autotuning solves failed");
+            return fail(RWT_ERR_DEADLOCK);
+        }
+        p->fwd = p->bwd = p->tuned_level < p->tuned_sf ? Algo::Level : Algo::SyncFree;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) {
+        set_hip_error(hipGetLastError(), "plan creation");
+        return fail(RWT_ERR_HIP);
+    }
+    *out = p;
+    return RWT_OK;
+}
+
+extern "C" rwt_status rwt_plan_get_info(const rwt_plan* p, rwt_plan_info* h) {
+    RWT_REQUIRE(p != nullptr && h != nullptr, RWT_ERR_INVALID_ARG, "null argument");
+    memset(h, 0, sizeof *h);
+    h->stats = p->stats;
+    h->algo_fwd = p->fwd == Algo::Level ? RWT_ALGO_LEVEL : RWT_ALGO_SYNCFREE;
+    h->algo_bwd = p->bwd == Algo::Level ? RWT_ALGO_LEVEL : RWT_ALGO_SYNCFREE;
+    h->block_rows = p->R;
+    h->lanes_per_row = p->lanes;
+    h->narrow_rows = p->opts.narrow_rows;
+    h->num_blocks = p->nblocks;
+    h->grid = (int32_t)solve_grid(p->fwd, p->L.dt, false, 1,
+                                  p->fwd == Algo::SyncFree ? syncfree_lds_bytes(p->R, 1, p->L.dt) : 0,
+                                  p->cus);
+    h->tuned_ms_level = p->tuned_level;
+    h->tuned_ms_syncfree = p->tuned_sf;
+    return RWT_OK;
+}
+
+extern "C" rwt_status rwt_plan_levels(const rwt_plan* p, const int32_t** d_level,
+                                      const int32_t** d_perm, const int32_t** d_level_ptr) {
+    RWT_REQUIRE(p != nullptr, RWT_ERR_INVALID_ARG, "null plan");
+    if (d_level) *d_level = p->level;
+    if (d_perm) *d_perm = p->perm;
+    if (d_level_ptr) *d_level_ptr = p->level_ptr;
+    return RWT_OK;
+}
+
+extern "C" rwt_status rwt_plan_destroy(rwt_plan* p) {
+    delete p;
+    return RWT_OK;
+}
+
+static rwt_status solve_common(const rwt_plan* p, bool transposed, const void* B, int32_t k,
+                               int64_t ldb, void* X, int64_t ldx, rwt_stream_t stream) {
+    RWT_REQUIRE(p != nullptr, RWT_ERR_INVALID_ARG, "null plan");
+    RWT_REQUIRE(k >= 0 && k <= p->opts.kmax, RWT_ERR_INVALID_ARG, "k=%d outside [0, kmax=%d]", k,
+                p->opts.kmax);
+    RWT_REQUIRE(B != nullptr && X != nullptr, RWT_ERR_INVALID_ARG, "null right-hand side");
+    RWT_REQUIRE(ldb >= p->L.n && ldx >= p->L.n, RWT_ERR_INVALID_ARG, "leading dimension < n");
+    if (k == 0 || p->L.n == 0) return RWT_OK;
+    Algo algo = transposed ? p->bwd : p->fwd;
+    return run_solve(p, transposed, algo, B, k, ldb, X, ldx, hs(stream));
+}
+
+extern "C" rwt_status rwt_solve(const rwt_plan* p, const void* d_B, int32_t k, int64_t ldb,
+                                void* d_X, int64_t ldx, rwt_stream_t stream) {
+    return solve_common(p, false, d_B, k, ldb, d_X, ldx, stream);
+}
+
+extern "C" rwt_status rwt_solve_transpose(const rwt_plan* p, const void* d_G, int32_t k,
+                                          int64_t ldg, void* d_Y, int64_t ldy,
+                                          rwt_stream_t stream) {
+    return solve_common(p, true, d_G, k, ldg, d_Y, ldy, stream);
+}
+
+extern "C" rwt_status rwt_plan_check(const rwt_plan* p, rwt_stream_t stream) {
+    RWT_REQUIRE(p != nullptr, RWT_ERR_INVALID_ARG, "null plan");
+    if (p->L.n == 0) return RWT_OK;
+    Ctrl hc;
+    RWT_HIP(hipMemcpyAsync(&hc, p->ctrl, sizeof hc, hipMemcpyDeviceToHost, hs(stream)));
+    RWT_HIP(hipStreamSynchronize(hs(stream)));
+    if (hc.err != 0) {
+        set_error("a device wait expired in the last solve (watchdog)");
+        return RWT_ERR_DEADLOCK;
+    }
+    return RWT_OK;
+}

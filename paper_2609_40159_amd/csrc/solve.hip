@@ -1,0 +1,299 @@
+// Forward substitution L X = B and its transpose L^T Y = G (paper Section
+// 2.1: x_i = (b_i - sum_j L_ij x_j) / L_ii once every dependency j is done;
+// the transposed system runs the same recurrence over successors, levels in
+// reverse order).
+//
+// Readiness travels with the data: before a solve X is filled with a
+// signalling-NaN sentinel, a row's result is published with one
+// device-scope store, and a reader of another workgroup's row spins
+// (bounded) until the sentinel is gone.  No device-scope fences are used.
+//
+// Two schedules:
+//   level-scheduled  (k_solve_level): one level after another.  Wide levels
+//       spread over the whole grid with a pacing barrier after each;
+//       consecutive narrow levels are one segment handled by workgroup 0
+//       alone with workgroup barriers (Section 2.1; the level-set method of
+//       Section 7).
+//   sync-free        (k_solve_sf): blocks of consecutive rows are claimed
+//       in row order from a ticket counter (deadlock-free: a block waits
+//       only on rows of earlier tickets).  Inside a block the rows go level
+//       by level with workgroup barriers and the block's x values live in
+//       LDS; dependencies outside the block are read from HBM with the
+//       sentinel wait (Section 7, synchronization-free methods).
+// A row is processed by a group of G lanes (rows-per-wavefront = 64/G):
+// strided partial dot products, then a butterfly reduction in the group.
+#include "solve.hpp"
+
+#include "prim.hpp"
+
+namespace rwt {
+
+namespace {
+
+constexpr int SV_THREADS = 256;
+
+template <typename T, bool TRANS, int KT, bool LOCAL>
+__device__ __forceinline__ void solve_row(const SolveArgs& a, bool active, int32_t i, int gl, int G,
+                                          T* xs, int32_t r0, int32_t r1) {
+    const T* vals = static_cast<const T*>(a.vals);
+    const T* B = static_cast<const T*>(a.B);
+    T* X = static_cast<T*>(a.X);
+    int32_t pb = 0, pe = 0;
+    T diag = T(1);
+    if (active) {
+        if (!TRANS) {
+            pb = a.rowptr[i];
+            pe = a.rowptr[i + 1] - 1;
+            diag = vals[pe];
+        } else {
+            pb = a.cptr[i];
+            pe = a.cptr[i + 1];
+            diag = vals[a.rowptr[i + 1] - 1];
+        }
+    }
+    int32_t* err = &a.ctrl->err;
+    for (int q0 = 0; q0 < a.k; q0 += KT) {
+        T acc[KT];
+#pragma unroll
+        for (int t = 0; t < KT; ++t) acc[t] = T(0);
+        for (int32_t p = pb + gl; p < pe; p += G) {
+            int32_t j;
+            T v;
+            if (!TRANS) {
+                j = a.colidx[p];
+                v = vals[p];
+            } else {
+                j = a.crow[p];
+                v = vals[a.cmap[p]];
+            }
+            const bool local = LOCAL && (TRANS ? (j < r1) : (j >= r0));
+#pragma unroll
+            for (int t = 0; t < KT; ++t) {
+                const int q = q0 + t;
+                if (KT == 1 || q < a.k) {
+                    T xj = local ? xs[(int64_t)(j - r0) * a.k + q]
+                                 : wait_value(&X[j + (int64_t)q * a.ldx], err, a.ticks);
+                    acc[t] += v * xj;
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < KT; ++t) acc[t] = group_sum(acc[t], G);
+        if (active && gl == 0) {
+#pragma unroll
+            for (int t = 0; t < KT; ++t) {
+                const int q = q0 + t;
+                if (KT == 1 || q < a.k) {
+                    T xi = (B[i + (int64_t)q * a.ldb] - acc[t]) / diag;
+                    if (LOCAL) xs[(int64_t)(i - r0) * a.k + q] = xi;
+                    st_relaxed(&X[i + (int64_t)q * a.ldx], xi);
+                }
+            }
+        }
+    }
+}
+
+template <typename T>
+__global__ void k_prefill(T* X, int64_t ldx, int32_t n, int32_t k) {
+    const T s = sentinel_value<T>();
+    int64_t total = (int64_t)n * k;
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t st = (int64_t)gridDim.x * blockDim.x;
+    for (; t < total; t += st) {
+        int64_t q = t / n, i = t - q * n;
+        X[i + q * ldx] = s;
+    }
+}
+
+// wave-uniform pacing barrier (see analyze.hip): data is never ordered by it
+__device__ bool solve_barrier(Ctrl* c, uint32_t& gen, int64_t ticks) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    __shared__ int s_ok;
+    if (threadIdx.x == 0) {
+        const uint32_t nb = gridDim.x;
+        uint32_t prev = fetch_add(&c->bar_count, 1u);
+        int ok = 1;
+        if (prev == nb * (gen + 1) - 1) {
+            __hip_atomic_exchange(&c->bar_gen, gen + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            int64_t t0 = wall_clock64();
+            uint32_t hb = ld_relaxed(&c->heartbeat);
+            while (ld_relaxed(&c->bar_gen) <= gen) {
+                __builtin_amdgcn_s_sleep(1);
+                if (ld_relaxed(&c->err) != 0) { ok = 0; break; }
+                int64_t now = wall_clock64();
+                uint32_t h2 = ld_relaxed(&c->heartbeat);
+                if (h2 != hb) { hb = h2; t0 = now; }
+                if (now - t0 > ticks) {
+                    __hip_atomic_store(&c->err, (int32_t)RWT_ERR_DEADLOCK, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+            }
+        }
+        s_ok = ok;
+    }
+    __syncthreads();
+    gen += 1;
+    return s_ok != 0;
+}
+
+template <typename T, bool TRANS, int KT>
+__global__ void __launch_bounds__(SV_THREADS) k_solve_level(SolveArgs a) {
+    const int G = a.lanes;
+    const int gl = threadIdx.x & (G - 1);
+    const int lane = lane_id();
+    const int groups_per_wave = WAVE / G;
+    const int wave_in_block = threadIdx.x / WAVE;
+    const int waves_per_block = blockDim.x / WAVE;
+    uint32_t gen = 0;
+    for (int32_t si = 0; si < a.nseg; ++si) {
+        const int32_t sidx = TRANS ? a.nseg - 1 - si : si;
+        const int32_t lb = a.seg[3 * sidx], le = a.seg[3 * sidx + 1];
+        const bool narrow = a.seg[3 * sidx + 2] != 0;
+        if (narrow) {
+            if (blockIdx.x == 0) {
+                for (int32_t t = 0; t < le - lb; ++t) {
+                    const int32_t l = TRANS ? le - 1 - t : lb + t;
+                    const int32_t beg = a.level_ptr[l], end = a.level_ptr[l + 1];
+                    const int32_t stride = waves_per_block * groups_per_wave;
+                    for (int32_t base = beg + wave_in_block * groups_per_wave; base < end;
+                         base += stride) {
+                        const int32_t q = base + lane / G;
+                        const bool act = q < end;
+                        solve_row<T, TRANS, KT, false>(a, act, act ? a.perm[q] : 0, gl, G, nullptr,
+                                                       0, 0);
+                    }
+                    __builtin_amdgcn_s_waitcnt(0);
+                    __syncthreads();
+                    if (threadIdx.x == 0)
+                        __hip_atomic_fetch_add(&a.ctrl->heartbeat, 1u, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+        } else {
+            const int32_t beg = a.level_ptr[lb], end = a.level_ptr[lb + 1];
+            const int32_t gwave = blockIdx.x * waves_per_block + wave_in_block;
+            const int32_t stride = gridDim.x * waves_per_block * groups_per_wave;
+            for (int32_t base = beg + gwave * groups_per_wave; base < end; base += stride) {
+                const int32_t q = base + lane / G;
+                const bool act = q < end;
+                solve_row<T, TRANS, KT, false>(a, act, act ? a.perm[q] : 0, gl, G, nullptr, 0, 0);
+            }
+        }
+        if (!solve_barrier(a.ctrl, gen, a.ticks)) return;
+    }
+}
+
+template <typename T, bool TRANS, int KT>
+__global__ void __launch_bounds__(SV_THREADS) k_solve_sf(SolveArgs a) {
+    extern __shared__ unsigned char s_raw[];
+    T* xs = reinterpret_cast<T*>(s_raw);
+    __shared__ int32_t s_blk;
+    const int G = a.lanes;
+    const int gl = threadIdx.x & (G - 1);
+    const int lane = lane_id();
+    const int groups_per_wave = WAVE / G;
+    const int wave_in_block = threadIdx.x / WAVE;
+    const int waves_per_block = blockDim.x / WAVE;
+    const int32_t stride = waves_per_block * groups_per_wave;
+    for (;;) {
+        if (threadIdx.x == 0) s_blk = (int32_t)fetch_add(&a.ctrl->ticket, 1u);
+        __syncthreads();
+        const int32_t t = s_blk;
+        __syncthreads();
+        if (t >= a.nblocks) break;
+        const int32_t blk = TRANS ? a.nblocks - 1 - t : t;
+        const int32_t r0 = blk * a.block_rows;
+        const int32_t r1 = min(a.n, r0 + a.block_rows);
+        const int32_t sb = a.blk_step[blk], se = a.blk_step[blk + 1];
+        for (int32_t u = 0; u < se - sb; ++u) {
+            const int32_t st = TRANS ? se - 1 - u : sb + u;
+            const int32_t beg = a.step_pos[st], end = a.step_pos[st + 1];
+            for (int32_t base = beg + wave_in_block * groups_per_wave; base < end; base += stride) {
+                const int32_t q = base + lane / G;
+                const bool act = q < end;
+                solve_row<T, TRANS, KT, true>(a, act, act ? a.bperm[q] : 0, gl, G, xs, r0, r1);
+            }
+            __syncthreads();
+        }
+        if (ld_relaxed(&a.ctrl->err) != 0) break;
+    }
+}
+
+template <typename T, bool TRANS>
+rwt_status launch_typed(const SolveArgs& a, Algo algo, unsigned grid, hipStream_t s) {
+    const bool multi = a.k > 1;
+    if (algo == Algo::Level) {
+        if (multi)
+            hipLaunchKernelGGL((k_solve_level<T, TRANS, 4>), dim3(grid), dim3(SV_THREADS), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_solve_level<T, TRANS, 1>), dim3(grid), dim3(SV_THREADS), 0, s, a);
+    } else {
+        const size_t lds = (size_t)a.block_rows * a.k * sizeof(T);
+        if (multi)
+            hipLaunchKernelGGL((k_solve_sf<T, TRANS, 4>), dim3(grid), dim3(SV_THREADS), lds, s, a);
+        else
+            hipLaunchKernelGGL((k_solve_sf<T, TRANS, 1>), dim3(grid), dim3(SV_THREADS), lds, s, a);
+    }
+    RWT_LAUNCHED();
+    return RWT_OK;
+}
+
+}  // namespace
+
+unsigned solve_grid(Algo algo, rwt_dtype dt, bool transposed, int k, size_t lds, int cus) {
+    const void* f = nullptr;
+    const bool multi = k > 1;
+#define RWT_PICK(T, TR)                                                                     \
+    if (algo == Algo::Level)                                                                \
+        f = multi ? (const void*)k_solve_level<T, TR, 4> : (const void*)k_solve_level<T, TR, 1>; \
+    else                                                                                    \
+        f = multi ? (const void*)k_solve_sf<T, TR, 4> : (const void*)k_solve_sf<T, TR, 1>;
+    if (dt == RWT_F64) {
+        if (transposed) { RWT_PICK(double, true) } else { RWT_PICK(double, false) }
+    } else {
+        if (transposed) { RWT_PICK(float, true) } else { RWT_PICK(float, false) }
+    }
+#undef RWT_PICK
+    if (algo == Algo::Level) return (unsigned)cus;   // one workgroup per compute unit
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, SV_THREADS, lds) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    if (per_cu > 8) per_cu = 8;
+    return (unsigned)(cus * per_cu);
+}
+
+int syncfree_lds_bytes(int block_rows, int k, rwt_dtype dt) {
+    return block_rows * k * (int)dtype_size(dt);
+}
+
+rwt_status solve_prepare(const SolveArgs& a, rwt_dtype dt, hipStream_t s) {
+    RWT_TRY(fill_u8(a.ctrl, sizeof(Ctrl), s));
+    const int64_t total = (int64_t)a.n * a.k;
+    if (total == 0) return RWT_OK;
+    const unsigned g = blocks_for(total, 256, 8192);
+    if (dt == RWT_F64)
+        hipLaunchKernelGGL(k_prefill<double>, dim3(g), dim3(256), 0, s, static_cast<double*>(a.X),
+                           a.ldx, a.n, a.k);
+    else
+        hipLaunchKernelGGL(k_prefill<float>, dim3(g), dim3(256), 0, s, static_cast<float*>(a.X),
+                           a.ldx, a.n, a.k);
+    RWT_LAUNCHED();
+    return RWT_OK;
+}
+
+rwt_status solve_launch(const SolveArgs& a, rwt_dtype dt, Algo algo, bool transposed, unsigned grid,
+                        hipStream_t s) {
+    if (a.n == 0 || a.k == 0) return RWT_OK;
+    if (dt == RWT_F64)
+        return transposed ? launch_typed<double, true>(a, algo, grid, s)
+                          : launch_typed<double, false>(a, algo, grid, s);
+    return transposed ? launch_typed<float, true>(a, algo, grid, s)
+                      : launch_typed<float, false>(a, algo, grid, s);
+}
+
+}  // namespace rwt

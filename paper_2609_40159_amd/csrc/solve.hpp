@@ -1,0 +1,49 @@
+// Triangular solve kernels and their launch parameters.
+#pragma once
+
+#include "analyze.hpp"
+
+namespace rwt {
+
+// Everything a solve kernel needs, forward (L) or transposed (L^T).
+struct SolveArgs {
+    int32_t n;
+    const int32_t* rowptr;     // L
+    const int32_t* colidx;
+    const void* vals;
+    const int32_t* cptr;       // successors (transposed solve)
+    const int32_t* crow;
+    const int32_t* cmap;
+    const int32_t* perm;       // level order
+    const int32_t* level_ptr;
+    // level-scheduled: segments of levels (begin, end, narrow flag)
+    const int32_t* seg;
+    int32_t nseg;
+    // sync-free: row blocks
+    int32_t block_rows;
+    int32_t nblocks;
+    const int32_t* bperm;      // rows grouped by block, each block in (level, row) order
+    const int32_t* step_pos;   // start of each step (one level of one block) in bperm
+    const int32_t* blk_step;   // first step of each block
+    // right-hand sides
+    const void* B;
+    int64_t ldb;
+    void* X;
+    int64_t ldx;
+    int32_t k;
+    int32_t lanes;             // lanes per row (power of two, 1..64)
+    Ctrl* ctrl;
+    int64_t ticks;
+};
+
+enum class Algo { Level, SyncFree };
+
+// Fill X with the not-ready sentinel and reset the control block.
+rwt_status solve_prepare(const SolveArgs& a, rwt_dtype dt, hipStream_t s);
+rwt_status solve_launch(const SolveArgs& a, rwt_dtype dt, Algo algo, bool transposed,
+                        unsigned grid, hipStream_t s);
+int syncfree_lds_bytes(int block_rows, int k, rwt_dtype dt);
+// workgroups of a persistent solve launch (all resident)
+unsigned solve_grid(Algo algo, rwt_dtype dt, bool transposed, int k, size_t lds, int cus);
+
+}  // namespace rwt

@@ -1,0 +1,101 @@
+"""CPU-side checks of the C-ABI boundary: the library loads and exports every
+symbol the header declares, with matching Python declarations.  No GPU call."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rwtrsv.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rwt_[a-z_A-Z0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2609_40159_amd import _lib, build
+    if not os.path.exists(_lib.LIB_PATH):
+        build.build()
+    return _lib.load()
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for name in ["rwt_validate", "rwt_analyze", "rwt_rewrite_symbolic", "rwt_rewrite_numeric",
+                 "rwt_plan_create", "rwt_solve", "rwt_solve_transpose", "rwt_apply_MT",
+                 "rwt_grad_vals"]:
+        assert name in syms
+
+
+def test_library_exports_every_declared_symbol(lib):
+    import subprocess
+    from paper_2609_40159_amd import _lib
+    out = subprocess.check_output(["nm", "-D", "--defined-only", _lib.LIB_PATH]).decode()
+    exported = set(re.findall(r"\bT (rwt_\w+)", out))
+    missing = [s for s in declared_symbols() if s not in exported]
+    assert not missing, missing
+    for s in declared_symbols():
+        assert hasattr(lib, s)
+
+
+def test_python_declarations_cover_header():
+    from paper_2609_40159_amd import _lib
+    assert sorted(_lib.SIGNATURES) == declared_symbols()
+
+
+def test_host_only_calls(lib):
+    import ctypes as C
+    from paper_2609_40159_amd import _lib
+    assert lib.rwt_version().startswith(b"rwtrsv")
+    assert lib.rwt_validate_ws() >= 16
+    # argument errors are reported without touching the device
+    sz = C.c_size_t(0)
+    assert lib.rwt_analyze_ws(None, C.byref(sz)) == -1
+    assert b"NULL" in lib.rwt_last_error_string()
+    assert lib.rwt_apply_MT_ws(-1, 0, C.byref(sz)) == -1
+    c = _lib.Csr()
+    c.n, c.nnz, c.dt = 10, 5, 0
+    c.rowptr = 1
+    c.colidx = 1
+    assert lib.rwt_analyze_ws(C.byref(c), C.byref(sz)) == -4     # nnz < n: diagonal missing
+    c.nnz = 1 << 31
+    assert lib.rwt_analyze_ws(C.byref(c), C.byref(sz)) == -8
+    c.nnz = 30
+    assert lib.rwt_analyze_ws(C.byref(c), C.byref(sz)) == 0 and sz.value > 0
+    o = _lib.PlanOpts()
+    o.algo, o.kmax, o.lanes_per_row = 0, 1, 3
+    c.vals = 1
+    assert lib.rwt_plan_ws(C.byref(c), C.byref(o), C.byref(sz)) == -1   # lanes not a power of 2
+    o.lanes_per_row = 0
+    assert lib.rwt_plan_ws(C.byref(c), C.byref(o), C.byref(sz)) == 0
+
+
+def test_package_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_2609_40159_amd import _lib
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError, match="no fallback"):
+        _lib.load()
+
+
+def test_oracle_and_gpu_path_are_independent():
+    """Neither side imports the other; the shared input module imports neither."""
+    import synth
+    ssrc = open(synth.__file__).read()
+    assert "oracle" not in ssrc.split('"""', 2)[2] and "paper_2609_40159_amd" not in ssrc
+    odir = os.path.join(ROOT, "oracle")
+    for f in os.listdir(odir):
+        if f.endswith((".py", ".c", ".h")):
+            assert "paper_2609_40159_amd" not in open(os.path.join(odir, f)).read(), f
+            assert "rwtrsv" not in open(os.path.join(odir, f)).read(), f
+    pdir = os.path.join(ROOT, "paper_2609_40159_amd")
+    for dirpath, _, files in os.walk(pdir):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f
+                assert "oracle.c" not in txt and "orc_" not in txt, f
