@@ -35,22 +35,6 @@ __global__ void k_ct_keys(const int32_t* ccol, int64_t nc, uint32_t* keys, int32
     }
 }
 
-__global__ void k_ct_ptr(const uint32_t* keys, int64_t nc, int32_t n, int32_t* ptr) {
-    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t st = (int64_t)gridDim.x * blockDim.x;
-    if (nc == 0) {
-        for (int64_t c = q; c <= n; c += st) ptr[c] = 0;
-        return;
-    }
-    for (; q < nc; q += st) {
-        int64_t c = keys[q];
-        int64_t prev = q == 0 ? -1 : (int64_t)keys[q - 1];
-        for (int64_t cc = prev + 1; cc <= c; ++cc) ptr[cc] = (int32_t)q;
-        if (q == nc - 1)
-            for (int64_t cc = c + 1; cc <= n; ++cc) ptr[cc] = (int32_t)nc;
-    }
-}
-
 // out[j,q] = Y[j,q] - sum over substitutions e of column j (ascending e)
 //            of cval[e] * Y[crow[e], q]
 template <typename T>
@@ -158,9 +142,7 @@ extern "C" rwt_status rwt_apply_MT(int32_t n, int64_t nC, const int32_t* d_crow,
         RWT_LAUNCHED();
         RWT_TRY(radix_sort(w.keys, w.vals, w.tkeys, w.tvals, nC, bits_for((uint64_t)n), w.rws, s));
     }
-    hipLaunchKernelGGL(k_ct_ptr, dim3(blocks_for(nC > 0 ? nC : n + 1, 256, 4096)), dim3(256), 0, s,
-                       w.keys, nC, n, w.ptr);
-    RWT_LAUNCHED();
+    RWT_TRY(segment_starts(w.keys, nC, n, w.ptr, nullptr, s));
     const unsigned g = blocks_for((size_t)n * k, 256, 8192);
     if (dt == RWT_F64)
         hipLaunchKernelGGL(k_apply_mt<double>, dim3(g), dim3(256), 0, s, w.ptr, w.vals, d_crow,

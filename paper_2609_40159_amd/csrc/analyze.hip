@@ -214,23 +214,11 @@ __global__ void k_csc_keys(const int32_t* rowptr, const int32_t* colidx, const i
     }
 }
 
-// Column pointers from the sorted keys; also the row of each successor.
-__global__ void k_csc_finish(const uint32_t* keys, const int32_t* pos, const int32_t* rowidx,
-                             int64_t noff, int32_t n, int32_t* cptr, int32_t* crow) {
+// the row of each successor (its CSR position came out of the sort)
+__global__ void k_csc_rows(const int32_t* pos, const int32_t* rowidx, int64_t noff, int32_t* crow) {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t st = (int64_t)gridDim.x * blockDim.x;
-    if (noff == 0) {
-        for (int64_t c = q; c <= n; c += st) cptr[c] = 0;
-        return;
-    }
-    for (; q < noff; q += st) {
-        int64_t c = keys[q];
-        int64_t prev = q == 0 ? -1 : (int64_t)keys[q - 1];
-        for (int64_t cc = prev + 1; cc <= c; ++cc) cptr[cc] = (int32_t)q;
-        if (q == noff - 1)
-            for (int64_t cc = c + 1; cc <= n; ++cc) cptr[cc] = (int32_t)noff;
-        crow[q] = rowidx[pos[q]];
-    }
+    for (; q < noff; q += st) crow[q] = rowidx[pos[q]];
 }
 
 size_t csc_ws(int32_t n, int64_t nnz) {
@@ -262,9 +250,12 @@ rwt_status build_csc(const rwt_csr& L, const Csc& out, void* ws, hipStream_t s) 
         RWT_TRY(radix_sort(keys, pos, tkeys, tpos, nnz, bits_for((uint64_t)n), rws, s));
     }
     const int64_t noff = nnz - n;
-    hipLaunchKernelGGL(k_csc_finish, dim3(blocks_for(noff > 0 ? noff : n + 1, 256, 8192)), dim3(256),
-                       0, s, keys, pos, rowidx, noff, n, out.ptr, out.row);
-    RWT_LAUNCHED();
+    RWT_TRY(segment_starts(keys, noff, n, out.ptr, nullptr, s));
+    if (noff > 0) {
+        hipLaunchKernelGGL(k_csc_rows, dim3(blocks_for(noff, 256, 8192)), dim3(256), 0, s, pos,
+                           rowidx, noff, out.row);
+        RWT_LAUNCHED();
+    }
     if (noff > 0 && out.map)
         RWT_HIP(hipMemcpyAsync(out.map, pos, (size_t)noff * 4, hipMemcpyDeviceToDevice, s));
     return RWT_OK;
@@ -496,17 +487,6 @@ __global__ void k_perm_keys(const int32_t* level, int32_t n, uint32_t* keys, int
     }
 }
 
-__global__ void k_level_ptr(const uint32_t* keys, int32_t n, int32_t* level_ptr) {
-    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t st = (int64_t)gridDim.x * blockDim.x;
-    for (; q < n; q += st) {
-        int64_t l = keys[q];
-        int64_t prev = q == 0 ? -1 : (int64_t)keys[q - 1];
-        for (int64_t ll = prev + 1; ll <= l; ++ll) level_ptr[ll] = (int32_t)q;
-        if (q == n - 1) level_ptr[l + 1] = n;
-    }
-}
-
 // one wave per level: rows and cost = sum of (2*nnz_row - 1)
 __global__ void k_level_cost(const int32_t* rowptr, const int32_t* perm, const int32_t* level_ptr,
                              const Ctrl* ctrl, int32_t* rows, int64_t* cost) {
@@ -682,8 +662,7 @@ rwt_status compute_levels(const rwt_csr& L, const Csc& csc, const LevelOut& out,
     RWT_LAUNCHED();
     RWT_TRY(radix_sort(keys, out.perm, tkeys, tvals, n, bits_for((uint64_t)(n > 0 ? n - 1 : 0)),
                        rws, s));
-    hipLaunchKernelGGL(k_level_ptr, dim3(gb), dim3(256), 0, s, keys, n, out.level_ptr);
-    RWT_LAUNCHED();
+    RWT_TRY(segment_starts(keys, n, n, out.level_ptr, &ctrl->i2, s));
     hipLaunchKernelGGL(k_level_cost, dim3(blocks_for((size_t)n * WAVE, 256, 4096)), dim3(256), 0, s,
                        L.rowptr, out.perm, out.level_ptr, ctrl, out.rows, out.cost);
     RWT_LAUNCHED();

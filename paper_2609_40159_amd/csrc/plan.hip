@@ -46,6 +46,19 @@ __global__ void k_step_pos(const int32_t* flag, const int32_t* pos, int32_t n, i
     }
 }
 
+// {row, first entry, end, diagonal position} of every row, in block order
+__global__ void k_row_desc(const int32_t* bperm, const int32_t* rowptr, const int32_t* cptr,
+                           int32_t n, int4* df, int4* dt) {
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t st = (int64_t)gridDim.x * blockDim.x;
+    for (; q < n; q += st) {
+        const int32_t i = bperm[q];
+        const int32_t d = rowptr[i + 1] - 1;
+        df[q] = make_int4(i, rowptr[i], d, d);
+        dt[q] = make_int4(i, cptr[i], cptr[i + 1], d);
+    }
+}
+
 template <typename T>
 __global__ void k_fill_val(T* p, int64_t n, T v) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -108,6 +121,8 @@ struct rwt_plan {
     int32_t* bperm = nullptr;
     int32_t* step_pos = nullptr;
     int32_t* blk_step = nullptr;
+    int4* desc_f = nullptr;   // forward row descriptors in block order
+    int4* desc_t = nullptr;   // transposed row descriptors in block order
     void* xtmp = nullptr;     // n * kmax values
     void* xtmp2 = nullptr;    // n values (autotuning)
     Algo fwd = Algo::SyncFree;
@@ -123,14 +138,27 @@ struct PlanLayout {
     size_t bytes;
 };
 
-int default_block_rows(const rwt_plan_opts& o, rwt_dtype dt) {
-    int kmax = o.kmax > 0 ? o.kmax : 1;
-    // LDS for the block's x values: at most 48 KB per workgroup
-    int cap = 49152 / (kmax * (int)dtype_size(dt));
-    int R = o.block_rows > 0 ? o.block_rows : 4096;
-    if (R > cap) R = cap;
-    if (R < 1) R = 1;
-    return R;
+constexpr int R_MIN = 32;   // smallest row block (sizes the block tables)
+
+// A row block size is usable when the block's x values and step starts fit
+// the LDS budget at the largest right-hand-side count.
+bool block_rows_ok(int R, int kmax, rwt_dtype dt) {
+    return R >= R_MIN && syncfree_lds_bytes(R, kmax, dt) <= SF_LDS_BUDGET;
+}
+
+std::vector<int> block_candidates(const rwt_plan_opts& o, rwt_dtype dt) {
+    const int kmax = o.kmax > 0 ? o.kmax : 1;
+    std::vector<int> out;
+    if (o.block_rows > 0) {
+        int R = o.block_rows;
+        while (R > R_MIN && !block_rows_ok(R, kmax, dt)) R /= 2;
+        out.push_back(R < R_MIN ? R_MIN : R);
+        return out;
+    }
+    for (int R : {4096, 2048, 1024, 512, 256, 128, 64, 32})
+        if (block_rows_ok(R, kmax, dt)) out.push_back(R);
+    if (out.empty()) out.push_back(R_MIN);
+    return out;
 }
 
 int default_lanes(int64_t nnz, int32_t n) {
@@ -151,16 +179,17 @@ struct PlanPtrs {
     Csc csc;
     int32_t* seg;
     int32_t *bperm, *step_pos, *blk_step;
+    int4 *desc_f, *desc_t;
     void* xtmp;
     void* xtmp2;
     void* scratch;
     size_t scratch_bytes;
 };
 
-size_t carve_plan(void* base, const rwt_csr& L, int R, int kmax, PlanPtrs* p) {
+size_t carve_plan(void* base, const rwt_csr& L, int kmax, PlanPtrs* p) {
     const int32_t n = L.n;
     const int64_t noff = L.nnz - n > 0 ? L.nnz - n : 1;
-    const int32_t nblocks = (n + R - 1) / R;
+    const int32_t nblocks = (n + R_MIN - 1) / R_MIN;
     const size_t s = dtype_size(L.dt);
     Carver cv(base);
     p->ctrl = cv.take<Ctrl>(1);
@@ -178,6 +207,8 @@ size_t carve_plan(void* base, const rwt_csr& L, int R, int kmax, PlanPtrs* p) {
     p->bperm = cv.take<int32_t>(n);
     p->step_pos = cv.take<int32_t>(n + 1);
     p->blk_step = cv.take<int32_t>(nblocks + 1);
+    p->desc_f = cv.take<int4>(n);
+    p->desc_t = cv.take<int4>(n);
     p->xtmp = cv.take<char>((size_t)n * kmax * s);
     p->xtmp2 = cv.take<char>((size_t)n * s);
     // scratch shared by the construction steps
@@ -256,7 +287,12 @@ rwt_status run_solve(const rwt_plan* p, bool transposed, Algo algo, const void* 
         a.ldb = ldb;
     }
     RWT_TRY(solve_prepare(a, p->L.dt, s));
-    size_t lds = algo == Algo::SyncFree ? (size_t)syncfree_lds_bytes(p->R, k, p->L.dt) : 0;
+    size_t lds = 0;
+    if (algo == Algo::SyncFree) {
+        a.desc = transposed ? p->desc_t : p->desc_f;
+        a.lds_bytes = syncfree_lds_bytes(p->R, k, p->L.dt);
+        lds = (size_t)a.lds_bytes;
+    }
     unsigned grid = solve_grid(algo, p->L.dt, transposed, k, lds, p->cus);
     return solve_launch(a, p->L.dt, algo, transposed, grid, s);
 }
@@ -293,7 +329,7 @@ extern "C" rwt_status rwt_plan_ws(const rwt_csr* L, const rwt_plan_opts* opts, s
     RWT_REQUIRE(h_bytes != nullptr, RWT_ERR_INVALID_ARG, "h_bytes is NULL");
     PlanPtrs pp;
     int kmax = opts->kmax > 0 ? opts->kmax : 1;
-    *h_bytes = carve_plan(nullptr, *L, default_block_rows(*opts, L->dt), kmax, &pp);
+    *h_bytes = carve_plan(nullptr, *L, kmax, &pp);
     return RWT_OK;
 }
 
@@ -303,12 +339,13 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
     RWT_REQUIRE(out != nullptr, RWT_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     const int kmax = opts->kmax > 0 ? opts->kmax : 1;
-    const int R = default_block_rows(*opts, L->dt);
+    const std::vector<int> cands = block_candidates(*opts, L->dt);
+    int R = cands.front();
     PlanPtrs pp;
-    const size_t need = carve_plan(nullptr, *L, R, kmax, &pp);
+    const size_t need = carve_plan(nullptr, *L, kmax, &pp);
     RWT_REQUIRE(d_ws != nullptr && ws_bytes >= need, RWT_ERR_BUFFER_TOO_SMALL,
                 "plan workspace must hold %zu bytes", need);
-    carve_plan(d_ws, *L, R, kmax, &pp);
+    carve_plan(d_ws, *L, kmax, &pp);
     hipStream_t s = hs(stream);
     rwt_plan* p = new (std::nothrow) rwt_plan();
     RWT_REQUIRE(p != nullptr, RWT_ERR_INVALID_ARG, "out of host memory");
@@ -326,6 +363,8 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
     p->bperm = pp.bperm;
     p->step_pos = pp.step_pos;
     p->blk_step = pp.blk_step;
+    p->desc_f = pp.desc_f;
+    p->desc_t = pp.desc_t;
     p->xtmp = pp.xtmp;
     p->xtmp2 = pp.xtmp2;
     p->lanes = opts->lanes_per_row > 0 ? opts->lanes_per_row : default_lanes(L->nnz, L->n);
@@ -395,7 +434,9 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
         return fail(RWT_ERR_HIP);
     }
     // sync-free blocks: rows grouped by block, each block in (level, row) order
-    {
+    auto build_blocks = [&](int Rb) -> rwt_status {
+        p->R = Rb;
+        p->nblocks = (n + Rb - 1) / Rb;
         Carver sc(pp.scratch);
         uint32_t* keys = sc.take<uint32_t>(n);
         uint32_t* tkeys = sc.take<uint32_t>(n);
@@ -404,21 +445,27 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
         void* rws = sc.take<char>(radix_ws(n));
         void* sws = sc.take<char>(scan_ws(n));
         const unsigned g = blocks_for(n, 256, 8192);
-        hipLaunchKernelGGL(k_block_keys, dim3(g), dim3(256), 0, s, p->perm, n, R, keys, p->bperm);
-        if (hipGetLastError() != hipSuccess) return fail(RWT_ERR_HIP);
-        if ((st = radix_sort(keys, p->bperm, tkeys, tvals, n, bits_for((uint64_t)(p->nblocks - 1)),
-                             rws, s)) != RWT_OK)
-            return fail(st);
+        hipLaunchKernelGGL(k_block_keys, dim3(g), dim3(256), 0, s, p->perm, n, Rb, keys, p->bperm);
+        RWT_LAUNCHED();
+        RWT_TRY(radix_sort(keys, p->bperm, tkeys, tvals, n, bits_for((uint64_t)(p->nblocks - 1)),
+                           rws, s));
         int32_t* flag = reinterpret_cast<int32_t*>(keys);   // keys no longer needed
-        hipLaunchKernelGGL(k_step_flags, dim3(g), dim3(256), 0, s, p->bperm, p->level, n, R, flag);
-        if ((st = scan_exclusive(flag, pos, n, sws, s)) != RWT_OK) return fail(st);
-        hipLaunchKernelGGL(k_step_pos, dim3(g), dim3(256), 0, s, flag, pos, n, R, p->nblocks,
+        hipLaunchKernelGGL(k_step_flags, dim3(g), dim3(256), 0, s, p->bperm, p->level, n, Rb, flag);
+        RWT_LAUNCHED();
+        RWT_TRY(scan_exclusive(flag, pos, n, sws, s));
+        hipLaunchKernelGGL(k_step_pos, dim3(g), dim3(256), 0, s, flag, pos, n, Rb, p->nblocks,
                            p->step_pos, p->blk_step);
-        if (hipGetLastError() != hipSuccess) return fail(RWT_ERR_HIP);
-    }
-    // algorithm choice
+        RWT_LAUNCHED();
+        hipLaunchKernelGGL(k_row_desc, dim3(g), dim3(256), 0, s, p->bperm, L->rowptr, p->csc.ptr, n,
+                           p->desc_f, p->desc_t);
+        RWT_LAUNCHED();
+        return RWT_OK;
+    };
+    // algorithm and block size: measured on the plan's own matrix unless forced
     p->fwd = p->bwd = opts->algo == RWT_ALGO_LEVEL ? Algo::Level : Algo::SyncFree;
-    if (opts->algo == RWT_ALGO_AUTO) {
+    const bool tune_algo = opts->algo == RWT_ALGO_AUTO;
+    const bool tune_R = opts->algo != RWT_ALGO_LEVEL && cands.size() > 1;
+    if (tune_algo || tune_R) {
         const unsigned g = blocks_for(n, 256, 8192);
         if (L->dt == RWT_F64)
             hipLaunchKernelGGL(k_fill_val<double>, dim3(g), dim3(256), 0, s,
@@ -426,14 +473,25 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
         else
             hipLaunchKernelGGL(k_fill_val<float>, dim3(g), dim3(256), 0, s,
                                static_cast<float*>(p->xtmp), (int64_t)n, 1.0f);
-        p->tuned_level = time_solve(p, Algo::Level, s, 3);
-        p->tuned_sf = time_solve(p, Algo::SyncFree, s, 3);
-        if (p->tuned_level >= 1e30 && p->tuned_sf >= 1e30) {
-            set_error("autotuning solves failed");
-            return fail(RWT_ERR_DEADLOCK);
+        double best_sf = 1e30;
+        int best_R = cands.front();
+        for (int Rc : cands) {
+            if ((st = build_blocks(Rc)) != RWT_OK) return fail(st);
+            double ms = time_solve(p, Algo::SyncFree, s, 3);
+            if (ms < best_sf) { best_sf = ms; best_R = Rc; }
         }
-        p->fwd = p->bwd = p->tuned_level < p->tuned_sf ? Algo::Level : Algo::SyncFree;
+        p->tuned_sf = best_sf;
+        R = best_R;
+        if (tune_algo) {
+            p->tuned_level = time_solve(p, Algo::Level, s, 3);
+            if (p->tuned_level >= 1e30 && best_sf >= 1e30) {
+                set_error("autotuning solves failed");
+                return fail(RWT_ERR_DEADLOCK);
+            }
+            p->fwd = p->bwd = p->tuned_level < best_sf ? Algo::Level : Algo::SyncFree;
+        }
     }
+    if ((st = build_blocks(R)) != RWT_OK) return fail(st);
     if (hipStreamSynchronize(s) != hipSuccess) {
         set_hip_error(hipGetLastError(), "plan creation");
         return fail(RWT_ERR_HIP);

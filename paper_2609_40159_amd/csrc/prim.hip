@@ -189,7 +189,31 @@ __global__ void k_expand_rows(const int32_t* rowptr, int32_t n, int32_t* rowidx)
     }
 }
 
+__global__ void k_segment_starts(const uint32_t* keys, int64_t nkeys, int64_t nseg, int32_t* ptr,
+                                 const int32_t* nseg_dev) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t st = (int64_t)gridDim.x * blockDim.x;
+    const int64_t last = nseg_dev ? (int64_t)*nseg_dev : nseg;
+    for (; c <= last; c += st) {
+        int64_t lo = 0, hi = nkeys;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if ((int64_t)keys[mid] < c) lo = mid + 1;
+            else hi = mid;
+        }
+        ptr[c] = (int32_t)lo;
+    }
+}
+
 }  // namespace
+
+rwt_status segment_starts(const uint32_t* keys, int64_t nkeys, int64_t nseg, int32_t* ptr,
+                          const int32_t* nseg_dev, hipStream_t s) {
+    hipLaunchKernelGGL(k_segment_starts, dim3(blocks_for(nseg + 1, 256, 8192)), dim3(256), 0, s,
+                       keys, nkeys, nseg, ptr, nseg_dev);
+    RWT_LAUNCHED();
+    return RWT_OK;
+}
 
 size_t scan_ws(int64_t n) {
     int64_t nt = (n + SCAN_TILE - 1) / SCAN_TILE;

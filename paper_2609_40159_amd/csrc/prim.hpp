@@ -22,6 +22,11 @@ rwt_status radix_sort(uint32_t* keys, int32_t* vals, uint32_t* tmp_keys, int32_t
 rwt_status fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 rwt_status fill_u8(void* p, int64_t bytes, hipStream_t s);   // zero bytes
 
+// ptr[c] = first position q with keys[q] >= c, for c in [0, nseg] (keys
+// ascending).  With nseg_dev != nullptr only c <= *nseg_dev is written.
+rwt_status segment_starts(const uint32_t* keys, int64_t nkeys, int64_t nseg, int32_t* ptr,
+                          const int32_t* nseg_dev, hipStream_t s);
+
 // row index of every stored entry
 rwt_status expand_rows(const int32_t* rowptr, int32_t n, int32_t* rowidx, hipStream_t s);
 

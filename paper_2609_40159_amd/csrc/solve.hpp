@@ -32,6 +32,8 @@ struct SolveArgs {
     int64_t ldx;
     int32_t k;
     int32_t lanes;             // lanes per row (power of two, 1..64)
+    const int4* desc;          // sync-free: per row in bperm order {row, first, end, diagonal}
+    int32_t lds_bytes;         // sync-free: dynamic LDS per workgroup
     Ctrl* ctrl;
     int64_t ticks;
 };
@@ -42,7 +44,9 @@ enum class Algo { Level, SyncFree };
 rwt_status solve_prepare(const SolveArgs& a, rwt_dtype dt, hipStream_t s);
 rwt_status solve_launch(const SolveArgs& a, rwt_dtype dt, Algo algo, bool transposed,
                         unsigned grid, hipStream_t s);
+// LDS of one sync-free workgroup: the block's x values and its step starts
 int syncfree_lds_bytes(int block_rows, int k, rwt_dtype dt);
+constexpr int SF_LDS_BUDGET = 60 * 1024;
 // workgroups of a persistent solve launch (all resident)
 unsigned solve_grid(Algo algo, rwt_dtype dt, bool transposed, int k, size_t lds, int cus);
 
