@@ -256,6 +256,86 @@ rwt_status rwt_apply_MT(int32_t n, int64_t nC, const int32_t* d_crow, const int3
 rwt_status rwt_grad_vals(const rwt_csr* L, const void* d_gB, int64_t ldg, const void* d_X,
                          int64_t ldx, int32_t k, void* d_gvals, rwt_stream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Batched launch: many matrices of uneven size, each with its own block of
+ * right-hand sides, plus many candidate rewrite sets (rewriting lists in
+ * the sense of Algorithm 1, one per environment step of the paper's agent)
+ * whose level statistics are computed -- all in one persistent kernel,
+ * preceded by a few setup kernels, launched together (optionally replayed
+ * from a captured hipGraph).
+ *
+ * Per matrix m: L (FP64 values), B / X (k columns; k may be 0 for
+ * analysis-only matrices).  Its solve schedule is autotuned at creation
+ * (sync-free row blocks of a measured size, or the whole matrix in one
+ * workgroup, level after level, when it fits in LDS).
+ * Per candidate c: the matrix h_cand_mat[c] and the rows
+ * d_cand_rows[d_cand_ptr[c] .. d_cand_ptr[c+1]) (strictly ascending) with
+ * targets d_cand_targets (NULL: level - 1).  Each launch recomputes, for
+ * every candidate, the levels of the rewritten matrix L' and its statistics
+ * (level count, S1, exact S2, CV of level costs) -- L' itself is not formed.
+ * The row lists (and d_cand_ptr) may change between launches within
+ * cand_rows_cap rows and pattern_cap rewritten-row entries.
+ *
+ * The batch keeps pointers to every caller array; the workspace
+ * (rwt_batch_ws bytes) holds the per-matrix plans and all scratch.
+ * Invalid candidate row lists are skipped (statistics flagged invalid) and
+ * reported by rwt_batch_stats as RWT_ERR_BAD_ROWSET.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    rwt_csr L;            /* device, FP64 values */
+    const void* B;        /* device, k columns (ldb) */
+    void* X;              /* device, k columns (ldx) */
+    int32_t k;
+    int32_t pad_;
+    int64_t ldb;
+    int64_t ldx;
+} rwt_batch_matrix;
+
+typedef struct {
+    int32_t count;                      /* matrices */
+    int32_t num_cand;                   /* candidate rewrite sets */
+    const rwt_batch_matrix* mats;       /* host array of count */
+    const int32_t* h_cand_mat;          /* host, num_cand */
+    const int32_t* d_cand_ptr;          /* device, num_cand + 1 */
+    const int32_t* d_cand_rows;         /* device */
+    const int32_t* d_cand_targets;      /* device or NULL */
+    int32_t cand_rows_cap;              /* capacity of the concatenated row lists */
+    int32_t pattern_cap;                /* capacity of rewritten-row patterns (0: 64 per row) */
+    int32_t watchdog_ms;
+    int32_t pad_;
+} rwt_batch_desc;
+
+typedef struct {
+    int32_t num_levels;
+    int32_t valid;        /* 0: the candidate's row list was rejected */
+    uint64_t S1;
+    uint64_t S2_lo;
+    uint64_t S2_hi;
+    double cv;
+} rwt_cand_stats;
+
+typedef struct {
+    int32_t tasks;        /* row-block tasks of the persistent launch */
+    int32_t solve_tasks;
+    int32_t grid;
+    int32_t captured;     /* a graph is instantiated */
+    double create_ms;
+} rwt_batch_info;
+
+typedef struct rwt_batch rwt_batch;
+
+rwt_status rwt_batch_ws(const rwt_batch_desc* desc, size_t* h_bytes);
+rwt_status rwt_batch_create(const rwt_batch_desc* desc, void* d_ws, size_t ws_bytes,
+                            rwt_batch** out, rwt_stream_t stream);
+rwt_status rwt_batch_run(rwt_batch* batch, rwt_stream_t stream);
+/* stream must not be the legacy default stream (capture needs a real stream) */
+rwt_status rwt_batch_capture(rwt_batch* batch, rwt_stream_t stream);
+rwt_status rwt_batch_launch(rwt_batch* batch, rwt_stream_t stream);
+rwt_status rwt_batch_stats(const rwt_batch* batch, rwt_cand_stats* h_out, rwt_stream_t stream);
+rwt_status rwt_batch_get_info(const rwt_batch* batch, rwt_batch_info* h_info);
+rwt_status rwt_batch_plan(const rwt_batch* batch, int32_t m, const rwt_plan** out);
+rwt_status rwt_batch_destroy(rwt_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

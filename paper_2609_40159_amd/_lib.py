@@ -61,6 +61,29 @@ class PlanInfo(C.Structure):
                 ("tuned_ms_syncfree", C.c_double)]
 
 
+class BatchMatrix(C.Structure):
+    _fields_ = [("L", Csr), ("B", C.c_void_p), ("X", C.c_void_p), ("k", C.c_int32),
+                ("pad_", C.c_int32), ("ldb", C.c_int64), ("ldx", C.c_int64)]
+
+
+class BatchDesc(C.Structure):
+    _fields_ = [("count", C.c_int32), ("num_cand", C.c_int32), ("mats", C.c_void_p),
+                ("h_cand_mat", C.c_void_p), ("d_cand_ptr", C.c_void_p),
+                ("d_cand_rows", C.c_void_p), ("d_cand_targets", C.c_void_p),
+                ("cand_rows_cap", C.c_int32), ("pattern_cap", C.c_int32),
+                ("watchdog_ms", C.c_int32), ("pad_", C.c_int32)]
+
+
+class CandStats(C.Structure):
+    _fields_ = [("num_levels", C.c_int32), ("valid", C.c_int32), ("S1", C.c_uint64),
+                ("S2_lo", C.c_uint64), ("S2_hi", C.c_uint64), ("cv", C.c_double)]
+
+
+class BatchInfo(C.Structure):
+    _fields_ = [("tasks", C.c_int32), ("solve_tasks", C.c_int32), ("grid", C.c_int32),
+                ("captured", C.c_int32), ("create_ms", C.c_double)]
+
+
 P = C.c_void_p
 I32 = C.c_int32
 I64 = C.c_int64
@@ -91,6 +114,15 @@ SIGNATURES = {
     "rwt_apply_MT_ws": (C.c_int, [I32, I64, C.POINTER(SZ)]),
     "rwt_apply_MT": (C.c_int, [I32, I64, P, P, P, I32, P, I32, I64, P, I64, P, SZ, P]),
     "rwt_grad_vals": (C.c_int, [C.POINTER(Csr), P, I64, P, I64, I32, P, P]),
+    "rwt_batch_ws": (C.c_int, [C.POINTER(BatchDesc), C.POINTER(SZ)]),
+    "rwt_batch_create": (C.c_int, [C.POINTER(BatchDesc), P, SZ, C.POINTER(P), P]),
+    "rwt_batch_run": (C.c_int, [P, P]),
+    "rwt_batch_capture": (C.c_int, [P, P]),
+    "rwt_batch_launch": (C.c_int, [P, P]),
+    "rwt_batch_stats": (C.c_int, [P, P, P]),
+    "rwt_batch_get_info": (C.c_int, [P, C.POINTER(BatchInfo)]),
+    "rwt_batch_plan": (C.c_int, [P, I32, C.POINTER(P)]),
+    "rwt_batch_destroy": (C.c_int, [P]),
 }
 
 _lib = None

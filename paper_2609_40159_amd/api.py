@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import RwtError, check
 
 __all__ = ["CSRMatrix", "LevelInfo", "validate", "analyze", "rewrite", "Rewrite", "Rewriter", "Plan",
-           "apply_MT", "grad_vals", "RwtError"]
+           "apply_MT", "grad_vals", "Batch", "RwtError"]
 
 
 def _stream() -> int:
@@ -318,3 +318,128 @@ def grad_vals(L: CSRMatrix, gB: torch.Tensor, X: torch.Tensor) -> torch.Tensor:
     check(lib.rwt_grad_vals(C.byref(L.view()), _ptr(gB2), L.n, _ptr(X2), L.n, k, _ptr(out),
                             _stream()))
     return out
+
+
+class Batch:
+    """Many matrices (each with k right-hand sides) and many candidate rewrite
+    sets, run as one persistent launch (optionally a captured graph).
+
+    mats: list of (CSRMatrix FP64, B (k, n) or None, X (k, n) or None).
+    cand_mat: matrix index of each candidate; cand_ptr (C+1) and cand_rows
+    are device int32 tensors whose contents may change between launches
+    (within cand_rows_cap rows).  All work runs on the batch's own stream,
+    ordered after the caller's current stream and before it again.
+    """
+
+    def __init__(self, mats, cand_mat, cand_ptr, cand_rows, cand_targets=None,
+                 cand_rows_cap: int | None = None, pattern_cap: int = 0, watchdog_ms: int = 0):
+        lib = _lib.load()
+        self._lib = lib
+        self.mats = list(mats)
+        dev = self.mats[0][0].device if self.mats else torch.device("cuda")
+        self.stream = torch.cuda.Stream(device=dev)
+        arr = (_lib.BatchMatrix * max(1, len(self.mats)))()
+        self._keep = []
+        for i, (L, B, X) in enumerate(self.mats):
+            if L.dtype != torch.float64:
+                raise TypeError("batched matrices must be float64")
+            arr[i].L = L.view()
+            k = 0
+            if B is not None:
+                B2, k = _block(B, L.n, L.dtype)
+                X2, k2 = _block(X, L.n, L.dtype)
+                if k != k2:
+                    raise ValueError("B and X must have the same number of columns")
+                arr[i].B = B2.data_ptr()
+                arr[i].X = X2.data_ptr()
+                self._keep += [B2, X2]
+            arr[i].k = k
+            arr[i].ldb = L.n
+            arr[i].ldx = L.n
+        self._arr = arr
+        self.cand_mat = (C.c_int32 * max(1, len(cand_mat)))(*cand_mat)
+        self.cand_ptr = cand_ptr
+        self.cand_rows = cand_rows
+        self.cand_targets = cand_targets
+        self.num_cand = len(cand_mat)
+        d = _lib.BatchDesc()
+        d.count = len(self.mats)
+        d.num_cand = self.num_cand
+        d.mats = C.cast(arr, C.c_void_p)
+        d.h_cand_mat = C.cast(self.cand_mat, C.c_void_p)
+        d.d_cand_ptr = cand_ptr.data_ptr() if self.num_cand else None
+        d.d_cand_rows = cand_rows.data_ptr() if self.num_cand else None
+        d.d_cand_targets = None if cand_targets is None else cand_targets.data_ptr()
+        d.cand_rows_cap = int(cand_rows_cap if cand_rows_cap is not None
+                              else (cand_rows.numel() if cand_rows is not None else 0))
+        d.pattern_cap = pattern_cap
+        d.watchdog_ms = watchdog_ms
+        self.desc = d
+        sz = C.c_size_t(0)
+        check(lib.rwt_batch_ws(C.byref(d), C.byref(sz)))
+        self.ws = _workspace(sz.value, dev)
+        h = C.c_void_p()
+        self._enter()
+        try:
+            check(lib.rwt_batch_create(C.byref(d), _ptr(self.ws), self.ws.numel(), C.byref(h),
+                                       self.stream.cuda_stream))
+        finally:
+            self._leave()
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.rwt_batch_destroy(h)
+            self._h = None
+
+    def _enter(self):
+        self.stream.wait_stream(torch.cuda.current_stream(self.stream.device))
+
+    def _leave(self):
+        torch.cuda.current_stream(self.stream.device).wait_stream(self.stream)
+
+    def run(self) -> None:
+        """Enqueue one batched launch (no graph)."""
+        self._enter()
+        check(self._lib.rwt_batch_run(self._h, self.stream.cuda_stream))
+        self._leave()
+
+    def capture(self) -> None:
+        """Capture the launch sequence into a graph (replayed by launch())."""
+        self._enter()
+        check(self._lib.rwt_batch_capture(self._h, self.stream.cuda_stream))
+        self._leave()
+
+    def launch(self) -> None:
+        self._enter()
+        check(self._lib.rwt_batch_launch(self._h, self.stream.cuda_stream))
+        self._leave()
+
+    def stats(self) -> list[dict]:
+        out = (_lib.CandStats * max(1, self.num_cand))()
+        st = self._lib.rwt_batch_stats(self._h, C.cast(out, C.c_void_p), self.stream.cuda_stream)
+        res = []
+        for c in range(self.num_cand):
+            s = out[c]
+            res.append({"num_levels": s.num_levels, "valid": bool(s.valid), "S1": int(s.S1),
+                        "S2": int(s.S2_lo) | (int(s.S2_hi) << 64), "cv": s.cv})
+        self.last_status = _lib.STATUS.get(st, str(st))
+        if st not in (_lib.OK, -6):        # rejected candidates are reported per entry
+            check(st)
+        return res
+
+    @property
+    def info(self) -> dict:
+        i = _lib.BatchInfo()
+        check(self._lib.rwt_batch_get_info(self._h, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in i._fields_}
+
+    def plan_info(self, m: int) -> dict:
+        p = C.c_void_p()
+        check(self._lib.rwt_batch_plan(self._h, m, C.byref(p)))
+        inf = _lib.PlanInfo()
+        check(self._lib.rwt_plan_get_info(p, C.byref(inf)))
+        return {"algo": "one workgroup" if inf.num_blocks == 1 else "sync-free blocks",
+                "block_rows": inf.block_rows, "lanes_per_row": inf.lanes_per_row,
+                "num_blocks": inf.num_blocks, "tuned_ms": inf.tuned_ms_syncfree}

@@ -1,0 +1,896 @@
+// Batched launch: solves of many matrices and level statistics of many
+// candidate rewrite sets in one persistent kernel (plus setup kernels),
+// optionally replayed from a captured hipGraph.
+//
+// Work is a table of row-block tasks.  A chain is the sequence of blocks of
+// one matrix's solve, or of one candidate's level computation; inside a
+// chain the tasks follow row order, so a task only ever waits for rows of
+// tasks with earlier tickets (deadlock-free for any number of resident
+// workgroups).  Chains are interleaved by their relative position, so that
+// every chain advances while others wait on dependencies.
+//
+//   solve task      one row block of matrix m: the sync-free block body
+//                   shared with the single-matrix solve (x values in LDS,
+//                   sentinel-checked reads of rows outside the block).
+//   level task      one row block of candidate c: the levels of the
+//                   rewritten matrix L' (Section 2.1 level of a row: 1 +
+//                   the largest level of its dependencies), taking rewritten
+//                   rows' new dependency lists from the batched symbolic
+//                   rewrite.  Rows are visited in the original (level, row)
+//                   order, which is topological for L' as well: a rewritten
+//                   row's new dependencies all sit on earlier original
+//                   levels.  Levels are published tagged with the launch
+//                   epoch (readiness without clearing the arrays).
+//   finalize        the workgroup finishing a candidate's last block builds
+//                   the level-cost histogram (cost 2*nnz'_row - 1) in LDS and
+//                   the exact S1 / S2 / CV.
+#include <algorithm>
+#include <chrono>
+#include <new>
+#include <vector>
+
+#include "batch.hpp"
+#include "plan.hpp"
+#include "prim.hpp"
+#include "sf_block.hpp"
+#include "u128.hpp"
+
+namespace rwt {
+
+namespace {
+
+constexpr int BT_THREADS = 256;
+constexpr int BT_LDS = SF_LDS_BUDGET;
+constexpr int NSLAB_B = 2;
+
+struct BatchMatDev {
+    int32_t n, R, lanes, nblocks, k, pad;
+    int64_t ldb, ldx;
+    const int32_t* rowptr;
+    const int32_t* colidx;
+    const int32_t* level;
+    const double* vals;
+    const int4* desc;
+    const int32_t* step_pos;
+    const int32_t* blk_step;
+    const double* B;
+    double* X;
+};
+
+struct BatchCandDev {
+    int32_t m;
+    int32_t pad;
+    uint32_t* bitmap;   // rewritten rows
+    int32_t* lev;       // levels of L', tagged with the launch epoch
+};
+
+struct BatchKArgs {
+    const BatchMatDev* mats;
+    const BatchCandDev* cands;
+    const int4* tasks;
+    int32_t ntasks;
+    int32_t C;
+    const int32_t* cand_ptr;
+    const int32_t* rows;
+    const int32_t* counts_q;
+    const int32_t* pat_ptr;
+    const int32_t* pat;
+    const unsigned char* cand_bad;
+    int32_t* cand_done;
+    rwt_cand_stats* stats;
+    Ctrl* ctrl;
+    const uint32_t* epoch;
+    int64_t ticks;
+};
+
+__device__ __forceinline__ uint32_t epoch_tag(uint32_t e) { return (e % 255u) + 1u; }
+
+__device__ __forceinline__ void lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// level of row j of candidate c, written by another workgroup
+__device__ __forceinline__ int32_t wait_level(const int32_t* p, uint32_t tag, int32_t* err,
+                                              int64_t ticks) {
+    int32_t v = ld_relaxed(p);
+    if (((uint32_t)v >> 24) == tag) return v & 0xffffff;
+    int64_t t0 = wall_clock64();
+    for (;;) {
+        __builtin_amdgcn_s_sleep(0);
+        v = ld_relaxed(p);
+        if (((uint32_t)v >> 24) == tag) return v & 0xffffff;
+        if (ld_relaxed(err) != 0) return 0;
+        if (wall_clock64() - t0 > ticks) {
+            __hip_atomic_store(err, (int32_t)RWT_ERR_DEADLOCK, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            return 0;
+        }
+    }
+}
+
+template <typename T>
+__device__ T group_max_i(T v, int G) {
+    for (int o = G / 2; o > 0; o >>= 1) {
+        T u = __shfl_xor(v, o);
+        v = u > v ? u : v;
+    }
+    return v;
+}
+
+__device__ int32_t lower_bound_g(const int32_t* a, int32_t lo, int32_t hi, int32_t x) {
+    while (lo < hi) {
+        int32_t mid = (lo + hi) >> 1;
+        if (a[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ void level_block(const BatchKArgs& a, const BatchMatDev& M, const BatchCandDev& Cd,
+                            int32_t c, int32_t blk, uint32_t tag, unsigned char* s_raw) {
+    const int32_t R = M.R;
+    const int32_t r0 = blk * R, r1 = min(M.n, r0 + R);
+    const int32_t sb = M.blk_step[blk], ns = M.blk_step[blk + 1] - sb;
+    int32_t* lv = reinterpret_cast<int32_t*>(s_raw);
+    int32_t* sp = reinterpret_cast<int32_t*>(s_raw + ((R * 4 + 15) & ~15));
+    for (int32_t u = threadIdx.x; u <= ns; u += blockDim.x) sp[u] = M.step_pos[sb + u] - r0;
+    __syncthreads();
+    const int32_t qb = a.cand_ptr[c], qe = a.cand_ptr[c + 1];
+    const int G = M.lanes;
+    const int gl = threadIdx.x & (G - 1);
+    const int lane = lane_id();
+    const int gpw = WAVE / G;
+    const int wib = threadIdx.x / WAVE;
+    const int32_t stride = (blockDim.x / WAVE) * gpw;
+    int32_t* err = &a.ctrl->err;
+    for (int32_t u = 0; u < ns; ++u) {
+        const int32_t beg = sp[u], end = sp[u + 1];
+        for (int32_t base = beg + wib * gpw; base < end; base += stride) {
+            const int32_t pos = base + lane / G;
+            const bool act = pos < end;
+            int32_t i = r0, db = 0, de = 0;
+            const int32_t* dep = M.colidx;
+            if (act) {
+                const int4 d = M.desc[r0 + pos];
+                i = d.x;
+                db = d.y;
+                de = d.z;   // forward pattern without the diagonal
+                if (!a.cand_bad[c] && ((Cd.bitmap[i >> 5] >> (i & 31)) & 1u)) {
+                    const int32_t q = lower_bound_g(a.rows, qb, qe, i);
+                    db = a.pat_ptr[q];
+                    de = a.pat_ptr[q + 1] - 1;   // the new row's diagonal is last
+                    dep = a.pat;
+                }
+            }
+            int32_t mx = -1;
+            for (int32_t p = db + gl; p < de; p += G) {
+                const int32_t j = dep[p];
+                if (j < 0 || j >= i) {   // cannot happen for a consistent batch; never index with it
+                    __hip_atomic_store(err, (int32_t)RWT_ERR_INVALID_ARG, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    continue;
+                }
+                const int32_t lj = j >= r0 ? lv[j - r0] : wait_level(&Cd.lev[j], tag, err, a.ticks);
+                mx = lj > mx ? lj : mx;
+            }
+            mx = group_max_i(mx, G);
+            if (act && gl == 0) {
+                const int32_t L = mx + 1;
+                lv[i - r0] = L;
+                st_relaxed(&Cd.lev[i], (int32_t)((tag << 24) | (uint32_t)L));
+            }
+        }
+        lds_sync();
+    }
+}
+
+__device__ U128 block_sum_u128_bt(U128 v, unsigned char* scratch) {
+    uint64_t* s = reinterpret_cast<uint64_t*>(scratch);
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        U128 u;
+        u.lo = __shfl_xor(v.lo, o);
+        u.hi = __shfl_xor(v.hi, o);
+        v = u128_add(v, u);
+    }
+    const int w = threadIdx.x / WAVE;
+    __syncthreads();
+    if (lane_id() == 0) {
+        s[2 * w] = v.lo;
+        s[2 * w + 1] = v.hi;
+    }
+    __syncthreads();
+    U128 r{0, 0};
+    for (int i = 0; i < (int)(blockDim.x / WAVE); ++i) r = u128_add(r, U128{s[2 * i], s[2 * i + 1]});
+    __syncthreads();
+    return r;
+}
+
+__device__ int32_t block_max_bt(int32_t v, int32_t* scratch) {
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        int32_t u = __shfl_xor(v, o);
+        v = u > v ? u : v;
+    }
+    const int w = threadIdx.x / WAVE;
+    __syncthreads();
+    if (lane_id() == 0) scratch[w] = v;
+    __syncthreads();
+    int32_t r = scratch[0];
+    for (int i = 1; i < (int)(blockDim.x / WAVE); ++i) r = scratch[i] > r ? scratch[i] : r;
+    __syncthreads();
+    return r;
+}
+
+// statistics of candidate c (its levels are all published)
+__device__ void finalize_cand(const BatchKArgs& a, const BatchMatDev& M, const BatchCandDev& Cd,
+                              int32_t c, uint32_t tag, unsigned char* s_raw) {
+    int32_t* err = &a.ctrl->err;
+    const int32_t n = M.n;
+    int32_t mx = -1;
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const int32_t L = wait_level(&Cd.lev[i], tag, err, a.ticks);
+        mx = L > mx ? L : mx;
+    }
+    const int32_t D = block_max_bt(mx, reinterpret_cast<int32_t*>(s_raw)) + 1;
+    const int32_t qb = a.cand_ptr[c], qe = a.cand_ptr[c + 1];
+    uint32_t* hist = reinterpret_cast<uint32_t*>(s_raw + 256);
+    const int32_t HC = (BT_LDS - 256) / 4;
+    uint64_t s1 = 0;
+    U128 s2{0, 0};
+    for (int32_t lb = 0; lb < D; lb += HC) {
+        const int32_t le = min(D, lb + HC);
+        for (int32_t l = threadIdx.x; l < le - lb; l += blockDim.x) hist[l] = 0u;
+        __syncthreads();
+        for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
+            const int32_t L = ld_relaxed(&Cd.lev[i]) & 0xffffff;
+            if (L >= lb && L < le)
+                atomicAdd(&hist[L - lb], (uint32_t)(2 * (M.rowptr[i + 1] - M.rowptr[i]) - 1));
+        }
+        // rewritten rows: cost of the new row instead of the old one (a
+        // rejected candidate's list is never read: its bounds may be invalid)
+        const int32_t qe_ok = a.cand_bad[c] ? qb : qe;
+        for (int32_t q = qb + threadIdx.x; q < qe_ok; q += blockDim.x) {
+            const int32_t r = a.rows[q];
+            if (!((Cd.bitmap[r >> 5] >> (r & 31)) & 1u)) continue;
+            const int32_t L = ld_relaxed(&Cd.lev[r]) & 0xffffff;
+            if (L >= lb && L < le)
+                atomicAdd(&hist[L - lb],
+                          (uint32_t)(2 * (a.counts_q[q] - (M.rowptr[r + 1] - M.rowptr[r]))));
+        }
+        __syncthreads();
+        for (int32_t l = threadIdx.x; l < le - lb; l += blockDim.x) {
+            const uint64_t v = hist[l];
+            s1 += v;
+            s2 = u128_add(s2, U128{v * v, __umul64hi(v, v)});
+        }
+        __syncthreads();
+    }
+    // sums across the workgroup (s1 fits 64 bits: it is 2 nnz' - n)
+    U128 s1w = block_sum_u128_bt(U128{s1, 0}, s_raw);
+    U128 s2w = block_sum_u128_bt(s2, s_raw);
+    if (threadIdx.x == 0) {
+        rwt_cand_stats o;
+        o.num_levels = D;
+        o.valid = a.cand_bad[c] ? 0 : 1;
+        o.S1 = s1w.lo;
+        o.S2_lo = s2w.lo;
+        o.S2_hi = s2w.hi;
+        o.cv = cv_exact((uint64_t)D, s1w.lo, s2w);
+        a.stats[c] = o;
+    }
+}
+
+__global__ void __launch_bounds__(BT_THREADS) k_batch_main(BatchKArgs a) {
+    extern __shared__ __align__(16) unsigned char s_raw[];
+    __shared__ int32_t s_task;
+    __shared__ int32_t s_last;
+    const uint32_t tag = epoch_tag(*a.epoch);
+    for (;;) {
+        if (threadIdx.x == 0) s_task = (int32_t)fetch_add(&a.ctrl->ticket, 1u);
+        __syncthreads();
+        const int32_t t = s_task;
+        __syncthreads();
+        if (t >= a.ntasks) break;
+        const int4 tk = a.tasks[t];
+        if (tk.x == 0) {
+            const BatchMatDev& M = a.mats[tk.y];
+            SfBlockArgs b;
+            b.r0 = tk.z * M.R;
+            b.r1 = min(M.n, b.r0 + M.R);
+            b.sb = M.blk_step[tk.z];
+            b.ns = M.blk_step[tk.z + 1] - b.sb;
+            b.k = M.k;
+            b.lanes = M.lanes;
+            b.ldb = M.ldb;
+            b.ldx = M.ldx;
+            b.colidx = M.colidx;
+            b.crow = nullptr;
+            b.cmap = nullptr;
+            b.vals = M.vals;
+            b.desc = M.desc;
+            b.step_pos = M.step_pos;
+            b.B = M.B;
+            b.X = M.X;
+            b.err = &a.ctrl->err;
+            b.ticks = a.ticks;
+            b.lds_rows = M.R;
+            if (M.k == 1) sf_block<double, false, 1>(b, s_raw);
+            else if (M.k <= 4) sf_block<double, false, 4>(b, s_raw);
+            else sf_block<double, false, 16>(b, s_raw);
+        } else {
+            const int32_t c = tk.y;
+            const BatchCandDev& Cd = a.cands[c];
+            const BatchMatDev& M = a.mats[Cd.m];
+            level_block(a, M, Cd, c, tk.z, tag, s_raw);
+            __syncthreads();
+            if (threadIdx.x == 0)
+                s_last = (fetch_add(&a.cand_done[c], 1) == M.nblocks - 1) ? 1 : 0;
+            __syncthreads();
+            if (s_last) finalize_cand(a, M, Cd, c, tag, s_raw);
+        }
+        __syncthreads();
+        if (ld_relaxed(&a.ctrl->err) != 0) break;
+    }
+}
+
+__global__ void k_batch_epoch(uint32_t* epoch) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *epoch = *epoch + 1u;
+}
+
+// Reset per-launch state: counters, bitmaps, overflow marks, X sentinels,
+// and every level array once per 255 launches (before its tags repeat).
+__global__ void k_batch_begin(const BatchMatDev* mats, int32_t count, uint32_t* bitmaps,
+                              int64_t bitmap_words, int32_t* levs, int64_t lev_words,
+                              const uint32_t* epoch, int32_t* cand_done, unsigned char* cand_bad,
+                              int32_t C, int32_t* counts_q, unsigned char* ovf_mark, int32_t qcap,
+                              Ctrl* ctrl, int32_t* rwctrl) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    if (tid == 0) {
+        ctrl->bar_count = 0;
+        ctrl->bar_gen = 0;
+        ctrl->ticket = 0;
+        ctrl->err = 0;
+        ctrl->heartbeat = 0;
+        for (int i = 0; i < 8; ++i) rwctrl[i] = 0;
+    }
+    for (int64_t i = tid; i < C; i += nth) {
+        cand_done[i] = 0;
+        cand_bad[i] = 0;
+    }
+    for (int64_t i = tid; i < bitmap_words; i += nth) bitmaps[i] = 0u;
+    for (int64_t i = tid; i <= qcap; i += nth) counts_q[i] = 0;
+    for (int64_t i = tid; i < qcap; i += nth) ovf_mark[i] = 0;
+    if ((*epoch % 255u) == 0u)
+        for (int64_t i = tid; i < lev_words; i += nth) levs[i] = 0;
+    const double s = sentinel_value<double>();
+    for (int32_t m = 0; m < count; ++m) {
+        const BatchMatDev& M = mats[m];
+        const int64_t total = (int64_t)M.n * M.k;
+        for (int64_t e = tid; e < total; e += nth) {
+            const int64_t q = e / M.n, i = e - q * M.n;
+            M.X[i + q * M.ldx] = s;
+        }
+    }
+}
+
+// The candidate list as a whole: offsets start at 0, never decrease and end
+// within the row capacity.  Otherwise every candidate is rejected.
+__global__ void k_batch_ptrcheck(const int32_t* cand_ptr, int32_t C, int32_t qcap,
+                                 int32_t* rwctrl) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    if (tid == 0) bad = cand_ptr[0] != 0 || cand_ptr[C] > qcap;
+    for (int64_t c = tid; c < C; c += nth) bad = bad || cand_ptr[c] > cand_ptr[c + 1];
+    if (bad) atomicExch(&rwctrl[6], 1);
+}
+
+// One wave per candidate: check its row list, then mark the rows that the
+// rewrite changes (level >= 1 and target below the level).
+__global__ void k_batch_bitmap(const BatchMatDev* mats, const BatchCandDev* cands, int32_t C,
+                               const int32_t* cand_ptr, const int32_t* rows, const int32_t* targets,
+                               int32_t qcap, unsigned char* cand_bad, int32_t* rwctrl) {
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+    const int lane = lane_id();
+    const bool list_ok = ld_relaxed(&rwctrl[6]) == 0;
+    for (int64_t c = wave; c < C; c += nw) {
+        const BatchCandDev& Cd = cands[c];
+        const BatchMatDev& M = mats[Cd.m];
+        const int32_t qb = cand_ptr[c], qe = cand_ptr[c + 1];
+        bool bad = !list_ok || qe < qb || qb < 0 || qe > qcap;
+        if (!bad) {
+            for (int32_t q = qb + lane; q < qe; q += WAVE) {
+                const int32_t r = rows[q];
+                if (r < 0 || r >= M.n || (q > qb && rows[q - 1] >= r) || (targets && targets[q] < 0))
+                    bad = true;
+            }
+        }
+        bad = __ballot(bad) != 0;
+        if (bad) {
+            if (lane == 0) {
+                cand_bad[c] = 1;
+                atomicExch(&rwctrl[5], 1);
+            }
+            continue;
+        }
+        for (int32_t q = qb + lane; q < qe; q += WAVE) {
+            const int32_t r = rows[q];
+            const int32_t lvl = M.level[r];
+            const int32_t t = targets ? targets[q] : lvl - 1;
+            if (lvl > 0 && t < lvl) atomicOr(&Cd.bitmap[r >> 5], 1u << (r & 31));
+        }
+    }
+}
+
+}  // namespace
+}  // namespace rwt
+
+using namespace rwt;
+
+struct rwt_batch {
+    rwt_batch_desc desc;
+    std::vector<rwt_batch_matrix> mats;
+    std::vector<int32_t> cand_mat;
+    std::vector<rwt_plan*> plans;
+    // device state
+    BatchMatDev* d_mats = nullptr;
+    BatchCandDev* d_cands = nullptr;
+    BatchRwMat* d_rwmats = nullptr;
+    int32_t* d_cand_mat = nullptr;
+    int4* d_tasks = nullptr;
+    int32_t ntasks = 0, solve_tasks = 0;
+    uint32_t* bitmaps = nullptr;
+    int64_t bitmap_words = 0;
+    int32_t* levs = nullptr;
+    int64_t lev_words = 0;
+    int32_t* cand_done = nullptr;
+    unsigned char* cand_bad = nullptr;
+    rwt_cand_stats* stats = nullptr;
+    int32_t* counts_q = nullptr;
+    int32_t* pat_ptr = nullptr;
+    int32_t* pat = nullptr;
+    int32_t* ovf = nullptr;
+    unsigned char* ovf_mark = nullptr;
+    int32_t* rwctrl = nullptr;
+    unsigned char* slab = nullptr;
+    int64_t slab_stride = 0;
+    int32_t slab_cap = 0;
+    void* scan_ws = nullptr;
+    Ctrl* ctrl = nullptr;
+    uint32_t* epoch = nullptr;
+    int32_t qcap = 0, pat_cap = 0;
+    int grid = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double create_ms = 0;
+};
+
+namespace {
+
+rwt_plan_opts batch_plan_opts(const rwt_batch_desc* d, const rwt_batch_matrix& m) {
+    rwt_plan_opts o;
+    memset(&o, 0, sizeof o);
+    o.algo = RWT_ALGO_SYNCFREE;   // block size (or one whole-matrix block) is tuned
+    o.kmax = m.k > 0 ? m.k : 1;
+    o.narrow_rows = -1;
+    o.watchdog_ms = d->watchdog_ms;
+    return o;
+}
+
+struct BatchLayout {
+    std::vector<size_t> plan_off, plan_bytes;
+    size_t mats, cands, candmat, rwmats, tasks, bitmaps, levs, done, bad, stats, counts, patptr, pat, ovf,
+        ovfmark, rwctrl, slab, scan, ctrl, epoch, total;
+    int64_t bitmap_words, lev_words, slab_stride;
+    int32_t qcap, pat_cap, slab_cap, ntasks_max;
+};
+
+rwt_status layout_batch(const rwt_batch_desc* d, BatchLayout* L) {
+    RWT_REQUIRE(d != nullptr && d->count >= 0 && d->num_cand >= 0, RWT_ERR_INVALID_ARG,
+                "bad batch descriptor");
+    RWT_REQUIRE(d->count == 0 || d->mats != nullptr, RWT_ERR_INVALID_ARG, "null matrix list");
+    RWT_REQUIRE(d->num_cand == 0 ||
+                    (d->h_cand_mat && d->d_cand_ptr && d->d_cand_rows && d->cand_rows_cap >= 0),
+                RWT_ERR_INVALID_ARG, "null candidate arrays");
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        off = (off + 255) & ~size_t(255);
+        size_t o = off;
+        off += bytes;
+        return o;
+    };
+    int32_t nmax = 1;
+    int64_t blocks_max = 0;
+    for (int32_t m = 0; m < d->count; ++m) {
+        const rwt_batch_matrix& M = d->mats[m];
+        RWT_REQUIRE(M.L.dt == RWT_F64, RWT_ERR_INVALID_ARG, "batched matrices must be FP64");
+        RWT_REQUIRE(M.k >= 0 && M.k <= 16, RWT_ERR_INVALID_ARG,
+                    "matrix %d: 0..16 right-hand sides per matrix in a batch", m);
+        RWT_REQUIRE(M.k == 0 || (M.B && M.X && M.ldb >= M.L.n && M.ldx >= M.L.n),
+                    RWT_ERR_INVALID_ARG, "matrix %d: bad right-hand sides", m);
+        rwt_plan_opts o = batch_plan_opts(d, M);
+        size_t pb = 0;
+        RWT_TRY(rwt_plan_ws(&M.L, &o, &pb));
+        L->plan_bytes.push_back(pb);
+        L->plan_off.push_back(take(pb));
+        nmax = std::max(nmax, M.L.n);
+        blocks_max += (M.L.n + 31) / 32;
+    }
+    for (int32_t c = 0; c < d->num_cand; ++c) {
+        int32_t m = d->h_cand_mat[c];
+        RWT_REQUIRE(m >= 0 && m < d->count, RWT_ERR_INVALID_ARG, "candidate %d: bad matrix", c);
+        RWT_REQUIRE(d->mats[m].L.n < (1 << 24), RWT_ERR_TOO_LARGE,
+                    "candidate analysis supports matrices below 2^24 rows");
+        RWT_REQUIRE(d->mats[m].L.n > 0, RWT_ERR_INVALID_ARG, "candidate %d: empty matrix", c);
+    }
+    L->bitmap_words = 0;
+    L->lev_words = 0;
+    for (int32_t c = 0; c < d->num_cand; ++c) {
+        const int32_t n = d->mats[d->h_cand_mat[c]].L.n;
+        L->bitmap_words += (n + 31) / 32 + 1;
+        L->lev_words += n;
+    }
+    L->qcap = d->cand_rows_cap;
+    int64_t pc = d->pattern_cap > 0 ? d->pattern_cap : (int64_t)64 * (L->qcap > 0 ? L->qcap : 1);
+    RWT_REQUIRE(pc < (int64_t(1) << 31), RWT_ERR_TOO_LARGE, "pattern capacity too large");
+    L->pat_cap = (int32_t)pc;
+    L->slab_cap = nmax + 1;
+    L->slab_stride = (int64_t)batch_rw_slab_stride(nmax);
+    int64_t ntask = 0;
+    for (int32_t m = 0; m < d->count; ++m)
+        if (d->mats[m].k > 0) ntask += (d->mats[m].L.n + 31) / 32;
+    for (int32_t c = 0; c < d->num_cand; ++c) ntask += (d->mats[d->h_cand_mat[c]].L.n + 31) / 32;
+    RWT_REQUIRE(ntask < (int64_t(1) << 31), RWT_ERR_TOO_LARGE, "too many tasks");
+    L->ntasks_max = (int32_t)ntask;
+    L->mats = take(sizeof(BatchMatDev) * std::max(1, d->count));
+    L->cands = take(sizeof(BatchCandDev) * std::max(1, d->num_cand));
+    L->candmat = take(sizeof(int32_t) * std::max(1, d->num_cand));
+    L->rwmats = take(sizeof(BatchRwMat) * std::max(1, d->count));
+    L->tasks = take(sizeof(int4) * std::max<int64_t>(1, ntask));
+    L->bitmaps = take(sizeof(uint32_t) * std::max<int64_t>(1, L->bitmap_words));
+    L->levs = take(sizeof(int32_t) * std::max<int64_t>(1, L->lev_words));
+    L->done = take(sizeof(int32_t) * std::max(1, d->num_cand));
+    L->bad = take(std::max(1, d->num_cand));
+    L->stats = take(sizeof(rwt_cand_stats) * std::max(1, d->num_cand));
+    L->counts = take(sizeof(int32_t) * ((size_t)L->qcap + 1));
+    L->patptr = take(sizeof(int32_t) * ((size_t)L->qcap + 1));
+    L->pat = take(sizeof(int32_t) * (size_t)L->pat_cap);
+    L->ovf = take(sizeof(int32_t) * std::max(1, L->qcap));
+    L->ovfmark = take(std::max(1, L->qcap));
+    L->rwctrl = take(sizeof(int32_t) * 8);
+    L->slab = take((size_t)NSLAB_B * (size_t)L->slab_stride);
+    L->scan = take(scan_ws((int64_t)L->qcap + 1));
+    L->ctrl = take(sizeof(Ctrl));
+    L->epoch = take(sizeof(uint32_t));
+    (void)blocks_max;
+    L->total = (off + 255) & ~size_t(255);
+    return RWT_OK;
+}
+
+template <typename P>
+P* at(void* base, size_t off) {
+    return reinterpret_cast<P*>(static_cast<char*>(base) + off);
+}
+
+rwt_status enqueue_run(rwt_batch* b, hipStream_t s) {
+    const rwt_batch_desc& d = b->desc;
+    const int32_t C = d.num_cand;
+    hipLaunchKernelGGL(k_batch_epoch, dim3(1), dim3(64), 0, s, b->epoch);
+    RWT_LAUNCHED();
+    const int64_t work = std::max<int64_t>(std::max<int64_t>(b->bitmap_words, b->lev_words / 4),
+                                           (int64_t)b->qcap + 1);
+    const unsigned gb = std::max<unsigned>(blocks_for(work, 256, 4096), (unsigned)std::min(d.count, 4096));
+    hipLaunchKernelGGL(k_batch_begin, dim3(gb), dim3(256), 0, s, b->d_mats, d.count, b->bitmaps,
+                       b->bitmap_words, b->levs, b->lev_words, b->epoch, b->cand_done, b->cand_bad, C,
+                       b->counts_q, b->ovf_mark, b->qcap, b->ctrl, b->rwctrl);
+    RWT_LAUNCHED();
+    if (C > 0) {
+        hipLaunchKernelGGL(k_batch_ptrcheck, dim3(blocks_for((size_t)C, 256, 1024)), dim3(256), 0, s,
+                           d.d_cand_ptr, C, b->qcap, b->rwctrl);
+        RWT_LAUNCHED();
+        hipLaunchKernelGGL(k_batch_bitmap, dim3(blocks_for((size_t)C * WAVE, 256, 4096)), dim3(256),
+                           0, s, b->d_mats, b->d_cands, C, d.d_cand_ptr, d.d_cand_rows,
+                           d.d_cand_targets, b->qcap, b->cand_bad, b->rwctrl);
+        RWT_LAUNCHED();
+        BatchRwArgs ra;
+        ra.mats = b->d_rwmats;
+        ra.cand_ptr = d.d_cand_ptr;
+        ra.cand_mat = nullptr;
+        ra.C = C;
+        ra.qcap = b->qcap;
+        ra.rows = d.d_cand_rows;
+        ra.targets = d.d_cand_targets;
+        ra.counts_q = b->counts_q;
+        ra.pat_ptr = b->pat_ptr;
+        ra.pat = b->pat;
+        ra.pat_cap = b->pat_cap;
+        ra.ovf = b->ovf;
+        ra.ovf_mark = b->ovf_mark;
+        ra.ctrl = b->rwctrl;
+        ra.cand_bad = b->cand_bad;
+        ra.slab = b->slab;
+        ra.slab_stride = b->slab_stride;
+        ra.slab_cap = b->slab_cap;
+        ra.nslab = NSLAB_B;
+        ra.cand_mat = b->d_cand_mat;
+        RWT_TRY(batch_rewrite_pass(ra, 1, s));
+        RWT_TRY(scan_exclusive(b->counts_q, b->pat_ptr, b->qcap, b->scan_ws, s));
+        RWT_TRY(batch_rewrite_pass(ra, 2, s));
+    }
+    BatchKArgs ka;
+    ka.mats = b->d_mats;
+    ka.cands = b->d_cands;
+    ka.tasks = b->d_tasks;
+    ka.ntasks = b->ntasks;
+    ka.C = C;
+    ka.cand_ptr = d.d_cand_ptr;
+    ka.rows = d.d_cand_rows;
+    ka.counts_q = b->counts_q;
+    ka.pat_ptr = b->pat_ptr;
+    ka.pat = b->pat;
+    ka.cand_bad = b->cand_bad;
+    ka.cand_done = b->cand_done;
+    ka.stats = b->stats;
+    ka.ctrl = b->ctrl;
+    ka.epoch = b->epoch;
+    ka.ticks = watchdog_ticks(d.watchdog_ms);
+    if (b->ntasks > 0) {
+        hipLaunchKernelGGL(k_batch_main, dim3(b->grid), dim3(BT_THREADS), BT_LDS, s, ka);
+        RWT_LAUNCHED();
+    }
+    return RWT_OK;
+}
+
+}  // namespace
+
+extern "C" rwt_status rwt_batch_ws(const rwt_batch_desc* desc, size_t* h_bytes) {
+    RWT_REQUIRE(h_bytes != nullptr, RWT_ERR_INVALID_ARG, "h_bytes is NULL");
+    BatchLayout L;
+    RWT_TRY(layout_batch(desc, &L));
+    *h_bytes = L.total;
+    return RWT_OK;
+}
+
+extern "C" rwt_status rwt_batch_create(const rwt_batch_desc* desc, void* d_ws, size_t ws_bytes,
+                                       rwt_batch** out, rwt_stream_t stream) {
+    RWT_REQUIRE(out != nullptr, RWT_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    const auto t0 = std::chrono::steady_clock::now();
+    BatchLayout L;
+    RWT_TRY(layout_batch(desc, &L));
+    RWT_REQUIRE(d_ws != nullptr && ws_bytes >= L.total, RWT_ERR_BUFFER_TOO_SMALL,
+                "batch workspace must hold %zu bytes", L.total);
+    hipStream_t s = hs(stream);
+    rwt_batch* b = new (std::nothrow) rwt_batch();
+    RWT_REQUIRE(b != nullptr, RWT_ERR_INVALID_ARG, "out of host memory");
+    auto fail = [&](rwt_status e) {
+        for (rwt_plan* p : b->plans) rwt_plan_destroy(p);
+        delete b;
+        return e;
+    };
+    b->desc = *desc;
+    b->mats.assign(desc->mats, desc->mats + desc->count);
+    b->cand_mat.assign(desc->h_cand_mat, desc->h_cand_mat + desc->num_cand);
+    b->desc.mats = b->mats.data();
+    b->desc.h_cand_mat = b->cand_mat.data();
+    // per-matrix plans: analysis, schedule, autotuned block size
+    std::vector<BatchMatDev> hm(desc->count);
+    std::vector<BatchRwMat> hr(desc->count);
+    for (int32_t m = 0; m < desc->count; ++m) {
+        const rwt_batch_matrix& M = b->mats[m];
+        rwt_plan_opts o = batch_plan_opts(desc, M);
+        rwt_plan* p = nullptr;
+        rwt_status st = rwt_plan_create(&M.L, &o, at<char>(d_ws, L.plan_off[m]), L.plan_bytes[m],
+                                        &p, stream);
+        if (st != RWT_OK) return fail(st);
+        b->plans.push_back(p);
+        BatchMatDev& d = hm[m];
+        memset(&d, 0, sizeof d);
+        d.n = M.L.n;
+        d.R = p->R;
+        d.lanes = p->lanes;
+        d.nblocks = p->nblocks;
+        d.k = M.k;
+        d.ldb = M.ldb;
+        d.ldx = M.ldx;
+        d.rowptr = M.L.rowptr;
+        d.colidx = M.L.colidx;
+        d.level = p->level;
+        d.vals = static_cast<const double*>(M.L.vals);
+        d.desc = p->desc_f;
+        d.step_pos = p->step_pos;
+        d.blk_step = p->blk_step;
+        d.B = static_cast<const double*>(M.B);
+        d.X = static_cast<double*>(M.X);
+        hr[m].n = M.L.n;
+        hr[m].pad = 0;
+        hr[m].rowptr = M.L.rowptr;
+        hr[m].colidx = M.L.colidx;
+        hr[m].level = p->level;
+    }
+    b->d_mats = at<BatchMatDev>(d_ws, L.mats);
+    b->d_cands = at<BatchCandDev>(d_ws, L.cands);
+    b->d_rwmats = at<BatchRwMat>(d_ws, L.rwmats);
+    b->d_cand_mat = at<int32_t>(d_ws, L.candmat);
+    b->d_tasks = at<int4>(d_ws, L.tasks);
+    b->bitmaps = at<uint32_t>(d_ws, L.bitmaps);
+    b->bitmap_words = L.bitmap_words;
+    b->levs = at<int32_t>(d_ws, L.levs);
+    b->lev_words = L.lev_words;
+    b->cand_done = at<int32_t>(d_ws, L.done);
+    b->cand_bad = at<unsigned char>(d_ws, L.bad);
+    b->stats = at<rwt_cand_stats>(d_ws, L.stats);
+    b->counts_q = at<int32_t>(d_ws, L.counts);
+    b->pat_ptr = at<int32_t>(d_ws, L.patptr);
+    b->pat = at<int32_t>(d_ws, L.pat);
+    b->ovf = at<int32_t>(d_ws, L.ovf);
+    b->ovf_mark = at<unsigned char>(d_ws, L.ovfmark);
+    b->rwctrl = at<int32_t>(d_ws, L.rwctrl);
+    b->slab = at<unsigned char>(d_ws, L.slab);
+    b->slab_stride = L.slab_stride;
+    b->slab_cap = L.slab_cap;
+    b->scan_ws = at<char>(d_ws, L.scan);
+    b->ctrl = at<Ctrl>(d_ws, L.ctrl);
+    b->epoch = at<uint32_t>(d_ws, L.epoch);
+    b->qcap = L.qcap;
+    b->pat_cap = L.pat_cap;
+    // candidates: matrix, bitmap and level array slices
+    std::vector<BatchCandDev> hc(desc->num_cand);
+    {
+        int64_t bw = 0, lw = 0;
+        for (int32_t c = 0; c < desc->num_cand; ++c) {
+            const int32_t n = b->mats[b->cand_mat[c]].L.n;
+            hc[c].m = b->cand_mat[c];
+            hc[c].pad = 0;
+            hc[c].bitmap = b->bitmaps + bw;
+            hc[c].lev = b->levs + lw;
+            bw += (n + 31) / 32 + 1;
+            lw += n;
+        }
+    }
+    // task table: chains in row order, interleaved by relative position
+    struct T {
+        double key;
+        int4 t;
+    };
+    std::vector<T> tv;
+    for (int32_t m = 0; m < desc->count; ++m) {
+        if (b->mats[m].k == 0) continue;
+        const int32_t nb = hm[m].nblocks;
+        for (int32_t k = 0; k < nb; ++k) tv.push_back({(k + 0.5) / nb, make_int4(0, m, k, 0)});
+    }
+    b->solve_tasks = (int32_t)tv.size();
+    for (int32_t c = 0; c < desc->num_cand; ++c) {
+        const int32_t nb = hm[hc[c].m].nblocks;
+        for (int32_t k = 0; k < nb; ++k) tv.push_back({(k + 0.5) / nb, make_int4(1, c, k, 0)});
+    }
+    std::stable_sort(tv.begin(), tv.end(), [](const T& x, const T& y) { return x.key < y.key; });
+    std::vector<int4> tasks(tv.size());
+    for (size_t i = 0; i < tv.size(); ++i) tasks[i] = tv[i].t;
+    b->ntasks = (int32_t)tasks.size();
+    if (hipMemcpyAsync(b->d_mats, hm.data(), sizeof(BatchMatDev) * hm.size(), hipMemcpyHostToDevice,
+                       s) != hipSuccess ||
+        hipMemcpyAsync(b->d_rwmats, hr.data(), sizeof(BatchRwMat) * hr.size(),
+                       hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(b->d_cands, hc.data(), sizeof(BatchCandDev) * hc.size(),
+                       hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(b->d_tasks, tasks.data(), sizeof(int4) * tasks.size(), hipMemcpyHostToDevice,
+                       s) != hipSuccess ||
+        (desc->num_cand > 0 &&
+         hipMemcpyAsync(b->d_cand_mat, b->cand_mat.data(), sizeof(int32_t) * b->cand_mat.size(),
+                        hipMemcpyHostToDevice, s) != hipSuccess)) {
+        set_hip_error(hipGetLastError(), "batch table upload");
+        return fail(RWT_ERR_HIP);
+    }
+    rwt_status st;
+    if ((st = fill_u8(b->levs, (int64_t)sizeof(int32_t) * std::max<int64_t>(1, b->lev_words), s)) !=
+            RWT_OK ||
+        (st = fill_u8(b->epoch, sizeof(uint32_t), s)) != RWT_OK)
+        return fail(st);
+    DeviceInfo di;
+    if ((st = device_info(&di)) != RWT_OK) return fail(st);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_batch_main, BT_THREADS,
+                                                      BT_LDS) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    b->grid = di.cus * std::min(per_cu, 8);
+    if (hipStreamSynchronize(s) != hipSuccess) {
+        set_hip_error(hipGetLastError(), "batch creation");
+        return fail(RWT_ERR_HIP);
+    }
+    b->create_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = b;
+    return RWT_OK;
+}
+
+extern "C" rwt_status rwt_batch_run(rwt_batch* b, rwt_stream_t stream) {
+    RWT_REQUIRE(b != nullptr, RWT_ERR_INVALID_ARG, "null batch");
+    return enqueue_run(b, hs(stream));
+}
+
+extern "C" rwt_status rwt_batch_capture(rwt_batch* b, rwt_stream_t stream) {
+    RWT_REQUIRE(b != nullptr, RWT_ERR_INVALID_ARG, "null batch");
+    RWT_REQUIRE(stream != nullptr, RWT_ERR_INVALID_ARG, "capture needs a non-default stream");
+    hipStream_t s = hs(stream);
+    if (b->exec) {
+        hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    RWT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    rwt_status st = enqueue_run(b, s);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (st != RWT_OK) {
+        if (g) hipGraphDestroy(g);
+        return st;
+    }
+    RWT_HIP(e);
+    b->graph = g;
+    RWT_HIP(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+    return RWT_OK;
+}
+
+extern "C" rwt_status rwt_batch_launch(rwt_batch* b, rwt_stream_t stream) {
+    RWT_REQUIRE(b != nullptr && b->exec != nullptr, RWT_ERR_INVALID_ARG,
+                "no captured graph: call rwt_batch_capture first");
+    RWT_HIP(hipGraphLaunch(b->exec, hs(stream)));
+    return RWT_OK;
+}
+
+extern "C" rwt_status rwt_batch_stats(const rwt_batch* b, rwt_cand_stats* h_out,
+                                      rwt_stream_t stream) {
+    RWT_REQUIRE(b != nullptr, RWT_ERR_INVALID_ARG, "null batch");
+    hipStream_t s = hs(stream);
+    Ctrl hc;
+    int32_t rc[8];
+    RWT_HIP(hipMemcpyAsync(&hc, b->ctrl, sizeof hc, hipMemcpyDeviceToHost, s));
+    RWT_HIP(hipMemcpyAsync(rc, b->rwctrl, sizeof rc, hipMemcpyDeviceToHost, s));
+    if (h_out && b->desc.num_cand > 0)
+        RWT_HIP(hipMemcpyAsync(h_out, b->stats, sizeof(rwt_cand_stats) * b->desc.num_cand,
+                               hipMemcpyDeviceToHost, s));
+    RWT_HIP(hipStreamSynchronize(s));
+    if (hc.err != 0) {
+        set_error("a device wait expired in the batch (watchdog)");
+        return RWT_ERR_DEADLOCK;
+    }
+    if (rc[3] != 0 || rc[4] != 0) {
+        set_error("rewritten-row patterns exceeded the batch capacity");
+        return RWT_ERR_TOO_LARGE;
+    }
+    if (rc[5] != 0) {
+        set_error("some candidate row lists were rejected (unsorted, out of range or over capacity)");
+        return RWT_ERR_BAD_ROWSET;
+    }
+    return RWT_OK;
+}
+
+extern "C" rwt_status rwt_batch_get_info(const rwt_batch* b, rwt_batch_info* h) {
+    RWT_REQUIRE(b != nullptr && h != nullptr, RWT_ERR_INVALID_ARG, "null argument");
+    h->tasks = b->ntasks;
+    h->solve_tasks = b->solve_tasks;
+    h->grid = b->grid;
+    h->captured = b->exec != nullptr;
+    h->create_ms = b->create_ms;
+    return RWT_OK;
+}
+
+extern "C" rwt_status rwt_batch_plan(const rwt_batch* b, int32_t m, const rwt_plan** out) {
+    RWT_REQUIRE(b != nullptr && out != nullptr && m >= 0 && m < (int32_t)b->plans.size(),
+                RWT_ERR_INVALID_ARG, "bad matrix index");
+    *out = b->plans[m];
+    return RWT_OK;
+}
+
+extern "C" rwt_status rwt_batch_destroy(rwt_batch* b) {
+    if (!b) return RWT_OK;
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    for (rwt_plan* p : b->plans) rwt_plan_destroy(p);
+    delete b;
+    return RWT_OK;
+}

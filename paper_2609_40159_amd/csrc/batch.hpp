@@ -1,0 +1,44 @@
+// Batched analysis + solve internals.
+#pragma once
+
+#include "common.hpp"
+
+namespace rwt {
+
+// One matrix as seen by the batched symbolic rewrite.
+struct BatchRwMat {
+    int32_t n;
+    int32_t pad;
+    const int32_t* rowptr;
+    const int32_t* colidx;
+    const int32_t* level;
+};
+
+// Host description of a batched symbolic pass over candidate rows.
+struct BatchRwArgs {
+    const BatchRwMat* mats;     // device
+    const int32_t* cand_ptr;    // device, C+1
+    const int32_t* cand_mat;    // device, C
+    int32_t C;
+    int32_t qcap;               // capacity of the candidate row list
+    const int32_t* rows;        // device, candidate rows (concatenated)
+    const int32_t* targets;     // device or NULL (level - 1)
+    int32_t* counts_q;          // device, qcap (+1)
+    const int32_t* pat_ptr;     // device, qcap + 1
+    int32_t* pat;               // device, pat_cap
+    int32_t pat_cap;
+    int32_t* ovf;               // device, qcap
+    unsigned char* ovf_mark;    // device, qcap
+    int32_t* ctrl;              // device, 8 ints
+    unsigned char* cand_bad;    // device, C: candidate row list rejected
+    unsigned char* slab;        // device, nslab * slab_stride
+    int64_t slab_stride;
+    int32_t slab_cap;
+    int32_t nslab;
+};
+
+size_t batch_rw_slab_stride(int32_t nmax);
+// qmode 1: new row lengths; qmode 2: new patterns (needs pat_ptr)
+rwt_status batch_rewrite_pass(const BatchRwArgs& h, int qmode, hipStream_t s);
+
+}  // namespace rwt

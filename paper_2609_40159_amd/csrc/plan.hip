@@ -4,8 +4,8 @@
 #include <new>
 #include <vector>
 
+#include "plan.hpp"
 #include "prim.hpp"
-#include "solve.hpp"
 
 namespace rwt {
 
@@ -104,33 +104,7 @@ rwt_status copy_block(const void* src, int64_t lds, void* dst, int64_t ldd, int3
 
 using namespace rwt;
 
-struct rwt_plan {
-    rwt_csr L;
-    rwt_plan_opts opts;
-    rwt_level_stats stats;
-    int32_t D = 0;
-    Ctrl* ctrl = nullptr;
-    int32_t* level = nullptr;
-    int32_t* perm = nullptr;
-    int32_t* level_ptr = nullptr;
-    Csc csc;
-    int32_t* seg = nullptr;
-    int32_t nseg = 0;
-    int32_t R = 0;
-    int32_t nblocks = 0;
-    int32_t* bperm = nullptr;
-    int32_t* step_pos = nullptr;
-    int32_t* blk_step = nullptr;
-    int4* desc_f = nullptr;   // forward row descriptors in block order
-    int4* desc_t = nullptr;   // transposed row descriptors in block order
-    void* xtmp = nullptr;     // n * kmax values
-    void* xtmp2 = nullptr;    // n values (autotuning)
-    Algo fwd = Algo::SyncFree;
-    Algo bwd = Algo::SyncFree;
-    int32_t lanes = 4;
-    int cus = 256;
-    double tuned_level = 0, tuned_sf = 0;
-};
+
 
 namespace {
 
@@ -146,17 +120,21 @@ bool block_rows_ok(int R, int kmax, rwt_dtype dt) {
     return R >= R_MIN && syncfree_lds_bytes(R, kmax, dt) <= SF_LDS_BUDGET;
 }
 
-std::vector<int> block_candidates(const rwt_plan_opts& o, rwt_dtype dt) {
+std::vector<int> block_candidates(const rwt_plan_opts& o, rwt_dtype dt, int32_t n) {
     const int kmax = o.kmax > 0 ? o.kmax : 1;
     std::vector<int> out;
+    // the whole matrix in one workgroup, level after level with workgroup
+    // barriers, when its x values fit in LDS
+    const bool whole = n > 0 && n <= (1 << 20) && syncfree_lds_bytes(n, kmax, dt) <= SF_LDS_BUDGET;
     if (o.block_rows > 0) {
         int R = o.block_rows;
         while (R > R_MIN && !block_rows_ok(R, kmax, dt)) R /= 2;
         out.push_back(R < R_MIN ? R_MIN : R);
         return out;
     }
+    if (whole) out.push_back(n);
     for (int R : {4096, 2048, 1024, 512, 256, 128, 64, 32})
-        if (block_rows_ok(R, kmax, dt)) out.push_back(R);
+        if (R < n && block_rows_ok(R, kmax, dt)) out.push_back(R);
     if (out.empty()) out.push_back(R_MIN);
     return out;
 }
@@ -324,6 +302,13 @@ double time_solve(rwt_plan* p, Algo algo, hipStream_t s, int reps) {
 
 }  // namespace
 
+namespace rwt {
+rwt_status plan_solve(const rwt_plan* p, bool transposed, const void* B, int32_t k, int64_t ldb,
+                      void* X, int64_t ldx, hipStream_t s) {
+    return run_solve(p, transposed, transposed ? p->bwd : p->fwd, B, k, ldb, X, ldx, s);
+}
+}  // namespace rwt
+
 extern "C" rwt_status rwt_plan_ws(const rwt_csr* L, const rwt_plan_opts* opts, size_t* h_bytes) {
     RWT_TRY(check_opts(L, opts));
     RWT_REQUIRE(h_bytes != nullptr, RWT_ERR_INVALID_ARG, "h_bytes is NULL");
@@ -339,7 +324,7 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
     RWT_REQUIRE(out != nullptr, RWT_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     const int kmax = opts->kmax > 0 ? opts->kmax : 1;
-    const std::vector<int> cands = block_candidates(*opts, L->dt);
+    const std::vector<int> cands = block_candidates(*opts, L->dt, L->n);
     int R = cands.front();
     PlanPtrs pp;
     const size_t need = carve_plan(nullptr, *L, kmax, &pp);

@@ -22,6 +22,7 @@
 // Rows whose accumulator outgrows the LDS capacity are redone by a
 // fallback kernel whose buffers are in the workspace.
 #include "analyze.hpp"
+#include "batch.hpp"
 #include "prim.hpp"
 
 namespace rwt {
@@ -78,6 +79,13 @@ struct RwArgs {
     unsigned char* slab;
     int64_t slab_stride;
     int32_t slab_cap;
+    // outputs indexed by set position (batched candidate analysis)
+    int32_t* counts_q;
+    const int32_t* pat_ptr;
+    int32_t* pat_out;
+    int32_t pat_cap;
+    unsigned char* cand_bad_out;   // batched: candidate rejected when its pattern does not fit
+    int32_t cand_index;
 };
 
 // Order this wave's earlier buffer writes before its later reads (the
@@ -110,7 +118,10 @@ __device__ __forceinline__ T sub_rn(T a, T b) {
 }
 
 // Rewrite one row with one wave.  Returns false on capacity overflow.
-template <typename T, bool NUMERIC>
+// QMODE 0: symbolic or numeric rewrite of one matrix; QMODE 1: only the new
+// row length, stored at counts_q[q]; QMODE 2: only the new pattern, stored
+// at pat_out[pat_ptr[q]...].
+template <typename T, bool NUMERIC, int QMODE = 0>
 __device__ bool rewrite_row(const RwArgs& a, int32_t q, const Bufs& bf) {
     const int lane = lane_id();
     const int32_t r = a.set_rows[q];
@@ -243,6 +254,18 @@ __device__ bool rewrite_row(const RwArgs& a, int32_t q, const Bufs& bf) {
             a.colidx_out[ob + p] = acol[p];
             vo[ob + p] = aval[p];
         }
+    } else if (QMODE == 1) {
+        if (lane == 0) a.counts_q[q] = alen;
+    } else if (QMODE == 2) {
+        const int32_t ob = a.pat_ptr[q];
+        if (a.pat_ptr[q + 1] - ob != alen || (int64_t)ob + alen > a.pat_cap) {
+            if (lane == 0) {
+                atomicExch(&a.ctrl[4], 1);
+                if (a.cand_bad_out) a.cand_bad_out[a.cand_index] = 1;
+            }
+            return true;
+        }
+        for (int32_t p = lane; p < alen; p += WAVE) a.pat_out[ob + p] = acol[p];
     } else if (lane == 0) {
         a.counts[r] = alen;
         a.csub[q] = nsub;
@@ -475,6 +498,207 @@ rwt_status launch_rows(const RwArgs& a, bool numeric, hipStream_t s) {
     return RWT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Batched candidate rows: many matrices, many candidate row sets.  Set
+// position q belongs to candidate c = the last c with cand_ptr[c] <= q, whose
+// matrix is cand_mat[c].
+// ---------------------------------------------------------------------------
+struct BatchRwArgsDev {
+    const BatchRwMat* mats;
+    const int32_t* cand_ptr;
+    const int32_t* cand_mat;
+    int32_t C;
+    const int32_t* rows;
+    const int32_t* targets;
+    int32_t qcap;
+    int32_t* counts_q;
+    const int32_t* pat_ptr;
+    int32_t* pat;
+    int32_t pat_cap;
+    int32_t* ovf;
+    unsigned char* ovf_mark;
+    int32_t* ctrl;   // [0] overflow count, [3] too large, [4] capacity error
+    unsigned char* cand_bad;
+    unsigned char* slab;
+    int64_t slab_stride;
+    int32_t slab_cap;
+};
+
+__device__ inline int32_t cand_of(const int32_t* cand_ptr, int32_t C, int32_t q) {
+    int32_t lo = 0, hi = C - 1;   // last c with cand_ptr[c] <= q
+    while (lo < hi) {
+        int32_t mid = (lo + hi + 1) >> 1;
+        if (cand_ptr[mid] <= q) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ inline RwArgs batch_row_args(const BatchRwArgsDev& ba, int32_t q) {
+    const int32_t c = cand_of(ba.cand_ptr, ba.C, q);
+    const BatchRwMat& M = ba.mats[ba.cand_mat[c]];
+    RwArgs a;
+    memset(&a, 0, sizeof a);
+    a.cand_bad_out = ba.cand_bad;
+    a.cand_index = c;
+    a.n = M.n;
+    a.rowptr = M.rowptr;
+    a.colidx = M.colidx;
+    a.level = M.level;
+    a.set_rows = ba.rows;
+    a.targets = ba.targets;
+    a.ctrl = ba.ctrl;
+    a.counts_q = ba.counts_q;
+    a.pat_ptr = ba.pat_ptr;
+    a.pat_out = ba.pat;
+    a.pat_cap = ba.pat_cap;
+    return a;
+}
+
+// rows left unchanged keep their own pattern
+template <int QMODE>
+__device__ bool batch_noop_row(const BatchRwArgsDev& ba, const RwArgs& a, int32_t q) {
+    const int32_t r = a.set_rows[q];
+    const int32_t lv = a.level[r];
+    const int32_t t = a.targets ? a.targets[q] : lv - 1;
+    if (!(lv == 0 || t >= lv)) return false;
+    const int32_t rb = a.rowptr[r], len = a.rowptr[r + 1] - rb;
+    if (QMODE == 1) {
+        if (lane_id() == 0) ba.counts_q[q] = len;
+    } else {
+        const int32_t ob = ba.pat_ptr[q];
+        if (ba.pat_ptr[q + 1] - ob != len || (int64_t)ob + len > ba.pat_cap) {
+            if (lane_id() == 0) {
+                atomicExch(&ba.ctrl[4], 1);
+                ba.cand_bad[cand_of(ba.cand_ptr, ba.C, q)] = 1;
+            }
+            return true;
+        }
+        for (int32_t p = lane_id(); p < len; p += WAVE) ba.pat[ob + p] = a.colidx[rb + p];
+    }
+    return true;
+}
+
+template <int QMODE>
+__global__ void __launch_bounds__(RW_WAVES * WAVE) k_batch_rw_lds(BatchRwArgsDev ba) {
+    constexpr int S = 8;
+    constexpr int PER_WAVE = 2 * RW_CAP * (4 + S + 1) + RW_CAPB * (4 + S) + (RW_CAPB + 1) * 4 +
+                             RW_CAPB + 64;
+    __shared__ __align__(16) unsigned char s_buf[RW_WAVES * PER_WAVE];
+    const int w = threadIdx.x / WAVE;
+    unsigned char* base = s_buf + w * PER_WAVE;
+    Bufs bf;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        unsigned char* p = base + off;
+        off += (bytes + 7) & ~size_t(7);
+        return p;
+    };
+    for (int i = 0; i < 2; ++i) {
+        bf.acol[i] = reinterpret_cast<int32_t*>(take(RW_CAP * 4));
+        bf.aval[i] = reinterpret_cast<double*>(take(RW_CAP * S));
+        bf.aelig[i] = take(RW_CAP);
+    }
+    bf.bcol = reinterpret_cast<int32_t*>(take(RW_CAPB * 4));
+    bf.bval = reinterpret_cast<double*>(take(RW_CAPB * S));
+    bf.nd = reinterpret_cast<int32_t*>(take((RW_CAPB + 1) * 4));
+    bf.bdup = take(RW_CAPB);
+    bf.cap = RW_CAP;
+    bf.capb = RW_CAPB;
+    const int32_t total = min(ba.cand_ptr[ba.C], ba.qcap);
+    const int64_t wave = (int64_t)blockIdx.x * RW_WAVES + w;
+    const int64_t nw = (int64_t)gridDim.x * RW_WAVES;
+    for (int64_t q = wave; q < total; q += nw) {
+        if (ba.cand_bad[cand_of(ba.cand_ptr, ba.C, (int32_t)q)]) {
+            if (QMODE == 1 && lane_id() == 0) ba.counts_q[q] = 0;
+            continue;
+        }
+        const RwArgs a = batch_row_args(ba, (int32_t)q);
+        if (batch_noop_row<QMODE>(ba, a, (int32_t)q)) continue;
+        if (QMODE == 2 && ba.ovf_mark[q]) continue;
+        const bool ok = rewrite_row<double, false, QMODE>(a, (int32_t)q, bf);
+        if (!ok && QMODE == 1 && lane_id() == 0) {
+            int slot = atomicAdd(&ba.ctrl[0], 1);
+            ba.ovf[slot] = (int32_t)q;
+            ba.ovf_mark[q] = 1;
+        }
+    }
+}
+
+template <int QMODE>
+__global__ void __launch_bounds__(WAVE) k_batch_rw_slab(BatchRwArgsDev ba) {
+    const int32_t cnt = ba.ctrl[0];
+    const int S = 8;
+    for (int32_t s = blockIdx.x; s < cnt; s += gridDim.x) {
+        unsigned char* base = ba.slab + (int64_t)blockIdx.x * ba.slab_stride;
+        const int64_t cap = ba.slab_cap;
+        int64_t off = 0;
+        auto take = [&](int64_t bytes) {
+            unsigned char* p = base + off;
+            off += (bytes + 7) & ~int64_t(7);
+            return p;
+        };
+        Bufs bf;
+        for (int i = 0; i < 2; ++i) {
+            bf.acol[i] = reinterpret_cast<int32_t*>(take(cap * 4));
+            bf.aval[i] = reinterpret_cast<double*>(take(cap * S));
+            bf.aelig[i] = take(cap);
+        }
+        bf.bcol = reinterpret_cast<int32_t*>(take(cap * 4));
+        bf.bval = reinterpret_cast<double*>(take(cap * S));
+        bf.nd = reinterpret_cast<int32_t*>(take((cap + 1) * 4));
+        bf.bdup = take(cap);
+        bf.cap = (int32_t)cap;
+        bf.capb = (int32_t)cap;
+        const int32_t q = ba.ovf[s];
+        const RwArgs a = batch_row_args(ba, q);
+        if (!rewrite_row<double, false, QMODE>(a, q, bf) && lane_id() == 0) atomicExch(&ba.ctrl[3], 1);
+    }
+}
+
+}  // namespace
+
+size_t batch_rw_slab_stride(int32_t nmax) {
+    const int64_t cap = (int64_t)nmax + 1;
+    return (size_t)((2 * cap * (4 + 8 + 1) + cap * (4 + 8) + (cap + 1) * 4 + cap + 256 + 255) &
+                    ~int64_t(255));
+}
+
+rwt_status batch_rewrite_pass(const BatchRwArgs& h, int qmode, hipStream_t s) {
+    BatchRwArgsDev ba;
+    ba.mats = h.mats;
+    ba.cand_ptr = h.cand_ptr;
+    ba.cand_mat = h.cand_mat;
+    ba.C = h.C;
+    ba.rows = h.rows;
+    ba.targets = h.targets;
+    ba.counts_q = h.counts_q;
+    ba.pat_ptr = h.pat_ptr;
+    ba.pat = h.pat;
+    ba.pat_cap = h.pat_cap;
+    ba.ovf = h.ovf;
+    ba.ovf_mark = h.ovf_mark;
+    ba.ctrl = h.ctrl;
+    ba.cand_bad = h.cand_bad;
+    ba.qcap = h.qcap;
+    ba.slab = h.slab;
+    ba.slab_stride = h.slab_stride;
+    ba.slab_cap = h.slab_cap;
+    const unsigned g = blocks_for((size_t)(h.qcap > 0 ? h.qcap : 1), RW_WAVES, 8192);
+    if (qmode == 1) {
+        hipLaunchKernelGGL(k_batch_rw_lds<1>, dim3(g), dim3(RW_WAVES * WAVE), 0, s, ba);
+        RWT_LAUNCHED();
+        hipLaunchKernelGGL(k_batch_rw_slab<1>, dim3(h.nslab), dim3(WAVE), 0, s, ba);
+    } else {
+        hipLaunchKernelGGL(k_batch_rw_lds<2>, dim3(g), dim3(RW_WAVES * WAVE), 0, s, ba);
+        RWT_LAUNCHED();
+        hipLaunchKernelGGL(k_batch_rw_slab<2>, dim3(h.nslab), dim3(WAVE), 0, s, ba);
+    }
+    RWT_LAUNCHED();
+    return RWT_OK;
+}
+
+namespace {
 }  // namespace
 }  // namespace rwt
 

@@ -24,6 +24,8 @@
 // strided partial dot products, then a butterfly reduction in the group.
 #include "solve.hpp"
 
+#include "sf_block.hpp"
+
 #include "prim.hpp"
 
 namespace rwt {
@@ -187,49 +189,26 @@ __global__ void __launch_bounds__(SV_THREADS) k_solve_level(SolveArgs a) {
     }
 }
 
-// Workgroup barrier that orders LDS only: global stores stay in flight
-// (other workgroups read them through the readiness wait).
-__device__ __forceinline__ void lds_barrier() {
-    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-}
-
-// Row of the current level step for one lane group, with its data loaded
-// ahead of time (software pipeline: descriptors two steps ahead, entries
-// one step ahead), so that only the x values wait on the dependency chain.
-struct SfDesc {
-    int32_t i, pb, pe, dpos;
-    bool act;
-};
-template <typename T>
-struct SfEnt {
-    int32_t j;   // first entry of this lane (-1: none)
-    T v;
-    T diag;
-};
-
 template <typename T, bool TRANS, int KT>
 __global__ void __launch_bounds__(SV_THREADS) k_solve_sf(SolveArgs a) {
     extern __shared__ __align__(16) unsigned char s_raw[];
-    const int k = a.k;
-    T* xs = reinterpret_cast<T*>(s_raw);
-    int32_t* sp = reinterpret_cast<int32_t*>(s_raw + ((a.block_rows * k * (int)sizeof(T) + 15) & ~15));
     __shared__ int32_t s_blk;
-    const T* vals = static_cast<const T*>(a.vals);
-    const T* Bg = static_cast<const T*>(a.B);
-    T* X = static_cast<T*>(a.X);
-    const int32_t* idx = TRANS ? a.crow : a.colidx;
-    const int G = a.lanes;
-    const int gl = threadIdx.x & (G - 1);
-    const int lane = lane_id();
-    const int groups_per_wave = WAVE / G;
-    const int wave_in_block = threadIdx.x / WAVE;
-    const int waves_per_block = blockDim.x / WAVE;
-    const int32_t ngroups = waves_per_block * groups_per_wave;
-    const int32_t gi = wave_in_block * groups_per_wave + lane / G;
-    int32_t* err = &a.ctrl->err;
-
-    auto value_at = [&](int32_t p) -> T { return TRANS ? vals[a.cmap[p]] : vals[p]; };
-
+    SfBlockArgs b;
+    b.k = a.k;
+    b.lanes = a.lanes;
+    b.ldb = a.ldb;
+    b.ldx = a.ldx;
+    b.colidx = a.colidx;
+    b.crow = a.crow;
+    b.cmap = a.cmap;
+    b.vals = a.vals;
+    b.desc = a.desc;
+    b.step_pos = a.step_pos;
+    b.B = a.B;
+    b.X = a.X;
+    b.err = &a.ctrl->err;
+    b.ticks = a.ticks;
+    b.lds_rows = a.block_rows;
     for (;;) {
         if (threadIdx.x == 0) s_blk = (int32_t)fetch_add(&a.ctrl->ticket, 1u);
         __syncthreads();
@@ -237,195 +216,12 @@ __global__ void __launch_bounds__(SV_THREADS) k_solve_sf(SolveArgs a) {
         __syncthreads();
         if (t >= a.nblocks) break;
         const int32_t blk = TRANS ? a.nblocks - 1 - t : t;
-        const int32_t r0 = blk * a.block_rows;
-        const int32_t r1 = min(a.n, r0 + a.block_rows);
-        const int32_t sb = a.blk_step[blk], ns = a.blk_step[blk + 1] - sb;
-        for (int32_t u = threadIdx.x; u <= ns; u += blockDim.x) sp[u] = a.step_pos[sb + u] - r0;
-        __syncthreads();
-
-        // Loads of future steps are issued by every lane unconditionally (an
-        // inactive lane reads a valid element and discards it): a load under a
-        // branch would let the compiler's wait counting assume nothing younger
-        // than the x loads is in flight and wait for everything.
-        auto load_desc = [&](int32_t u) -> SfDesc {
-            SfDesc d;
-            const bool has = u < ns;
-            const int32_t st = TRANS ? ns - 1 - u : u;
-            const int32_t st_c = has ? st : 0;
-            const int32_t pos = sp[st_c] + gi;
-            d.act = has && pos < sp[st_c + 1];
-            const int4 v = a.desc[d.act ? r0 + pos : 0];
-            d.i = d.act ? v.x : r0;
-            d.pb = d.act ? v.y : 0;
-            d.pe = d.act ? v.z : 0;
-            d.dpos = d.act ? v.w : 0;
-            return d;
-        };
-        auto load_ent = [&](const SfDesc& d) -> SfEnt<T> {
-            SfEnt<T> e;
-            const int32_t p = d.pb + gl;
-            const bool ok = d.act && p < d.pe;
-            const int32_t pc = ok ? p : 0;
-            const int32_t jj = idx[pc];
-            int32_t vp = pc;
-            if (TRANS) {
-                const int32_t m = a.cmap[pc];
-                vp = ok ? m : 0;
-            }
-            const T vv = vals[vp];
-            const T dd = vals[d.act ? d.dpos : 0];
-            e.j = ok ? jj : -1;
-            e.v = ok ? vv : T(0);
-            e.diag = d.act ? dd : T(1);
-            return e;
-        };
-        // A row solved without pipelining (rows beyond one per group, right-hand
-        // sides beyond the first KT): all lanes of the wave call this together.
-        auto solve_inline = [&](const SfDesc& d, const SfEnt<T>& e, int q_begin) {
-            for (int q0 = q_begin; q0 < k; q0 += KT) {
-                T acc[KT], bq[KT];
-#pragma unroll
-                for (int tt = 0; tt < KT; ++tt) {
-                    acc[tt] = T(0);
-                    bq[tt] = T(0);
-                    if (d.act && gl == 0 && (KT == 1 || q0 + tt < k))
-                        bq[tt] = Bg[d.i + (int64_t)(q0 + tt) * a.ldb];
-                }
-                auto add_entry = [&](int32_t j, T v) {
-                    const bool local = TRANS ? (j < r1) : (j >= r0);
-#pragma unroll
-                    for (int tt = 0; tt < KT; ++tt) {
-                        const int q = q0 + tt;
-                        if (KT == 1 || q < k) {
-                            T xj = local ? xs[(j - r0) * k + q]
-                                         : wait_value(&X[j + (int64_t)q * a.ldx], err, a.ticks);
-                            acc[tt] += v * xj;
-                        }
-                    }
-                };
-                if (e.j >= 0) add_entry(e.j, e.v);
-                for (int32_t p = d.pb + gl + G; p < d.pe; p += G) add_entry(idx[p], value_at(p));
-#pragma unroll
-                for (int tt = 0; tt < KT; ++tt) acc[tt] = group_sum(acc[tt], G);
-                if (d.act && gl == 0) {
-#pragma unroll
-                    for (int tt = 0; tt < KT; ++tt) {
-                        const int q = q0 + tt;
-                        if (KT == 1 || q < k) {
-                            T xi = (bq[tt] - acc[tt]) / e.diag;
-                            xs[(d.i - r0) * k + q] = xi;
-                            st_relaxed(&X[d.i + (int64_t)q * a.ldx], xi);
-                        }
-                    }
-                }
-            }
-        };
-
-        // Pipelined level loop.  Per step, in this order: (1) load the x
-        // values of the row's first entry and its right-hand side, (2) publish
-        // the previous step's results, (3) load the data of the next steps,
-        // (4) wait for (1) only.  Vector-memory counters retire in order, so
-        // anything issued after (1) is not waited for by (4).
-        SfDesc dc = load_desc(0);
-        SfEnt<T> ec = load_ent(dc);
-        SfDesc dn = load_desc(1);
-        bool pend = false;
-        int32_t pend_i = 0;
-        T pend_x[KT];
-#pragma unroll
-        for (int tt = 0; tt < KT; ++tt) pend_x[tt] = T(0);
-        for (int32_t u = 0; u < ns; ++u) {
-            // (1)
-            const bool have = dc.act && ec.j >= 0;
-            const bool loc = have && (TRANS ? (ec.j < r1) : (ec.j >= r0));
-            T xv[KT], bq[KT];
-#pragma unroll
-            for (int tt = 0; tt < KT; ++tt) {
-                xv[tt] = T(0);
-                bq[tt] = T(0);
-                if (KT == 1 || tt < k) {
-                    if (have) xv[tt] = loc ? xs[(ec.j - r0) * k + tt]
-                                           : ld_relaxed(&X[ec.j + (int64_t)tt * a.ldx]);
-                    if (dc.act && gl == 0) bq[tt] = Bg[dc.i + (int64_t)tt * a.ldb];
-                }
-            }
-            // (2)
-            if (pend) {
-#pragma unroll
-                for (int tt = 0; tt < KT; ++tt)
-                    if (KT == 1 || tt < k) st_relaxed(&X[pend_i + (int64_t)tt * a.ldx], pend_x[tt]);
-                pend = false;
-            }
-            // (3)
-            const SfDesc dnn = load_desc(u + 2);
-            const SfEnt<T> en = load_ent(dn);
-            // (4)
-            T acc[KT];
-#pragma unroll
-            for (int tt = 0; tt < KT; ++tt) {
-                acc[tt] = T(0);
-                if (KT == 1 || tt < k) {
-                    if (have && !loc && is_sentinel(xv[tt]))
-                        xv[tt] = wait_value(&X[ec.j + (int64_t)tt * a.ldx], err, a.ticks);
-                    if (have) acc[tt] = ec.v * xv[tt];
-                }
-            }
-            for (int32_t p = dc.pb + gl + G; p < dc.pe; p += G) {
-                const int32_t j = idx[p];
-                const T v = value_at(p);
-                const bool local = TRANS ? (j < r1) : (j >= r0);
-#pragma unroll
-                for (int tt = 0; tt < KT; ++tt)
-                    if (KT == 1 || tt < k)
-                        acc[tt] += v * (local ? xs[(j - r0) * k + tt]
-                                              : wait_value(&X[j + (int64_t)tt * a.ldx], err, a.ticks));
-            }
-#pragma unroll
-            for (int tt = 0; tt < KT; ++tt) acc[tt] = group_sum(acc[tt], G);
-            if (dc.act && gl == 0) {
-#pragma unroll
-                for (int tt = 0; tt < KT; ++tt) {
-                    if (KT == 1 || tt < k) {
-                        T xi = (bq[tt] - acc[tt]) / ec.diag;
-                        xs[(dc.i - r0) * k + tt] = xi;
-                        pend_x[tt] = xi;
-                    }
-                }
-                pend = true;
-                pend_i = dc.i;
-            }
-            // right-hand sides beyond the first KT of this row
-            if (k > KT) solve_inline(dc, ec, KT);
-            // rows of this step beyond one per group
-            const int32_t st = TRANS ? ns - 1 - u : u;
-            const int32_t beg = sp[st], end = sp[st + 1];
-            for (int32_t base = beg + ngroups + wave_in_block * groups_per_wave; base < end;
-                 base += ngroups) {
-                const int32_t pos = base + lane / G;
-                SfDesc d;
-                d.act = pos < end;
-                d.i = d.pb = d.pe = d.dpos = 0;
-                if (d.act) {
-                    const int4 v = a.desc[r0 + pos];
-                    d.i = v.x;
-                    d.pb = v.y;
-                    d.pe = v.z;
-                    d.dpos = v.w;
-                }
-                solve_inline(d, load_ent(d), 0);
-            }
-            lds_barrier();
-            dc = dn;
-            ec = en;
-            dn = dnn;
-        }
-        if (pend) {
-#pragma unroll
-            for (int tt = 0; tt < KT; ++tt)
-                if (KT == 1 || tt < k) st_relaxed(&X[pend_i + (int64_t)tt * a.ldx], pend_x[tt]);
-        }
-        __syncthreads();
-        if (ld_relaxed(err) != 0) break;
+        b.r0 = blk * a.block_rows;
+        b.r1 = min(a.n, b.r0 + a.block_rows);
+        b.sb = a.blk_step[blk];
+        b.ns = a.blk_step[blk + 1] - b.sb;
+        sf_block<T, TRANS, KT>(b, s_raw);
+        if (ld_relaxed(&a.ctrl->err) != 0) break;
     }
 }
 
@@ -474,7 +270,7 @@ unsigned solve_grid(Algo algo, rwt_dtype dt, bool transposed, int k, size_t lds,
 }
 
 int syncfree_lds_bytes(int block_rows, int k, rwt_dtype dt) {
-    return ((block_rows * k * (int)dtype_size(dt) + 15) & ~15) + (block_rows + 1) * 4;
+    return sf_x_bytes(block_rows, k, (int)dtype_size(dt)) + (block_rows + 1) * 4;
 }
 
 rwt_status solve_prepare(const SolveArgs& a, rwt_dtype dt, hipStream_t s) {
