@@ -29,6 +29,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# sources of the solve kernels and their schedules (a change invalidates the
+# committed counter measurements)
+SOLVE_SOURCES = ["paper_2609_40159_amd/csrc/solve.hip", "paper_2609_40159_amd/csrc/solve.hpp",
+                 "paper_2609_40159_amd/csrc/sf_block.hpp", "paper_2609_40159_amd/csrc/common.hpp",
+                 "paper_2609_40159_amd/csrc/plan.hip"]
 METRIC = "SpTRSV HBM GB/s & solves/s, rewritten vs original DAG, fwd+adjoint, batched"
 
 
@@ -44,6 +49,13 @@ def parse():
                     help="approximate CPU budget of the oracle baseline")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter scaling for profiles)")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the comparison solves (original DAG, forced schedules)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
+    ap.add_argument("--batch-count", type=int, default=256, help="matrices in the batch")
+    ap.add_argument("--batch-steps", type=int, default=5, help="timed batched launches")
+    ap.add_argument("--gen-workers", type=int, default=min(16, os.cpu_count() or 1),
+                    help="host processes generating the batch")
     return ap.parse_args()
 
 
@@ -101,6 +113,153 @@ def load_traffic(kernel_key: str, srchash: str):
     return e.get("hbm_bytes_per_launch")
 
 
+def log(msg: str) -> None:
+    """Progress to stderr (the JSON result is the only line on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def compare(cmp, time_solve, plan, plan_orig, rw, B, Bp, G, k, Plan):
+    """Original vs rewritten DAG, and the two schedules forced (not part of value)."""
+    cmp["orig_fwd_ms"] = time_solve(plan_orig, B)
+    cmp["orig_bwd_ms"] = time_solve(plan_orig, G, True)
+    cmp["rewritten_fwd_ms"] = time_solve(plan, Bp)
+    cmp["rewritten_bwd_ms"] = time_solve(plan, G, True)
+    for algo in ("level", "syncfree"):
+        pl = Plan(rw.Lp, algo=algo, kmax=k)
+        cmp[f"rewritten_fwd_{algo}_ms"] = time_solve(pl, Bp)
+        del pl
+    cmp["speedup_rewritten_vs_original_fwd"] = cmp["orig_fwd_ms"] / cmp["rewritten_fwd_ms"]
+    cmp["speedup_rewritten_vs_original_fwd_adj"] = (
+        (cmp["orig_fwd_ms"] + cmp["orig_bwd_ms"]) / (cmp["rewritten_fwd_ms"] + cmp["rewritten_bwd_ms"]))
+
+
+def bytes_levels(n, nnz):
+    """Level computation of one candidate: row pointers, dependency columns,
+    the level written per row (the rewritten rows' patterns are extra)."""
+    return 4 * (n + 1) + 4 * (nnz - n) + 4 * n
+
+
+def run_batched(args, man, gen, dev):
+    """Many uneven matrices with 1-16 right-hand sides each and 32 candidate
+    rewrite sets per matrix: one captured persistent launch, against one
+    solve launch per matrix and against per-candidate rewrite + analysis."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2609_40159_amd.api import Batch, CSRMatrix, Rewriter, analyze
+
+    res = {"matrices": len(man)}
+    t0 = time.perf_counter()
+    mats, xstar = [], []
+    for spec, (Lh, xs, Bh) in zip(man, gen):
+        L = CSRMatrix.from_arrays(Lh.rowptr, Lh.colidx, Lh.vals, device=dev, dtype=torch.float64)
+        Bd = torch.as_tensor(Bh).to(dev).contiguous()
+        mats.append((L, Bd, torch.empty_like(Bd)))
+        xstar.append(xs)
+    torch.cuda.synchronize()
+    res["upload_s"] = time.perf_counter() - t0
+    n_tot = sum(L.n for L, _, _ in mats)
+    nnz_tot = sum(L.nnz for L, _, _ in mats)
+    sum_k = sum(spec["k"] for spec in man)
+    t0 = time.perf_counter()
+    infos = [analyze(L) for L, _, _ in mats]
+    res["analyze_all_s"] = time.perf_counter() - t0
+    levels = [inf.level for inf in infos]
+    cand_mat, rows_l, ptr = [], [], [0]
+    for m, spec in enumerate(man):
+        lv = levels[m].cpu().numpy()
+        for c in range(len(spec["phis"])):
+            r = synth.candidate_rows(spec, lv, c)
+            cand_mat.append(m)
+            rows_l.append(r)
+            ptr.append(ptr[-1] + len(r))
+    rows = np.concatenate(rows_l).astype(np.int32)
+    d_rows = torch.as_tensor(rows, device=dev)
+    d_ptr = torch.as_tensor(np.asarray(ptr, np.int32), device=dev)
+    C = len(cand_mat)
+    pcap = 256 * max(1, rows.size)
+    res.update({"n_total": n_tot, "nnz_total": nnz_tot, "rhs_total": sum_k,
+                "max_levels": max(inf.num_levels for inf in infos), "candidates": C,
+                "candidate_rows": int(rows.size)})
+
+    def timed(bt, fn, reps):
+        fn()
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(bt.stream)
+            fn()
+            b.record(bt.stream)
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts))
+
+    log(f"batch uploaded and analysed; {C} candidates")
+    # (1) everything in one launch: solves of all matrices + all candidates
+    full = Batch(mats, cand_mat, d_ptr, d_rows, None, pattern_cap=pcap)
+    R = [full.plan_info(m)["block_rows"] for m in range(len(mats))]
+    res["create_ms"] = full.info["create_ms"]
+    res["tasks"] = full.info["tasks"]
+    full.capture()
+    log(f"full batch created in {res['create_ms']:.0f} ms")
+    res["full_ms"] = timed(full, full.launch, args.batch_steps)
+    log(f"full batch launch {res['full_ms']:.2f} ms")
+    st = full.stats()
+    assert full.last_status == "OK" and all(x["valid"] for x in st), full.last_status
+    err = 0.0
+    for (L, Bd, Xd), xs in zip(mats, xstar):
+        xt = torch.as_tensor(xs, device=dev)
+        err = max(err, float((Xd - xt).abs().max() / xt.abs().max()))
+    res["relerr_vs_xstar_max"] = err
+    b_solve = sum(bytes_solve(L.n, L.nnz, spec["k"], 8) for (L, _, _), spec in zip(mats, man))
+    b_cand = sum(bytes_levels(mats[m][0].n, mats[m][0].nnz) for m in cand_mat)
+    res["full_gbs"] = (b_solve + b_cand) / res["full_ms"] / 1e6
+    del full
+    # (2) solves only: one launch vs one launch per matrix (same schedules)
+    solves = Batch(mats, [], None, None, block_rows=R)
+    solves.capture()
+    res["solves_batched_ms"] = timed(solves, solves.launch, args.batch_steps)
+    res["solves_plain_ms"] = timed(solves, solves.solve_plain, max(1, args.batch_steps // 2))
+    log("batched and per-matrix solves timed")
+    res["solves_per_s_batched"] = sum_k / res["solves_batched_ms"] * 1e3
+    res["solves_per_s_plain"] = sum_k / res["solves_plain_ms"] * 1e3
+    res["solve_gbs_batched"] = b_solve / res["solves_batched_ms"] / 1e6
+    res["solve_gbs_plain"] = b_solve / res["solves_plain_ms"] / 1e6
+    res["speedup_solves_batched_vs_plain"] = res["solves_plain_ms"] / res["solves_batched_ms"]
+    del solves
+    # (3) candidates only: one launch vs rewrite + analysis per candidate
+    mats0 = [(L, None, None) for L, _, _ in mats]
+    cands = Batch(mats0, cand_mat, d_ptr, d_rows, None, pattern_cap=pcap, block_rows=R)
+    cands.capture()
+    res["cands_batched_ms"] = timed(cands, cands.launch, args.batch_steps)
+    stc = cands.stats()
+    res["candidates_per_s_batched"] = C / res["cands_batched_ms"] * 1e3
+    log("candidate-only batch timed")
+    # per-candidate path on a sample: symbolic + numeric rewrite, then analysis
+    sample = list(range(0, C, max(1, C // 64)))[:64]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    same = True
+    for c in sample:
+        m = cand_mat[c]
+        rw = Rewriter(mats[m][0], levels[m], rows_l[c])
+        rw.numeric()
+        a = analyze(rw.Lp)
+        same = same and (a.num_levels == stc[c]["num_levels"] and a.stats["S1"] == stc[c]["S1"]
+                         and a.stats["S2"] == stc[c]["S2"] and a.stats["cv"] == stc[c]["cv"])
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / len(sample)
+    res["candidates_per_s_plain"] = 1.0 / t_plain
+    res["speedup_candidates_batched_vs_plain"] = res["candidates_per_s_batched"] * t_plain
+    res["plain_candidate_sample"] = len(sample)
+    res["batched_stats_equal_plain"] = bool(same)
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -113,6 +272,18 @@ def main():
     import torch
 
     import synth
+
+    # batched workload inputs: generated first, in forked host processes,
+    # before anything touches the GPU
+    man = gen = None
+    gen_s = 0.0
+    if not args.no_batch:
+        t0 = time.perf_counter()
+        man = synth.batch_manifest(count=args.batch_count)
+        gen = synth.build_batch(man, args.gen_workers)
+        gen_s = time.perf_counter() - t0
+        log(f"batch inputs generated in {gen_s:.1f} s")
+
     from paper_2609_40159_amd import _lib
     from paper_2609_40159_amd.api import (CSRMatrix, Plan, Rewriter, analyze, apply_MT,
                                           grad_vals, validate)
@@ -202,6 +373,7 @@ def main():
         if e: e[5].record()
         return X, gB, gV
 
+    log("main workload prepared")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -245,17 +417,10 @@ def main():
         return float(np.median(ts))
 
     cmp = {}
-    cmp["orig_fwd_ms"] = time_solve(plan_orig, B)
-    cmp["orig_bwd_ms"] = time_solve(plan_orig, G, True)
-    cmp["rewritten_fwd_ms"] = time_solve(plan, Bp)
-    cmp["rewritten_bwd_ms"] = time_solve(plan, G, True)
-    for algo in ("level", "syncfree"):
-        pl = Plan(rw.Lp, algo=algo, kmax=k)
-        cmp[f"rewritten_fwd_{algo}_ms"] = time_solve(pl, Bp)
-        del pl
-    cmp["speedup_rewritten_vs_original_fwd"] = cmp["orig_fwd_ms"] / cmp["rewritten_fwd_ms"]
-    cmp["speedup_rewritten_vs_original_fwd_adj"] = (
-        (cmp["orig_fwd_ms"] + cmp["orig_bwd_ms"]) / (cmp["rewritten_fwd_ms"] + cmp["rewritten_bwd_ms"]))
+    if args.no_compare:
+        cmp = None
+    else:
+        compare(cmp, time_solve, plan, plan_orig, rw, B, Bp, G, k, Plan)
 
     copy_probe = None
     if args.copy_probe:
@@ -272,6 +437,7 @@ def main():
         copy_probe = {"bytes_each": 2 * a.numel() * 8, "ms_each": e0.elapsed_time(e1) / 5}
         del a, b2
 
+    log("main workload timed")
     # ---------------- CPU oracle baseline ----------------
     cpu = None
     if not args.no_cpu:
@@ -297,15 +463,27 @@ def main():
                          f"workload, single-threaded FP64 oracle"}
 
     # ---------------- roofline of the dominant kernel ----------------
-    fwd_algo = pinfo["algo_fwd"]
-    kname = f"k_solve_{'sf' if fwd_algo == 'syncfree' else 'level'}<{'double' if s == 8 else 'float'}, false, 1>"
-    srch = src_hash(["paper_2609_40159_amd/csrc/solve.hip", "paper_2609_40159_amd/csrc/common.hpp"])
-    traffic = load_traffic(f"{args.workload}:{args.dtype}:{kname}", srch)
-    achieved = b_fwd / (ms["fwd"] * 1e-3) / 1e9
-    roof = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": PEAK_HBM_GBS,
-            "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-            "algorithmic_bytes_per_launch": b_fwd,
+    # the forward and the transposed solve take most of a step; the longer
+    # of the two is the dominant kernel (its phase also holds the sentinel
+    # prefill of the output, a plain n*k store)
+    srch = src_hash(SOLVE_SOURCES)
+    tname = "double" if s == 8 else "float"
+    roofs = {}
+    for ph_name, trans, nbytes in (("fwd", False, b_fwd), ("bwd", True, b_bwd)):
+        algo = pinfo["algo_fwd"] if not trans else pinfo["algo_bwd"]
+        kname = f"k_solve_{'sf' if algo == 'syncfree' else 'level'}<{tname}, {str(trans).lower()}, 1>"
+        achieved = nbytes / (ms[ph_name] * 1e-3) / 1e9
+        roofs[ph_name] = {
+            "bound": "hbm", "kernel": kname, "achieved": achieved, "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+            "traffic": load_traffic(f"{args.workload}:{args.dtype}:{kname}", srch),
+            "algorithmic_bytes_per_launch": nbytes, "avg_launch_ms": ms[ph_name],
             "latency_floor_note": f"{Dp} dependent levels on the critical path"}
+    dom = "fwd" if ms["fwd"] >= ms["bwd"] else "bwd"
+    roof = roofs[dom]
+    batched = run_batched(args, man, gen, dev) if man is not None else None
+    if batched is not None:
+        batched["host_generation_s"] = gen_s
 
     ms_per_step = elapsed / args.steps * 1e3
     value = b_step * args.steps / elapsed / 1e9
@@ -336,6 +514,8 @@ def main():
         "preprocess": pre,
         "relerr_vs_xstar": err,
         "roofline": roof,
+        "roofline_other": roofs["bwd" if dom == "fwd" else "fwd"],
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     if copy_probe:

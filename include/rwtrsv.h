@@ -267,7 +267,8 @@ rwt_status rwt_grad_vals(const rwt_csr* L, const void* d_gB, int64_t ldg, const 
  * Per matrix m: L (FP64 values), B / X (k columns; k may be 0 for
  * analysis-only matrices).  Its solve schedule is autotuned at creation
  * (sync-free row blocks of a measured size, or the whole matrix in one
- * workgroup, level after level, when it fits in LDS).
+ * workgroup, level after level, when it fits in LDS) unless block_rows
+ * fixes the block size.
  * Per candidate c: the matrix h_cand_mat[c] and the rows
  * d_cand_rows[d_cand_ptr[c] .. d_cand_ptr[c+1]) (strictly ascending) with
  * targets d_cand_targets (NULL: level - 1).  Each launch recomputes, for
@@ -286,7 +287,7 @@ typedef struct {
     const void* B;        /* device, k columns (ldb) */
     void* X;              /* device, k columns (ldx) */
     int32_t k;
-    int32_t pad_;
+    int32_t block_rows;   /* solve row-block size; 0: autotuned at creation */
     int64_t ldb;
     int64_t ldx;
 } rwt_batch_matrix;

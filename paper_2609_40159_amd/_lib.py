@@ -63,7 +63,7 @@ class PlanInfo(C.Structure):
 
 class BatchMatrix(C.Structure):
     _fields_ = [("L", Csr), ("B", C.c_void_p), ("X", C.c_void_p), ("k", C.c_int32),
-                ("pad_", C.c_int32), ("ldb", C.c_int64), ("ldx", C.c_int64)]
+                ("block_rows", C.c_int32), ("ldb", C.c_int64), ("ldx", C.c_int64)]
 
 
 class BatchDesc(C.Structure):

@@ -327,12 +327,14 @@ class Batch:
     mats: list of (CSRMatrix FP64, B (k, n) or None, X (k, n) or None).
     cand_mat: matrix index of each candidate; cand_ptr (C+1) and cand_rows
     are device int32 tensors whose contents may change between launches
-    (within cand_rows_cap rows).  All work runs on the batch's own stream,
+    (within cand_rows_cap rows).  block_rows: per-matrix solve block sizes
+    (default: autotuned).  All work runs on the batch's own stream,
     ordered after the caller's current stream and before it again.
     """
 
     def __init__(self, mats, cand_mat, cand_ptr, cand_rows, cand_targets=None,
-                 cand_rows_cap: int | None = None, pattern_cap: int = 0, watchdog_ms: int = 0):
+                 cand_rows_cap: int | None = None, pattern_cap: int = 0, watchdog_ms: int = 0,
+                 block_rows=None):
         lib = _lib.load()
         self._lib = lib
         self.mats = list(mats)
@@ -354,6 +356,7 @@ class Batch:
                 arr[i].X = X2.data_ptr()
                 self._keep += [B2, X2]
             arr[i].k = k
+            arr[i].block_rows = 0 if block_rows is None else int(block_rows[i])
             arr[i].ldb = L.n
             arr[i].ldx = L.n
         self._arr = arr
@@ -434,6 +437,22 @@ class Batch:
         i = _lib.BatchInfo()
         check(self._lib.rwt_batch_get_info(self._h, C.byref(i)))
         return {f: getattr(i, f) for f, _ in i._fields_}
+
+    def solve_plain(self, which=None) -> None:
+        """Solve the given matrices (default: all) one launch each with their
+        batch plans (same schedules): the one-launch-per-matrix baseline."""
+        which = range(len(self.mats)) if which is None else which
+        self._enter()
+        for m in which:
+            L, B, X = self.mats[m]
+            if B is None:
+                continue
+            p = C.c_void_p()
+            check(self._lib.rwt_batch_plan(self._h, m, C.byref(p)))
+            B2, k = _block(B, L.n, L.dtype)
+            X2, _ = _block(X, L.n, L.dtype)
+            check(self._lib.rwt_solve(p, _ptr(B2), k, L.n, _ptr(X2), L.n, self.stream.cuda_stream))
+        self._leave()
 
     def plan_info(self, m: int) -> dict:
         p = C.c_void_p()

@@ -458,12 +458,17 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
         else
             hipLaunchKernelGGL(k_fill_val<float>, dim3(g), dim3(256), 0, s,
                                static_cast<float*>(p->xtmp), (int64_t)n, 1.0f);
+        // candidates run from large blocks to small; stop after two in a row
+        // that are more than 10% slower than the best so far
         double best_sf = 1e30;
         int best_R = cands.front();
+        int worse = 0;
         for (int Rc : cands) {
             if ((st = build_blocks(Rc)) != RWT_OK) return fail(st);
-            double ms = time_solve(p, Algo::SyncFree, s, 3);
+            double ms = time_solve(p, Algo::SyncFree, s, 2);
             if (ms < best_sf) { best_sf = ms; best_R = Rc; }
+            worse = ms > 1.1 * best_sf ? worse + 1 : 0;
+            if (worse >= 2) break;
         }
         p->tuned_sf = best_sf;
         R = best_R;

@@ -327,6 +327,30 @@ def build_matrix(spec: dict) -> CSR:
     raise ValueError(kind)
 
 
+def _batch_member(spec: dict):
+    L = build_matrix(spec)
+    k = spec["k"]
+    xs, B = rhs(L, k, spec["index"] + 1) if k > 0 else (None, None)
+    return L, xs, B
+
+
+def build_batch(manifest: list[dict], workers: int = 1) -> list[tuple]:
+    """(L, x*, B) of every manifest entry, optionally in forked worker
+    processes (call before any GPU use in the parent)."""
+    if workers <= 1:
+        return [_batch_member(s) for s in manifest]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(_batch_member, manifest, chunksize=1)
+
+
+def candidate_rows(spec: dict, level: np.ndarray, c: int) -> np.ndarray:
+    """Candidate c of a batched matrix: a uniform sample of floor(phi_c * n)
+    rows with level >= 1 (seed (matrix seed, c)); targets are level - 1."""
+    rows, _ = random_rowset(level, spec["phis"][c], list(spec["cand_seeds"][c]))
+    return rows
+
+
 #: The named workloads (the paper's scale classes, synthetic stand-ins).
 WORKLOADS = {
     "lap2d_64": {"kind": "lap2d", "dims": (64, 64), "k": 1, "seed": 1,
