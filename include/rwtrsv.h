@@ -177,9 +177,13 @@ rwt_status rwt_rewrite_numeric(const rwt_csr* L, const int32_t* d_level,
  *   RWT_ALGO_SYNCFREE synchronization-free (Section 7): row blocks claimed
  *                     in row order, each block solved level by level in
  *                     LDS, waiting on per-row readiness in HBM for
- *                     dependencies outside the block;
- *   RWT_ALGO_AUTO     autotuned: both candidates are timed once on the
- *                     plan's matrix and the faster kept.
+ *                     dependencies outside the block; k right-hand sides
+ *                     are split into chains of rhs_chunk columns that run
+ *                     concurrently (each chain is a full sync-free solve);
+ *   RWT_ALGO_AUTO     autotuned: both candidates are timed on the plan's
+ *                     matrix and the faster kept.
+ * Unless fixed by the options, the sync-free block size and RHS chunk are
+ * chosen by timing solves on the plan's own matrix (min(kmax, 4) columns).
  * The plan keeps pointers to L (pattern and values): the caller keeps them
  * alive and may change the values between solves.  The plan's device
  * state lives in the caller's workspace (rwt_plan_ws bytes).
@@ -192,7 +196,9 @@ typedef struct {
     int32_t lanes_per_row;    /* 0: choose from the mean row length; else 1..64, power of 2 */
     int32_t narrow_rows;      /* level-scheduled: levels up to this many rows run on one workgroup (-1: choose) */
     int32_t kmax;             /* largest number of right-hand sides solved at once (>=1) */
-    int32_t watchdog_ms;      /* bound on any device wait (0: 2000 ms) */
+    int32_t watchdog_ms;      /* bound on any device wait (0: 5000 ms) */
+    int32_t rhs_chunk;        /* sync-free columns per chain: 0 choose, else 1..4 */
+    int32_t pad_;
 } rwt_plan_opts;
 
 typedef struct rwt_plan rwt_plan;
@@ -206,7 +212,7 @@ typedef struct {
     int32_t narrow_rows;
     int32_t num_blocks;
     int32_t grid;             /* workgroups of the persistent launches */
-    int32_t pad_;
+    int32_t rhs_chunk;        /* sync-free right-hand-side columns per chain */
     double tuned_ms_level;    /* autotuner measurements (0 when not tuned) */
     double tuned_ms_syncfree;
 } rwt_plan_info;

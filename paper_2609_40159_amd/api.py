@@ -223,7 +223,8 @@ class Plan:
     """Analysis + schedule of one matrix; solves L X = B and L^T Y = G."""
 
     def __init__(self, L: CSRMatrix, algo: str = "auto", kmax: int = 1, block_rows: int = 0,
-                 lanes_per_row: int = 0, narrow_rows: int = -1, watchdog_ms: int = 0):
+                 lanes_per_row: int = 0, narrow_rows: int = -1, watchdog_ms: int = 0,
+                 rhs_chunk: int = 0):
         lib = _lib.load()
         self.L = L
         self._lib = lib
@@ -234,6 +235,7 @@ class Plan:
         o.narrow_rows = narrow_rows
         o.kmax = kmax
         o.watchdog_ms = watchdog_ms
+        o.rhs_chunk = rhs_chunk
         self.opts = o
         sz = C.c_size_t(0)
         check(lib.rwt_plan_ws(C.byref(L.view()), C.byref(o), C.byref(sz)))
@@ -461,4 +463,5 @@ class Batch:
         check(self._lib.rwt_plan_get_info(p, C.byref(inf)))
         return {"algo": "one workgroup" if inf.num_blocks == 1 else "sync-free blocks",
                 "block_rows": inf.block_rows, "lanes_per_row": inf.lanes_per_row,
-                "num_blocks": inf.num_blocks, "tuned_ms": inf.tuned_ms_syncfree}
+                "rhs_chunk": inf.rhs_chunk, "num_blocks": inf.num_blocks,
+                "tuned_ms": inf.tuned_ms_syncfree}

@@ -44,7 +44,7 @@ constexpr int BT_LDS = SF_LDS_BUDGET;
 constexpr int NSLAB_B = 2;
 
 struct BatchMatDev {
-    int32_t n, R, lanes, nblocks, k, pad;
+    int32_t n, R, lanes, nblocks, k, kc;   // kc: right-hand sides per solve chain
     int64_t ldb, ldx;
     const int32_t* rowptr;
     const int32_t* colidx;
@@ -124,7 +124,7 @@ __device__ int32_t lower_bound_g(const int32_t* a, int32_t lo, int32_t hi, int32
     return lo;
 }
 
-__device__ void level_block(const BatchKArgs& a, const BatchMatDev& M, const BatchCandDev& Cd,
+__device__ __forceinline__ void level_block(const BatchKArgs& a, const BatchMatDev& M, const BatchCandDev& Cd,
                             int32_t c, int32_t blk, uint32_t tag, unsigned char* s_raw) {
     const int32_t R = M.R;
     const int32_t r0 = blk * R, r1 = min(M.n, r0 + R);
@@ -160,16 +160,39 @@ __device__ void level_block(const BatchKArgs& a, const BatchMatDev& M, const Bat
                     dep = a.pat;
                 }
             }
+            // levels of U dependencies are loaded together, then checked
+            constexpr int U = 8;
             int32_t mx = -1;
-            for (int32_t p = db + gl; p < de; p += G) {
-                const int32_t j = dep[p];
-                if (j < 0 || j >= i) {   // cannot happen for a consistent batch; never index with it
-                    __hip_atomic_store(err, (int32_t)RWT_ERR_INVALID_ARG, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                    continue;
+            for (int32_t p0 = db + gl; p0 < de; p0 += U * G) {
+                int32_t jv[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int32_t p = p0 + u * G;
+                    const int32_t jj = dep[p < de ? p : p0];   // p0 < de: a valid entry
+                    // out of range cannot happen for a consistent batch; never index with it
+                    const bool ok = p < de && jj >= 0 && jj < i;
+                    if (p < de && !ok)
+                        __hip_atomic_store(err, (int32_t)RWT_ERR_INVALID_ARG, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    jv[u] = ok ? jj : -1;
                 }
-                const int32_t lj = j >= r0 ? lv[j - r0] : wait_level(&Cd.lev[j], tag, err, a.ticks);
-                mx = lj > mx ? lj : mx;
+                int32_t lvv[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int32_t j = jv[u];
+                    lvv[u] = j < 0 ? 0 : (j >= r0 ? lv[j - r0] : ld_relaxed(&Cd.lev[j]));
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int32_t j = jv[u];
+                    if (j < 0) continue;
+                    int32_t lj = lvv[u];
+                    if (j < r0) {
+                        lj = (((uint32_t)lj >> 24) == tag) ? (lj & 0xffffff)
+                                                           : wait_level(&Cd.lev[j], tag, err, a.ticks);
+                    }
+                    mx = lj > mx ? lj : mx;
+                }
             }
             mx = group_max_i(mx, G);
             if (act && gl == 0) {
@@ -219,7 +242,7 @@ __device__ int32_t block_max_bt(int32_t v, int32_t* scratch) {
 }
 
 // statistics of candidate c (its levels are all published)
-__device__ void finalize_cand(const BatchKArgs& a, const BatchMatDev& M, const BatchCandDev& Cd,
+__device__ __forceinline__ void finalize_cand(const BatchKArgs& a, const BatchMatDev& M, const BatchCandDev& Cd,
                               int32_t c, uint32_t tag, unsigned char* s_raw) {
     int32_t* err = &a.ctrl->err;
     const int32_t n = M.n;
@@ -291,12 +314,13 @@ __global__ void __launch_bounds__(BT_THREADS) k_batch_main(BatchKArgs a) {
         const int4 tk = a.tasks[t];
         if (tk.x == 0) {
             const BatchMatDev& M = a.mats[tk.y];
+            const int32_t q0 = tk.w * M.kc;   // this chain's first column
             SfBlockArgs b;
             b.r0 = tk.z * M.R;
             b.r1 = min(M.n, b.r0 + M.R);
             b.sb = M.blk_step[tk.z];
             b.ns = M.blk_step[tk.z + 1] - b.sb;
-            b.k = M.k;
+            b.k = min(M.kc, M.k - q0);
             b.lanes = M.lanes;
             b.ldb = M.ldb;
             b.ldx = M.ldx;
@@ -306,14 +330,13 @@ __global__ void __launch_bounds__(BT_THREADS) k_batch_main(BatchKArgs a) {
             b.vals = M.vals;
             b.desc = M.desc;
             b.step_pos = M.step_pos;
-            b.B = M.B;
-            b.X = M.X;
+            b.B = M.B + (int64_t)q0 * M.ldb;
+            b.X = M.X + (int64_t)q0 * M.ldx;
             b.err = &a.ctrl->err;
             b.ticks = a.ticks;
             b.lds_rows = M.R;
-            if (M.k == 1) sf_block<double, false, 1>(b, s_raw);
-            else if (M.k <= 4) sf_block<double, false, 4>(b, s_raw);
-            else sf_block<double, false, 16>(b, s_raw);
+            if (M.kc == 1) sf_block<double, false, 1>(b, s_raw);
+            else sf_block<double, false, 4>(b, s_raw);
         } else {
             const int32_t c = tk.y;
             const BatchCandDev& Cd = a.cands[c];
@@ -328,6 +351,20 @@ __global__ void __launch_bounds__(BT_THREADS) k_batch_main(BatchKArgs a) {
         __syncthreads();
         if (ld_relaxed(&a.ctrl->err) != 0) break;
     }
+}
+
+// Lowest level among the rows of each row block (tasks are ordered by when
+// their first rows can start).
+__global__ void k_block_minlev(const int32_t* level, int32_t n, int32_t R, int32_t* out) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = tid; i < n; i += nth) atomicMin(&out[i / R], level[i]);
+}
+
+__global__ void k_fill_i32max(int32_t* p, int64_t n) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = tid; i < n; i += nth) p[i] = 0x7fffffff;
 }
 
 __global__ void k_batch_epoch(uint32_t* epoch) {
@@ -480,7 +517,7 @@ rwt_plan_opts batch_plan_opts(const rwt_batch_desc* d, const rwt_batch_matrix& m
 struct BatchLayout {
     std::vector<size_t> plan_off, plan_bytes;
     size_t mats, cands, candmat, rwmats, tasks, bitmaps, levs, done, bad, stats, counts, patptr, pat, ovf,
-        ovfmark, rwctrl, slab, scan, ctrl, epoch, total;
+        ovfmark, rwctrl, slab, scan, ctrl, epoch, blkmin, total;
     int64_t bitmap_words, lev_words, slab_stride;
     int32_t qcap, pat_cap, slab_cap, ntasks_max;
 };
@@ -538,8 +575,8 @@ rwt_status layout_batch(const rwt_batch_desc* d, BatchLayout* L) {
     L->slab_cap = nmax + 1;
     L->slab_stride = (int64_t)batch_rw_slab_stride(nmax);
     int64_t ntask = 0;
-    for (int32_t m = 0; m < d->count; ++m)
-        if (d->mats[m].k > 0) ntask += (d->mats[m].L.n + 31) / 32;
+    for (int32_t m = 0; m < d->count; ++m)   // at most one chain per column
+        if (d->mats[m].k > 0) ntask += (int64_t)d->mats[m].k * ((d->mats[m].L.n + 31) / 32);
     for (int32_t c = 0; c < d->num_cand; ++c) ntask += (d->mats[d->h_cand_mat[c]].L.n + 31) / 32;
     RWT_REQUIRE(ntask < (int64_t(1) << 31), RWT_ERR_TOO_LARGE, "too many tasks");
     L->ntasks_max = (int32_t)ntask;
@@ -563,7 +600,7 @@ rwt_status layout_batch(const rwt_batch_desc* d, BatchLayout* L) {
     L->scan = take(scan_ws((int64_t)L->qcap + 1));
     L->ctrl = take(sizeof(Ctrl));
     L->epoch = take(sizeof(uint32_t));
-    (void)blocks_max;
+    L->blkmin = take(sizeof(int32_t) * std::max<int64_t>(1, blocks_max));
     L->total = (off + 255) & ~size_t(255);
     return RWT_OK;
 }
@@ -692,6 +729,7 @@ extern "C" rwt_status rwt_batch_create(const rwt_batch_desc* desc, void* d_ws, s
         d.lanes = p->lanes;
         d.nblocks = p->nblocks;
         d.k = M.k;
+        d.kc = p->kc;
         d.ldb = M.ldb;
         d.ldx = M.ldx;
         d.rowptr = M.L.rowptr;
@@ -749,22 +787,54 @@ extern "C" rwt_status rwt_batch_create(const rwt_batch_desc* desc, void* d_ws, s
             lw += n;
         }
     }
-    // task table: chains in row order, interleaved by relative position
+    // task table.  A chain (one matrix's solve, or one candidate's levels)
+    // is its row blocks in row order.  A task is keyed by the level at which
+    // it can first do work: the lowest level of its rows, raised to the
+    // running maximum along the chain so that keys never decrease inside a
+    // chain.  Sorting all tasks by key (stably) keeps each chain in row
+    // order -- a task waits only for tasks with earlier tickets, so the
+    // schedule is deadlock-free for any number of resident workgroups --
+    // and claims a task roughly when its dependencies are done, instead of
+    // letting tasks of deep chains hold workgroups while they wait.
+    std::vector<int64_t> blk_off(desc->count + 1, 0);
+    for (int32_t m = 0; m < desc->count; ++m) blk_off[m + 1] = blk_off[m] + hm[m].nblocks;
+    std::vector<int32_t> minlev(std::max<int64_t>(1, blk_off[desc->count]), 0);
+    {
+        int32_t* d_min = at<int32_t>(d_ws, L.blkmin);
+        const int64_t tot = blk_off[desc->count];
+        if (tot > 0) {
+            hipLaunchKernelGGL(k_fill_i32max, dim3(blocks_for(tot, 256, 1024)), dim3(256), 0, s, d_min,
+                               tot);
+            for (int32_t m = 0; m < desc->count; ++m)
+                if (hm[m].n > 0)
+                    hipLaunchKernelGGL(k_block_minlev, dim3(blocks_for(hm[m].n, 256, 1024)), dim3(256), 0,
+                                       s, hm[m].level, hm[m].n, hm[m].R, d_min + blk_off[m]);
+            if (hipGetLastError() != hipSuccess ||
+                hipMemcpyAsync(minlev.data(), d_min, sizeof(int32_t) * tot, hipMemcpyDeviceToHost, s) !=
+                    hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
+                set_hip_error(hipGetLastError(), "batch task keys");
+                return fail(RWT_ERR_HIP);
+            }
+        }
+    }
     struct T {
-        double key;
+        int32_t key;
         int4 t;
     };
     std::vector<T> tv;
-    for (int32_t m = 0; m < desc->count; ++m) {
-        if (b->mats[m].k == 0) continue;
-        const int32_t nb = hm[m].nblocks;
-        for (int32_t k = 0; k < nb; ++k) tv.push_back({(k + 0.5) / nb, make_int4(0, m, k, 0)});
-    }
+    auto add_chain = [&](int32_t m, int kind, int32_t id, int32_t chunk) {
+        int32_t run = 0;
+        for (int32_t k = 0; k < hm[m].nblocks; ++k) {
+            run = std::max(run, minlev[blk_off[m] + k]);
+            tv.push_back({run, make_int4(kind, id, k, chunk)});
+        }
+    };
+    // one solve chain per chunk of kc right-hand-side columns
+    for (int32_t m = 0; m < desc->count; ++m)
+        for (int32_t c = 0; c * hm[m].kc < b->mats[m].k; ++c) add_chain(m, 0, m, c);
     b->solve_tasks = (int32_t)tv.size();
-    for (int32_t c = 0; c < desc->num_cand; ++c) {
-        const int32_t nb = hm[hc[c].m].nblocks;
-        for (int32_t k = 0; k < nb; ++k) tv.push_back({(k + 0.5) / nb, make_int4(1, c, k, 0)});
-    }
+    for (int32_t c = 0; c < desc->num_cand; ++c) add_chain(hc[c].m, 1, c, 0);
     std::stable_sort(tv.begin(), tv.end(), [](const T& x, const T& y) { return x.key < y.key; });
     std::vector<int4> tasks(tv.size());
     for (size_t i = 0; i < tv.size(); ++i) tasks[i] = tv[i].t;

@@ -120,8 +120,9 @@ bool block_rows_ok(int R, int kmax, rwt_dtype dt) {
     return R >= R_MIN && syncfree_lds_bytes(R, kmax, dt) <= SF_LDS_BUDGET;
 }
 
-std::vector<int> block_candidates(const rwt_plan_opts& o, rwt_dtype dt, int32_t n) {
-    const int kmax = o.kmax > 0 ? o.kmax : 1;
+// Block sizes to try for chains of kc right-hand-side columns.
+std::vector<int> block_candidates(const rwt_plan_opts& o, rwt_dtype dt, int32_t n, int kc) {
+    const int kmax = kc;
     std::vector<int> out;
     // the whole matrix in one workgroup, level after level with workgroup
     // barriers, when its x values fit in LDS
@@ -188,7 +189,7 @@ size_t carve_plan(void* base, const rwt_csr& L, int kmax, PlanPtrs* p) {
     p->desc_f = cv.take<int4>(n);
     p->desc_t = cv.take<int4>(n);
     p->xtmp = cv.take<char>((size_t)n * kmax * s);
-    p->xtmp2 = cv.take<char>((size_t)n * s);
+    p->xtmp2 = cv.take<char>((size_t)n * std::min(kmax, 4) * s);
     // scratch shared by the construction steps
     size_t sched = 0;
     {
@@ -222,6 +223,8 @@ rwt_status check_opts(const rwt_csr* L, const rwt_plan_opts* o) {
                      (o->lanes_per_row & (o->lanes_per_row - 1)) == 0),
                 RWT_ERR_INVALID_ARG, "lanes_per_row must be 0 or a power of two <= 64");
     RWT_REQUIRE(o->block_rows >= 0, RWT_ERR_INVALID_ARG, "negative block_rows");
+    RWT_REQUIRE(o->rhs_chunk >= 0 && o->rhs_chunk <= 4, RWT_ERR_INVALID_ARG,
+                "rhs_chunk must be 0..4");
     return RWT_OK;
 }
 
@@ -245,6 +248,7 @@ SolveArgs make_args(const rwt_plan* p) {
     a.step_pos = p->step_pos;
     a.blk_step = p->blk_step;
     a.lanes = p->lanes;
+    a.kc = p->kc;
     a.ctrl = p->ctrl;
     a.ticks = watchdog_ticks(p->opts.watchdog_ms);
     return a;
@@ -266,23 +270,28 @@ rwt_status run_solve(const rwt_plan* p, bool transposed, Algo algo, const void* 
     }
     RWT_TRY(solve_prepare(a, p->L.dt, s));
     size_t lds = 0;
+    int kg = k;
     if (algo == Algo::SyncFree) {
+        a.kc = std::min(p->kc, k);
+        kg = a.kc;
         a.desc = transposed ? p->desc_t : p->desc_f;
-        a.lds_bytes = syncfree_lds_bytes(p->R, k, p->L.dt);
+        a.lds_bytes = syncfree_lds_bytes(p->R, a.kc, p->L.dt);
         lds = (size_t)a.lds_bytes;
     }
-    unsigned grid = solve_grid(algo, p->L.dt, transposed, k, lds, p->cus);
+    unsigned grid = solve_grid(algo, p->L.dt, transposed, kg, lds, p->cus);
     return solve_launch(a, p->L.dt, algo, transposed, grid, s);
 }
 
-double time_solve(rwt_plan* p, Algo algo, hipStream_t s, int reps) {
+// Median-free timing: best of reps - 1 runs after one warm-up, on kt
+// columns of ones.
+double time_solve(rwt_plan* p, Algo algo, int kt, hipStream_t s, int reps) {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return 1e30;
     if (hipEventCreate(&e1) != hipSuccess) { hipEventDestroy(e0); return 1e30; }
     double best = 1e30;
     for (int r = 0; r < reps; ++r) {
         hipEventRecord(e0, s);
-        rwt_status st = run_solve(p, false, algo, p->xtmp, 1, p->L.n, p->xtmp2, p->L.n, s);
+        rwt_status st = run_solve(p, false, algo, p->xtmp, kt, p->L.n, p->xtmp2, p->L.n, s);
         hipEventRecord(e1, s);
         if (st != RWT_OK || hipEventSynchronize(e1) != hipSuccess) { best = 1e30; break; }
         float ms = 0;
@@ -324,8 +333,12 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
     RWT_REQUIRE(out != nullptr, RWT_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     const int kmax = opts->kmax > 0 ? opts->kmax : 1;
-    const std::vector<int> cands = block_candidates(*opts, L->dt, L->n);
-    int R = cands.front();
+    // right-hand-side chunk candidates (columns per sync-free chain)
+    std::vector<int> kcs;
+    if (opts->rhs_chunk > 0) kcs.push_back(std::min(opts->rhs_chunk, kmax));
+    else if (kmax == 1) kcs.push_back(1);
+    else kcs = {std::min(kmax, 4), 1};
+    int R = block_candidates(*opts, L->dt, L->n, kcs.front()).front();
     PlanPtrs pp;
     const size_t need = carve_plan(nullptr, *L, kmax, &pp);
     RWT_REQUIRE(d_ws != nullptr && ws_bytes >= need, RWT_ERR_BUFFER_TOO_SMALL,
@@ -353,6 +366,7 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
     p->xtmp = pp.xtmp;
     p->xtmp2 = pp.xtmp2;
     p->lanes = opts->lanes_per_row > 0 ? opts->lanes_per_row : default_lanes(L->nnz, L->n);
+    p->kc = kcs.front();
     DeviceInfo di;
     rwt_status st = device_info(&di);
     if (st != RWT_OK) { delete p; return st; }
@@ -446,34 +460,44 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
         RWT_LAUNCHED();
         return RWT_OK;
     };
-    // algorithm and block size: measured on the plan's own matrix unless forced
+    // algorithm, RHS chunk and block size: measured on the plan's own matrix
+    // (with kt = min(kmax, 4) columns) unless forced
     p->fwd = p->bwd = opts->algo == RWT_ALGO_LEVEL ? Algo::Level : Algo::SyncFree;
+    const int kt = std::min(kmax, 4);
     const bool tune_algo = opts->algo == RWT_ALGO_AUTO;
-    const bool tune_R = opts->algo != RWT_ALGO_LEVEL && cands.size() > 1;
-    if (tune_algo || tune_R) {
-        const unsigned g = blocks_for(n, 256, 8192);
+    const bool tune_sf = opts->algo != RWT_ALGO_LEVEL &&
+                         (kcs.size() > 1 || block_candidates(*opts, L->dt, n, kcs.front()).size() > 1);
+    if (tune_algo || tune_sf) {
+        const int64_t nf = (int64_t)n * kt;
+        const unsigned g = blocks_for(nf, 256, 8192);
         if (L->dt == RWT_F64)
             hipLaunchKernelGGL(k_fill_val<double>, dim3(g), dim3(256), 0, s,
-                               static_cast<double*>(p->xtmp), (int64_t)n, 1.0);
+                               static_cast<double*>(p->xtmp), nf, 1.0);
         else
             hipLaunchKernelGGL(k_fill_val<float>, dim3(g), dim3(256), 0, s,
-                               static_cast<float*>(p->xtmp), (int64_t)n, 1.0f);
-        // candidates run from large blocks to small; stop after two in a row
-        // that are more than 10% slower than the best so far
+                               static_cast<float*>(p->xtmp), nf, 1.0f);
+        // per chunk, candidates run from large blocks to small; stop after
+        // two in a row that are more than 10% slower than the best so far
         double best_sf = 1e30;
-        int best_R = cands.front();
-        int worse = 0;
-        for (int Rc : cands) {
-            if ((st = build_blocks(Rc)) != RWT_OK) return fail(st);
-            double ms = time_solve(p, Algo::SyncFree, s, 2);
-            if (ms < best_sf) { best_sf = ms; best_R = Rc; }
-            worse = ms > 1.1 * best_sf ? worse + 1 : 0;
-            if (worse >= 2) break;
+        int best_R = R, best_kc = kcs.front();
+        for (int kc : kcs) {
+            p->kc = kc;
+            double best_here = 1e30;
+            int worse = 0;
+            for (int Rc : block_candidates(*opts, L->dt, n, kc)) {
+                if ((st = build_blocks(Rc)) != RWT_OK) return fail(st);
+                double ms = time_solve(p, Algo::SyncFree, kt, s, 2);
+                if (ms < best_sf) { best_sf = ms; best_R = Rc; best_kc = kc; }
+                if (ms < best_here) best_here = ms;
+                worse = ms > 1.1 * best_here ? worse + 1 : 0;
+                if (worse >= 2) break;
+            }
         }
         p->tuned_sf = best_sf;
         R = best_R;
+        p->kc = best_kc;
         if (tune_algo) {
-            p->tuned_level = time_solve(p, Algo::Level, s, 3);
+            p->tuned_level = time_solve(p, Algo::Level, kt, s, 3);
             if (p->tuned_level >= 1e30 && best_sf >= 1e30) {
                 set_error("autotuning solves failed");
                 return fail(RWT_ERR_DEADLOCK);
@@ -500,8 +524,9 @@ extern "C" rwt_status rwt_plan_get_info(const rwt_plan* p, rwt_plan_info* h) {
     h->lanes_per_row = p->lanes;
     h->narrow_rows = p->opts.narrow_rows;
     h->num_blocks = p->nblocks;
-    h->grid = (int32_t)solve_grid(p->fwd, p->L.dt, false, 1,
-                                  p->fwd == Algo::SyncFree ? syncfree_lds_bytes(p->R, 1, p->L.dt) : 0,
+    h->rhs_chunk = p->kc;
+    h->grid = (int32_t)solve_grid(p->fwd, p->L.dt, false, p->fwd == Algo::SyncFree ? p->kc : 1,
+                                  p->fwd == Algo::SyncFree ? syncfree_lds_bytes(p->R, p->kc, p->L.dt) : 0,
                                   p->cus);
     h->tuned_ms_level = p->tuned_level;
     h->tuned_ms_syncfree = p->tuned_sf;

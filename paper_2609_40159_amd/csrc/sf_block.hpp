@@ -50,7 +50,7 @@ struct SfBlockArgs {
 __host__ __device__ inline int sf_x_bytes(int rows, int k, int s) { return (rows * k * s + 15) & ~15; }
 
 template <typename T, bool TRANS, int KT>
-__device__ void sf_block(const SfBlockArgs& b, unsigned char* s_raw) {
+__device__ __forceinline__ void sf_block(const SfBlockArgs& b, unsigned char* s_raw) {
     const int k = b.k;
     const int32_t r0 = b.r0, r1 = b.r1, sb = b.sb, ns = b.ns;
     T* xs = reinterpret_cast<T*>(s_raw);
@@ -71,6 +71,16 @@ __device__ void sf_block(const SfBlockArgs& b, unsigned char* s_raw) {
     auto value_at = [&](int32_t p) -> T { return TRANS ? vals[b.cmap[p]] : vals[p]; };
 
     for (int32_t u = threadIdx.x; u <= ns; u += blockDim.x) sp[u] = b.step_pos[sb + u] - r0;
+    // the block's right-hand sides, coalesced, into the LDS x area: a row
+    // reads b_i there and overwrites it with x_i (rows of one step never
+    // read each other), so no step waits on a global load of B
+    {
+        const int32_t nr = r1 - r0;
+        for (int32_t e = threadIdx.x; e < nr * k; e += blockDim.x) {
+            const int32_t q = e / nr, i = e - q * nr;
+            xs[i * k + q] = Bg[r0 + i + (int64_t)q * b.ldb];
+        }
+    }
     __syncthreads();
 
     // Loads of future steps are issued by every lane unconditionally (an
@@ -109,6 +119,82 @@ __device__ void sf_block(const SfBlockArgs& b, unsigned char* s_raw) {
         e.diag = d.act ? dd : T(1);
         return e;
     };
+    // acc[tt] += v_p * x[j_p, q0 + tt] over this lane's entries p = p_start,
+    // p_start + G, ... < pe, in ascending p.  The x values of U entries (and
+    // all KT right-hand sides) are loaded together and only then checked, so
+    // one memory latency covers them; a value still marked not ready is
+    // waited for on its own.
+    constexpr int U = 1;   // more entries per round lengthened the common one-entry path
+    auto add_entries = [&](int32_t p_start, int32_t pe, int q0, T(&acc)[KT]) {
+        for (int32_t p0 = p_start; p0 < pe; p0 += U * G) {
+            int32_t jv[U];
+            T vv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t p = p0 + u * G;
+                const bool ok = p < pe;
+                const int32_t pc = ok ? p : p0;   // p0 < pe: always a valid entry
+                const int32_t jj = idx[pc];
+                const T v = value_at(pc);
+                jv[u] = ok ? jj : -1;
+                vv[u] = ok ? v : T(0);
+            }
+            T xv[U][KT];
+            bool miss = false;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool local = TRANS ? (jv[u] < r1) : (jv[u] >= r0);
+#pragma unroll
+                for (int tt = 0; tt < KT; ++tt) {
+                    xv[u][tt] = T(0);
+                    if (jv[u] >= 0 && (KT == 1 || q0 + tt < k))
+                        xv[u][tt] = local ? xs[(jv[u] - r0) * k + q0 + tt]
+                                          : ld_relaxed(&X[jv[u] + (int64_t)(q0 + tt) * b.ldx]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int tt = 0; tt < KT; ++tt) miss = miss || (jv[u] >= 0 && is_sentinel(xv[u][tt]));
+            if (miss) {
+                // rare: poll the values not yet published until all have
+                // arrived (bounded by the watchdog; on expiry the error flag
+                // is set and the missing values count as zero)
+                const int64_t t0 = wall_clock64();
+                for (;;) {
+                    bool still = false;
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+#pragma unroll
+                        for (int tt = 0; tt < KT; ++tt)
+                            if (jv[u] >= 0 && is_sentinel(xv[u][tt])) {
+                                xv[u][tt] = ld_relaxed(&X[jv[u] + (int64_t)(q0 + tt) * b.ldx]);
+                                still = still || is_sentinel(xv[u][tt]);
+                            }
+                    if (!still) break;
+                    const bool expired = wall_clock64() - t0 > b.ticks;
+                    if (expired)
+                        __hip_atomic_store(err, (int32_t)RWT_ERR_DEADLOCK, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    if (expired || ld_relaxed(err) != 0) {
+#pragma unroll
+                        for (int u = 0; u < U; ++u)
+#pragma unroll
+                            for (int tt = 0; tt < KT; ++tt)
+                                if (is_sentinel(xv[u][tt])) xv[u][tt] = T(0);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(0);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int tt = 0; tt < KT; ++tt)
+                    if (jv[u] >= 0 && (KT == 1 || q0 + tt < k)) acc[tt] += vv[u] * xv[u][tt];
+        }
+    };
+
     // A row solved without pipelining (rows beyond one per group, right-hand
     // sides beyond the first KT): all lanes of the wave call this together.
     auto solve_inline = [&](const SfDesc& d, const SfEnt<T>& e, int q_begin) {
@@ -118,23 +204,9 @@ __device__ void sf_block(const SfBlockArgs& b, unsigned char* s_raw) {
             for (int tt = 0; tt < KT; ++tt) {
                 acc[tt] = T(0);
                 bq[tt] = T(0);
-                if (d.act && gl == 0 && (KT == 1 || q0 + tt < k))
-                    bq[tt] = Bg[d.i + (int64_t)(q0 + tt) * b.ldb];
+                if (d.act && gl == 0 && (KT == 1 || q0 + tt < k)) bq[tt] = xs[(d.i - r0) * k + q0 + tt];
             }
-            auto add_entry = [&](int32_t j, T v) {
-                const bool local = TRANS ? (j < r1) : (j >= r0);
-#pragma unroll
-                for (int tt = 0; tt < KT; ++tt) {
-                    const int q = q0 + tt;
-                    if (KT == 1 || q < k) {
-                        T xj = local ? xs[(j - r0) * k + q]
-                                     : wait_value(&X[j + (int64_t)q * b.ldx], err, b.ticks);
-                        acc[tt] += v * xj;
-                    }
-                }
-            };
-            if (e.j >= 0) add_entry(e.j, e.v);
-            for (int32_t p = d.pb + gl + G; p < d.pe; p += G) add_entry(idx[p], value_at(p));
+            add_entries(d.pb + gl, d.pe, q0, acc);
 #pragma unroll
             for (int tt = 0; tt < KT; ++tt) acc[tt] = group_sum(acc[tt], G);
             if (d.act && gl == 0) {
@@ -152,7 +224,7 @@ __device__ void sf_block(const SfBlockArgs& b, unsigned char* s_raw) {
     };
 
     // Pipelined level loop.  Per step, in this order: (1) load the x
-    // values of the row's first entry and its right-hand side, (2) publish
+    // values of the row's first entry (and b_i from LDS), (2) publish
     // the previous step's results, (3) load the data of the next steps,
     // (4) wait for (1) only.  Vector-memory counters retire in order, so
     // anything issued after (1) is not waited for by (4).
@@ -176,7 +248,7 @@ __device__ void sf_block(const SfBlockArgs& b, unsigned char* s_raw) {
             if (KT == 1 || tt < k) {
                 if (have) xv[tt] = loc ? xs[(ec.j - r0) * k + tt]
                                        : ld_relaxed(&X[ec.j + (int64_t)tt * b.ldx]);
-                if (dc.act && gl == 0) bq[tt] = Bg[dc.i + (int64_t)tt * b.ldb];
+                if (dc.act && gl == 0) bq[tt] = xs[(dc.i - r0) * k + tt];
             }
         }
         // (2)
@@ -200,16 +272,7 @@ __device__ void sf_block(const SfBlockArgs& b, unsigned char* s_raw) {
                 if (have) acc[tt] = ec.v * xv[tt];
             }
         }
-        for (int32_t p = dc.pb + gl + G; p < dc.pe; p += G) {
-            const int32_t j = idx[p];
-            const T v = value_at(p);
-            const bool local = TRANS ? (j < r1) : (j >= r0);
-#pragma unroll
-            for (int tt = 0; tt < KT; ++tt)
-                if (KT == 1 || tt < k)
-                    acc[tt] += v * (local ? xs[(j - r0) * k + tt]
-                                          : wait_value(&X[j + (int64_t)tt * b.ldx], err, b.ticks));
-        }
+        add_entries(dc.pb + gl + G, dc.pe, 0, acc);
 #pragma unroll
         for (int tt = 0; tt < KT; ++tt) acc[tt] = group_sum(acc[tt], G);
         if (dc.act && gl == 0) {

@@ -209,13 +209,23 @@ __global__ void __launch_bounds__(SV_THREADS) k_solve_sf(SolveArgs a) {
     b.err = &a.ctrl->err;
     b.ticks = a.ticks;
     b.lds_rows = a.block_rows;
+    // tasks: (row block, column chunk) with the chunks of one block on
+    // consecutive tickets; each chunk's blocks follow row order (reverse for
+    // the transposed solve), so a task waits only on earlier tickets
+    const int32_t nch = (a.k + a.kc - 1) / a.kc;
+    const int64_t ntask = (int64_t)a.nblocks * nch;
     for (;;) {
         if (threadIdx.x == 0) s_blk = (int32_t)fetch_add(&a.ctrl->ticket, 1u);
         __syncthreads();
-        const int32_t t = s_blk;
+        const int64_t t = (uint32_t)s_blk;
         __syncthreads();
-        if (t >= a.nblocks) break;
-        const int32_t blk = TRANS ? a.nblocks - 1 - t : t;
+        if (t >= ntask) break;
+        const int32_t tb = (int32_t)(t / nch), c = (int32_t)(t - (int64_t)tb * nch);
+        const int32_t blk = TRANS ? a.nblocks - 1 - tb : tb;
+        const int32_t q0 = c * a.kc;
+        b.k = min(a.kc, a.k - q0);
+        b.B = static_cast<const T*>(a.B) + (int64_t)q0 * a.ldb;
+        b.X = static_cast<T*>(a.X) + (int64_t)q0 * a.ldx;
         b.r0 = blk * a.block_rows;
         b.r1 = min(a.n, b.r0 + a.block_rows);
         b.sb = a.blk_step[blk];
@@ -227,7 +237,7 @@ __global__ void __launch_bounds__(SV_THREADS) k_solve_sf(SolveArgs a) {
 
 template <typename T, bool TRANS>
 rwt_status launch_typed(const SolveArgs& a, Algo algo, unsigned grid, hipStream_t s) {
-    const bool multi = a.k > 1;
+    const bool multi = (algo == Algo::Level ? a.k : a.kc) > 1;
     if (algo == Algo::Level) {
         if (multi)
             hipLaunchKernelGGL((k_solve_level<T, TRANS, 4>), dim3(grid), dim3(SV_THREADS), 0, s, a);

@@ -31,6 +31,7 @@ struct SolveArgs {
     void* X;
     int64_t ldx;
     int32_t k;
+    int32_t kc;                // sync-free: right-hand sides per chain (1..4)
     int32_t lanes;             // lanes per row (power of two, 1..64)
     const int4* desc;          // sync-free: per row in bperm order {row, first, end, diagonal}
     int32_t lds_bytes;         // sync-free: dynamic LDS per workgroup
@@ -47,7 +48,8 @@ rwt_status solve_launch(const SolveArgs& a, rwt_dtype dt, Algo algo, bool transp
 // LDS of one sync-free workgroup: the block's x values and its step starts
 int syncfree_lds_bytes(int block_rows, int k, rwt_dtype dt);
 constexpr int SF_LDS_BUDGET = 60 * 1024;
-// workgroups of a persistent solve launch (all resident)
+// workgroups of a persistent solve launch (all resident); k: columns per
+// chain (sync-free) or per launch (level-scheduled)
 unsigned solve_grid(Algo algo, rwt_dtype dt, bool transposed, int k, size_t lds, int cus);
 
 }  // namespace rwt

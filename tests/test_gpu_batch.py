@@ -169,7 +169,7 @@ def test_batch_solve_bitwise_equals_single_plan(orc):
     for i, ((name, L, k), (G, Bd, Xd)) in enumerate(zip(mats, gm)):
         pi = bt.plan_info(i)
         p = Plan(G, algo="syncfree", kmax=k, block_rows=pi["block_rows"],
-                 lanes_per_row=pi["lanes_per_row"])
+                 lanes_per_row=pi["lanes_per_row"], rhs_chunk=pi["rhs_chunk"])
         X1 = p.solve(Bd)
         assert torch.equal(X1, Xd), name
 

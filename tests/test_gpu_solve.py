@@ -79,3 +79,53 @@ def test_solve_full_size_3d_128(orc, dt):
         X = plan.solve(block(B, dt))
         plan.check()
         assert relerr(host(X).astype(np.float64), ref) <= TOL[dt]
+
+
+@pytest.mark.parametrize("block_rows", [64, 2048])
+def test_solve_rhs_chunks_agree(orc, block_rows):
+    """Right-hand sides split into chains of 1 or 4 columns (the last one
+    ragged): identical results, forward and transposed."""
+    from paper_2609_40159_amd.api import Plan
+    L = synth.power_law(20000, 22)
+    xs, B = synth.rhs(L, 6, 8)
+    ref = orc.solve(L.n, L.rowptr, L.colidx, L.vals, B)
+    refT = orc.solve_transpose(L.n, L.rowptr, L.colidx, L.vals, B)
+    G = to_gpu(L)
+    out = {}
+    for kc in (1, 4):
+        plan = Plan(G, algo="syncfree", kmax=6, block_rows=block_rows, rhs_chunk=kc)
+        assert plan.info["rhs_chunk"] == kc
+        X = plan.solve(block(B))
+        Y = plan.solve_transpose(block(B))
+        plan.check()
+        assert relerr(host(X), ref) <= 1e-12 and relerr(host(X), xs) <= 1e-12
+        assert relerr(host(Y), refT) <= 1e-12
+        out[kc] = (X, Y)
+    assert torch.equal(out[1][0], out[4][0]) and torch.equal(out[1][1], out[4][1])
+    # fewer columns than the chunk, and a tuned plan
+    plan = Plan(G, algo="auto", kmax=6)
+    assert plan.info["rhs_chunk"] in (1, 4)
+    X2 = plan.solve(block(B[:2]))
+    assert relerr(host(X2), ref[:2]) <= 1e-12
+
+
+def test_solve_full_size_powerlaw_1m_64rhs(orc):
+    """Power-law n = 1M, 64 right-hand sides, 0.8% of rows rewritten
+    (thin-first): the rewritten system solved with the tuned plan, checked
+    element by element against the oracle's solve of the same system."""
+    from paper_2609_40159_amd.api import Plan, analyze, rewrite
+    spec = synth.WORKLOADS["powerlaw_1m"]
+    L = synth.build_matrix(spec)
+    xs, B = synth.rhs(L, spec["k"], spec["seed"])
+    a = orc.analyze(L.n, L.rowptr, L.colidx)
+    rows, targets = synth.thin_first_rows(a.level, spec["frac"])
+    ro = orc.rewrite(L.n, L.rowptr, L.colidx, L.vals, a.level, rows, targets, B)
+    ref = orc.solve(L.n, ro.rowptr, ro.colidx, ro.vals, ro.Bp)
+    G = to_gpu(L)
+    rw = rewrite(G, analyze(G).level, rows, targets, block(B))
+    assert np.array_equal(host(rw.L.colidx), ro.colidx)
+    plan = Plan(rw.L, algo="auto", kmax=spec["k"])
+    X = plan.solve(rw.B)
+    plan.check()
+    assert relerr(host(X), ref) <= 1e-12
+    assert relerr(host(X), xs) <= 1e-10      # the rewritten system, against x*
