@@ -259,6 +259,19 @@ rwt_status rwt_apply_MT(int32_t n, int64_t nC, const int32_t* d_crow, const int3
                         const void* d_cval, rwt_dtype dt, const void* d_Y, int32_t k, int64_t ldy,
                         void* d_out, int64_t ldo, void* d_ws, size_t ws_bytes,
                         rwt_stream_t stream);
+/* The two halves of rwt_apply_MT, for repeated use with one multiplier
+ * pattern (the pattern of C is structural: it does not change when the
+ * rewrite's numeric part is re-run).  rwt_apply_MT_prepare builds the C^T
+ * ordering from d_ccol into the workspace; rwt_apply_MT_apply then applies
+ * Y - C^T Y with any values d_cval, reading that ordering.  Same sizes,
+ * errors and workspace (rwt_apply_MT_ws bytes) as rwt_apply_MT; the caller
+ * keeps the workspace untouched between the two. */
+rwt_status rwt_apply_MT_prepare(int32_t n, int64_t nC, const int32_t* d_ccol, void* d_ws,
+                                size_t ws_bytes, rwt_stream_t stream);
+rwt_status rwt_apply_MT_apply(int32_t n, int64_t nC, const int32_t* d_crow, const void* d_cval,
+                              rwt_dtype dt, const void* d_Y, int32_t k, int64_t ldy, void* d_out,
+                              int64_t ldo, const void* d_ws, size_t ws_bytes,
+                              rwt_stream_t stream);
 rwt_status rwt_grad_vals(const rwt_csr* L, const void* d_gB, int64_t ldg, const void* d_X,
                          int64_t ldx, int32_t k, void* d_gvals, rwt_stream_t stream);
 

@@ -114,6 +114,8 @@ SIGNATURES = {
     "rwt_plan_check": (C.c_int, [P, P]),
     "rwt_apply_MT_ws": (C.c_int, [I32, I64, C.POINTER(SZ)]),
     "rwt_apply_MT": (C.c_int, [I32, I64, P, P, P, I32, P, I32, I64, P, I64, P, SZ, P]),
+    "rwt_apply_MT_prepare": (C.c_int, [I32, I64, P, P, SZ, P]),
+    "rwt_apply_MT_apply": (C.c_int, [I32, I64, P, P, I32, P, I32, I64, P, I64, P, SZ, P]),
     "rwt_grad_vals": (C.c_int, [C.POINTER(Csr), P, I64, P, I64, I32, P, P]),
     "rwt_batch_ws": (C.c_int, [C.POINTER(BatchDesc), C.POINTER(SZ)]),
     "rwt_batch_create": (C.c_int, [C.POINTER(BatchDesc), P, SZ, C.POINTER(P), P]),

@@ -138,6 +138,9 @@ class Rewrite:
     cval: torch.Tensor
     cptr: torch.Tensor        # offsets of each set row's substitutions
     skipped: int
+    # C^T ordering for apply_MT, built on first use (the pattern of C does
+    # not change when the numeric rewrite is re-run)
+    mt_ws: torch.Tensor | None = None
 
 
 def _block(B: torch.Tensor | None, n: int, dtype) -> tuple[torch.Tensor | None, int]:
@@ -300,12 +303,16 @@ def apply_MT(rw: Rewrite, Y: torch.Tensor) -> torch.Tensor:
     n = rw.L.n
     Y2, k = _block(Y, n, rw.L.dtype)
     nc = rw.crow.numel()
-    sz = C.c_size_t(0)
-    check(lib.rwt_apply_MT_ws(n, nc, C.byref(sz)))
-    ws = _workspace(sz.value, Y.device)
+    if rw.mt_ws is None:
+        sz = C.c_size_t(0)
+        check(lib.rwt_apply_MT_ws(n, nc, C.byref(sz)))
+        ws = _workspace(sz.value, Y.device)
+        check(lib.rwt_apply_MT_prepare(n, nc, _ptr(rw.ccol), _ptr(ws), ws.numel(), _stream()))
+        rw.mt_ws = ws
+    ws = rw.mt_ws
     out = torch.empty_like(Y2)
-    check(lib.rwt_apply_MT(n, nc, _ptr(rw.crow), _ptr(rw.ccol), _ptr(rw.cval), _dt(rw.L.dtype),
-                           _ptr(Y2), k, n, _ptr(out), n, _ptr(ws), ws.numel(), _stream()))
+    check(lib.rwt_apply_MT_apply(n, nc, _ptr(rw.crow), _ptr(rw.cval), _dt(rw.L.dtype), _ptr(Y2), k,
+                                 n, _ptr(out), n, _ptr(ws), ws.numel(), _stream()))
     return out.reshape(Y.shape)
 
 

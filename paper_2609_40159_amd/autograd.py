@@ -32,6 +32,8 @@ class TriangularSolve:
         if rows is not None:
             self.rw = Rewriter(self.L, self.info.level, rows, targets)
             self.rw.numeric(None, None)
+            # multipliers of the rewrite; their C^T ordering is built once
+            self.rwres = self.rw.result()
             self.plan = Plan(self.rw.Lp, algo=algo, kmax=kmax, **plan_opts)
         else:
             self.plan = Plan(self.L, algo=algo, kmax=kmax, **plan_opts)
@@ -60,7 +62,7 @@ class TriangularSolve:
         if vals is not None:
             self._load(vals)
         Y = self.plan.solve_transpose(G.contiguous())
-        gB = apply_MT(self.rw.result(), Y) if self.rw is not None else Y
+        gB = apply_MT(self.rwres, Y) if self.rw is not None else Y
         gV = grad_vals(self.L, gB, X)
         return gV, gB
 

@@ -118,22 +118,21 @@ extern "C" rwt_status rwt_apply_MT_ws(int32_t n, int64_t nC, size_t* h_bytes) {
     return RWT_OK;
 }
 
-extern "C" rwt_status rwt_apply_MT(int32_t n, int64_t nC, const int32_t* d_crow,
-                                   const int32_t* d_ccol, const void* d_cval, rwt_dtype dt,
-                                   const void* d_Y, int32_t k, int64_t ldy, void* d_out,
-                                   int64_t ldo, void* d_ws, size_t ws_bytes, rwt_stream_t stream) {
-    RWT_REQUIRE(n >= 0 && nC >= 0 && k >= 0, RWT_ERR_INVALID_ARG, "negative size");
+static rwt_status mt_checks(int32_t n, int64_t nC, size_t ws_bytes, const void* d_ws) {
+    RWT_REQUIRE(n >= 0 && nC >= 0, RWT_ERR_INVALID_ARG, "negative size");
     RWT_REQUIRE(nC < (int64_t(1) << 31), RWT_ERR_TOO_LARGE, "too many multipliers");
-    RWT_REQUIRE(dt == RWT_F64 || dt == RWT_F32, RWT_ERR_INVALID_ARG, "bad dtype");
-    RWT_REQUIRE(nC == 0 || (d_crow && d_ccol && d_cval), RWT_ERR_INVALID_ARG, "null multipliers");
-    RWT_REQUIRE(k == 0 || (d_Y && d_out && ldy >= n && ldo >= n), RWT_ERR_INVALID_ARG,
-                "bad dense blocks");
-    RWT_REQUIRE(k == 0 || d_Y != d_out, RWT_ERR_INVALID_ARG, "output may not alias Y");
     MtWs w;
     size_t need = carve_mt(nullptr, n, nC, &w);
     RWT_REQUIRE(d_ws != nullptr && ws_bytes >= need, RWT_ERR_BUFFER_TOO_SMALL,
                 "apply_MT workspace must hold %zu bytes", need);
-    if (n == 0 || k == 0) return RWT_OK;
+    return RWT_OK;
+}
+
+extern "C" rwt_status rwt_apply_MT_prepare(int32_t n, int64_t nC, const int32_t* d_ccol,
+                                           void* d_ws, size_t ws_bytes, rwt_stream_t stream) {
+    RWT_TRY(mt_checks(n, nC, ws_bytes, d_ws));
+    RWT_REQUIRE(nC == 0 || d_ccol, RWT_ERR_INVALID_ARG, "null multiplier columns");
+    MtWs w;
     carve_mt(d_ws, n, nC, &w);
     hipStream_t s = hs(stream);
     if (nC > 0) {
@@ -142,7 +141,25 @@ extern "C" rwt_status rwt_apply_MT(int32_t n, int64_t nC, const int32_t* d_crow,
         RWT_LAUNCHED();
         RWT_TRY(radix_sort(w.keys, w.vals, w.tkeys, w.tvals, nC, bits_for((uint64_t)n), w.rws, s));
     }
-    RWT_TRY(segment_starts(w.keys, nC, n, w.ptr, nullptr, s));
+    if (n > 0) RWT_TRY(segment_starts(w.keys, nC, n, w.ptr, nullptr, s));
+    return RWT_OK;
+}
+
+extern "C" rwt_status rwt_apply_MT_apply(int32_t n, int64_t nC, const int32_t* d_crow,
+                                         const void* d_cval, rwt_dtype dt, const void* d_Y,
+                                         int32_t k, int64_t ldy, void* d_out, int64_t ldo,
+                                         const void* d_ws, size_t ws_bytes, rwt_stream_t stream) {
+    RWT_TRY(mt_checks(n, nC, ws_bytes, d_ws));
+    RWT_REQUIRE(k >= 0, RWT_ERR_INVALID_ARG, "negative k");
+    RWT_REQUIRE(dt == RWT_F64 || dt == RWT_F32, RWT_ERR_INVALID_ARG, "bad dtype");
+    RWT_REQUIRE(nC == 0 || (d_crow && d_cval), RWT_ERR_INVALID_ARG, "null multipliers");
+    RWT_REQUIRE(k == 0 || (d_Y && d_out && ldy >= n && ldo >= n), RWT_ERR_INVALID_ARG,
+                "bad dense blocks");
+    RWT_REQUIRE(k == 0 || d_Y != d_out, RWT_ERR_INVALID_ARG, "output may not alias Y");
+    if (n == 0 || k == 0) return RWT_OK;
+    MtWs w;
+    carve_mt(const_cast<void*>(d_ws), n, nC, &w);
+    hipStream_t s = hs(stream);
     const unsigned g = blocks_for((size_t)n * k, 256, 8192);
     if (dt == RWT_F64)
         hipLaunchKernelGGL(k_apply_mt<double>, dim3(g), dim3(256), 0, s, w.ptr, w.vals, d_crow,
@@ -154,6 +171,23 @@ extern "C" rwt_status rwt_apply_MT(int32_t n, int64_t nC, const int32_t* d_crow,
                            static_cast<float*>(d_out), ldo, n, k);
     RWT_LAUNCHED();
     return RWT_OK;
+}
+
+extern "C" rwt_status rwt_apply_MT(int32_t n, int64_t nC, const int32_t* d_crow,
+                                   const int32_t* d_ccol, const void* d_cval, rwt_dtype dt,
+                                   const void* d_Y, int32_t k, int64_t ldy, void* d_out,
+                                   int64_t ldo, void* d_ws, size_t ws_bytes, rwt_stream_t stream) {
+    RWT_TRY(mt_checks(n, nC, ws_bytes, d_ws));
+    RWT_REQUIRE(k >= 0, RWT_ERR_INVALID_ARG, "negative k");
+    RWT_REQUIRE(dt == RWT_F64 || dt == RWT_F32, RWT_ERR_INVALID_ARG, "bad dtype");
+    RWT_REQUIRE(nC == 0 || (d_crow && d_ccol && d_cval), RWT_ERR_INVALID_ARG, "null multipliers");
+    RWT_REQUIRE(k == 0 || (d_Y && d_out && ldy >= n && ldo >= n), RWT_ERR_INVALID_ARG,
+                "bad dense blocks");
+    RWT_REQUIRE(k == 0 || d_Y != d_out, RWT_ERR_INVALID_ARG, "output may not alias Y");
+    if (n == 0 || k == 0) return RWT_OK;
+    RWT_TRY(rwt_apply_MT_prepare(n, nC, d_ccol, d_ws, ws_bytes, stream));
+    return rwt_apply_MT_apply(n, nC, d_crow, d_cval, dt, d_Y, k, ldy, d_out, ldo, d_ws, ws_bytes,
+                              stream);
 }
 
 extern "C" rwt_status rwt_grad_vals(const rwt_csr* L, const void* d_gB, int64_t ldg,

@@ -486,6 +486,7 @@ struct rwt_batch {
     int32_t* pat_ptr = nullptr;
     int32_t* pat = nullptr;
     int32_t* ovf = nullptr;
+    int32_t* ovf2 = nullptr;
     unsigned char* ovf_mark = nullptr;
     int32_t* rwctrl = nullptr;
     unsigned char* slab = nullptr;
@@ -516,7 +517,7 @@ rwt_plan_opts batch_plan_opts(const rwt_batch_desc* d, const rwt_batch_matrix& m
 
 struct BatchLayout {
     std::vector<size_t> plan_off, plan_bytes;
-    size_t mats, cands, candmat, rwmats, tasks, bitmaps, levs, done, bad, stats, counts, patptr, pat, ovf,
+    size_t mats, cands, candmat, rwmats, tasks, bitmaps, levs, done, bad, stats, counts, patptr, pat, ovf, ovf2,
         ovfmark, rwctrl, slab, scan, ctrl, epoch, blkmin, total;
     int64_t bitmap_words, lev_words, slab_stride;
     int32_t qcap, pat_cap, slab_cap, ntasks_max;
@@ -594,6 +595,7 @@ rwt_status layout_batch(const rwt_batch_desc* d, BatchLayout* L) {
     L->patptr = take(sizeof(int32_t) * ((size_t)L->qcap + 1));
     L->pat = take(sizeof(int32_t) * (size_t)L->pat_cap);
     L->ovf = take(sizeof(int32_t) * std::max(1, L->qcap));
+    L->ovf2 = take(sizeof(int32_t) * std::max(1, L->qcap));
     L->ovfmark = take(std::max(1, L->qcap));
     L->rwctrl = take(sizeof(int32_t) * 8);
     L->slab = take((size_t)NSLAB_B * (size_t)L->slab_stride);
@@ -643,6 +645,7 @@ rwt_status enqueue_run(rwt_batch* b, hipStream_t s) {
         ra.pat = b->pat;
         ra.pat_cap = b->pat_cap;
         ra.ovf = b->ovf;
+        ra.ovf2 = b->ovf2;
         ra.ovf_mark = b->ovf_mark;
         ra.ctrl = b->rwctrl;
         ra.cand_bad = b->cand_bad;
@@ -763,6 +766,7 @@ extern "C" rwt_status rwt_batch_create(const rwt_batch_desc* desc, void* d_ws, s
     b->pat_ptr = at<int32_t>(d_ws, L.patptr);
     b->pat = at<int32_t>(d_ws, L.pat);
     b->ovf = at<int32_t>(d_ws, L.ovf);
+    b->ovf2 = at<int32_t>(d_ws, L.ovf2);
     b->ovf_mark = at<unsigned char>(d_ws, L.ovfmark);
     b->rwctrl = at<int32_t>(d_ws, L.rwctrl);
     b->slab = at<unsigned char>(d_ws, L.slab);

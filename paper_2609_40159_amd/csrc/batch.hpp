@@ -27,7 +27,8 @@ struct BatchRwArgs {
     const int32_t* pat_ptr;     // device, qcap + 1
     int32_t* pat;               // device, pat_cap
     int32_t pat_cap;
-    int32_t* ovf;               // device, qcap
+    int32_t* ovf;               // device, qcap: positions over the small LDS tier
+    int32_t* ovf2;              // device, qcap: positions over the large LDS tier
     unsigned char* ovf_mark;    // device, qcap
     int32_t* ctrl;              // device, 8 ints
     unsigned char* cand_bad;    // device, C: candidate row list rejected

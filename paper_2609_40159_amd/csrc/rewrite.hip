@@ -29,10 +29,20 @@ namespace rwt {
 
 namespace {
 
-constexpr int RW_WAVES = 2;                // waves per workgroup
-constexpr int RW_CAP = 640;                // accumulator capacity in LDS (entries)
-constexpr int RW_CAPB = 640;               // row-j capacity in LDS (entries)
+// Rows are rewritten by one wave each with the accumulator in LDS, in two
+// capacity tiers: most rows fit the small tier, whose low LDS use keeps
+// many waves resident; rows that overflow it retry in the large tier, and
+// rows that overflow that one use workspace slabs in global memory.
+constexpr int RW_CAP1 = 128;               // small tier: entries per accumulator / staged row
+constexpr int RW_WAVES1 = 4;               // small tier: waves per workgroup
+constexpr int RW_CAP2 = 640;               // large tier
+constexpr int RW_WAVES2 = 2;
 constexpr int NSLAB = 2;                   // concurrent fallback rows
+
+// LDS bytes of one wave's buffers at capacity CAP (value size S)
+constexpr int rw_wave_bytes(int CAP, int S) {
+    return 2 * CAP * (4 + S + 1) + CAP * (4 + S) + (CAP + 1) * 4 + CAP + 64;
+}
 
 struct Bufs {
     int32_t* acol[2];
@@ -59,9 +69,11 @@ struct RwArgs {
     int32_t* counts;          // n (+1 for the scan total)
     int32_t* csub;            // m (+1)
     unsigned char* rewritten; // n
-    int32_t* ovf;             // overflow list (set indices)
-    unsigned char* ovf_mark;  // m: row overflowed the LDS capacity
-    int32_t* ctrl;            // [0] overflow count, [1] skipped, [2] error, [3] too-large
+    int32_t* ovf;             // rows that overflowed the small LDS tier (set indices)
+    int32_t* ovf2;            // rows that overflowed the large LDS tier
+    unsigned char* ovf_mark;  // m: 0 small tier, 1 large tier, 2 slab
+    int32_t* ctrl;            // [0] overflow count, [1] skipped, [2] error, [3] too-large,
+                              // [4] capacity mismatch, [5] second overflow count
     // numeric inputs / outputs
     const int32_t* rowptr_out;
     int32_t* colidx_out;
@@ -210,9 +222,10 @@ __device__ bool rewrite_row(const RwArgs& a, int32_t q, const Bufs& bf) {
         const int32_t nlen = alen - 1 + run;
         if (nlen > bf.cap) return false;
         const int nxt = cur ^ 1;
-        int32_t* ocol = bf.acol[nxt];
-        T* oval = reinterpret_cast<T*>(bf.aval[nxt]);
-        unsigned char* oelig = bf.aelig[nxt];
+        // select, not index: a dynamically indexed pointer array would live in scratch
+        int32_t* ocol = nxt ? bf.acol[1] : bf.acol[0];
+        T* oval = reinterpret_cast<T*>(nxt ? bf.aval[1] : bf.aval[0]);
+        unsigned char* oelig = nxt ? bf.aelig[1] : bf.aelig[0];
         // accumulator entries (except j)
         for (int32_t p = lane; p < alen; p += WAVE) {
             if (p == jpos) continue;
@@ -281,15 +294,9 @@ __device__ __forceinline__ bool row_is_noop(const RwArgs& a, int32_t q) {
     return lv == 0 || t >= lv;
 }
 
-template <typename T, bool NUMERIC>
-__global__ void __launch_bounds__(RW_WAVES * WAVE) k_rewrite_lds(RwArgs a) {
-    constexpr int S = sizeof(T);
-    // per wave: 2 accumulators (col, val, elig), row j (col, val), prefix, dup flags
-    constexpr int PER_WAVE = 2 * RW_CAP * (4 + S + 1) + RW_CAPB * (4 + S) + (RW_CAPB + 1) * 4 +
-                             RW_CAPB + 64;
-    __shared__ __align__(16) unsigned char s_buf[RW_WAVES * PER_WAVE];
-    const int w = threadIdx.x / WAVE;
-    unsigned char* base = s_buf + w * PER_WAVE;
+// Carve one wave's buffers (capacity CAP entries) from base.
+template <int CAP, int S>
+__device__ __forceinline__ Bufs carve_bufs(unsigned char* base) {
     Bufs bf;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -298,32 +305,56 @@ __global__ void __launch_bounds__(RW_WAVES * WAVE) k_rewrite_lds(RwArgs a) {
         return p;
     };
     for (int i = 0; i < 2; ++i) {
-        bf.acol[i] = reinterpret_cast<int32_t*>(take(RW_CAP * 4));
-        bf.aval[i] = reinterpret_cast<double*>(take(RW_CAP * S));
-        bf.aelig[i] = take(RW_CAP);
+        bf.acol[i] = reinterpret_cast<int32_t*>(take(CAP * 4));
+        bf.aval[i] = reinterpret_cast<double*>(take(CAP * S));
+        bf.aelig[i] = take(CAP);
     }
-    bf.bcol = reinterpret_cast<int32_t*>(take(RW_CAPB * 4));
-    bf.bval = reinterpret_cast<double*>(take(RW_CAPB * S));
-    bf.nd = reinterpret_cast<int32_t*>(take((RW_CAPB + 1) * 4));
-    bf.bdup = take(RW_CAPB);
-    bf.cap = RW_CAP;
-    bf.capb = RW_CAPB;
-    const int64_t wave = (int64_t)blockIdx.x * RW_WAVES + w;
-    const int64_t nw = (int64_t)gridDim.x * RW_WAVES;
-    for (int64_t q = wave; q < a.m; q += nw) {
-        if (row_is_noop(a, (int32_t)q)) {
+    bf.bcol = reinterpret_cast<int32_t*>(take(CAP * 4));
+    bf.bval = reinterpret_cast<double*>(take(CAP * S));
+    bf.nd = reinterpret_cast<int32_t*>(take((CAP + 1) * 4));
+    bf.bdup = take(CAP);
+    bf.cap = CAP;
+    bf.capb = CAP;
+    return bf;
+}
+
+// TIER 1: every set position; a row that overflows goes to the first
+// overflow list (mark 1).  TIER 2: the rows of the first list; a row that
+// overflows again goes to the second list (mark 2) for the slabs.  The
+// numeric pass follows the marks the symbolic pass left.
+template <typename T, bool NUMERIC, int TIER>
+__global__ void __launch_bounds__((TIER == 1 ? RW_WAVES1 : RW_WAVES2) * WAVE) k_rewrite_lds(RwArgs a) {
+    constexpr int S = sizeof(T);
+    constexpr int CAP = TIER == 1 ? RW_CAP1 : RW_CAP2;
+    constexpr int WAVES = TIER == 1 ? RW_WAVES1 : RW_WAVES2;
+    constexpr int PER_WAVE = rw_wave_bytes(CAP, S);
+    __shared__ __align__(16) unsigned char s_buf[WAVES * PER_WAVE];
+    const int w = threadIdx.x / WAVE;
+    const Bufs bf = carve_bufs<CAP, S>(s_buf + w * PER_WAVE);
+    const int64_t wave = (int64_t)blockIdx.x * WAVES + w;
+    const int64_t nw = (int64_t)gridDim.x * WAVES;
+    const int64_t count = TIER == 1 ? a.m : a.ctrl[0];
+    for (int64_t idx = wave; idx < count; idx += nw) {
+        const int32_t q = TIER == 1 ? (int32_t)idx : a.ovf[idx];
+        if (TIER == 1 && row_is_noop(a, q)) {
             if (!NUMERIC && lane_id() == 0) {
                 atomicAdd(&a.ctrl[1], 1);
                 a.csub[q] = 0;
             }
             continue;
         }
-        if (NUMERIC && a.ovf_mark[q]) continue;
-        bool ok = rewrite_row<T, NUMERIC>(a, (int32_t)q, bf);
+        if (NUMERIC && a.ovf_mark[q] >= TIER) continue;
+        const bool ok = rewrite_row<T, NUMERIC>(a, q, bf);
         if (!ok && !NUMERIC && lane_id() == 0) {
-            int slot = atomicAdd(&a.ctrl[0], 1);
-            a.ovf[slot] = (int32_t)q;
-            a.ovf_mark[q] = 1;
+            if (TIER == 1) {
+                const int slot = atomicAdd(&a.ctrl[0], 1);
+                a.ovf[slot] = q;
+                a.ovf_mark[q] = 1;
+            } else {
+                const int slot = atomicAdd(&a.ctrl[5], 1);
+                a.ovf2[slot] = q;
+                a.ovf_mark[q] = 2;
+            }
         }
     }
 }
@@ -332,7 +363,7 @@ __global__ void __launch_bounds__(RW_WAVES * WAVE) k_rewrite_lds(RwArgs a) {
 // workspace slab large enough for any row (n + 1 entries).
 template <typename T, bool NUMERIC>
 __global__ void __launch_bounds__(WAVE) k_rewrite_slab(RwArgs a) {
-    const int32_t cnt = a.ctrl[0];
+    const int32_t cnt = a.ctrl[5];
     const int S = sizeof(T);
     for (int32_t s = blockIdx.x; s < cnt; s += gridDim.x) {
         unsigned char* base = a.slab + (int64_t)blockIdx.x * a.slab_stride;
@@ -355,7 +386,7 @@ __global__ void __launch_bounds__(WAVE) k_rewrite_slab(RwArgs a) {
         bf.bdup = take(cap);
         bf.cap = (int32_t)cap;
         bf.capb = (int32_t)cap;
-        const int32_t q = a.ovf[s];
+        const int32_t q = a.ovf2[s];
         if (!rewrite_row<T, NUMERIC>(a, q, bf) && lane_id() == 0) atomicExch(&a.ctrl[3], 1);
     }
 }
@@ -430,6 +461,7 @@ struct RwWs {
     int32_t* cptr;
     unsigned char* rewritten;
     int32_t* ovf;
+    int32_t* ovf2;
     unsigned char* ovf_mark;
     int32_t* ctrl;
     void* scan;
@@ -445,6 +477,7 @@ size_t carve_rw(void* base, int32_t n, int32_t m, rwt_dtype dt, RwWs* w) {
     w->cptr = cv.take<int32_t>((size_t)m + 1);
     w->rewritten = cv.take<unsigned char>(n > 0 ? n : 1);
     w->ovf = cv.take<int32_t>(m > 0 ? m : 1);
+    w->ovf2 = cv.take<int32_t>(m > 0 ? m : 1);
     w->ovf_mark = cv.take<unsigned char>(m > 0 ? m : 1);
     w->ctrl = cv.take<int32_t>(8);
     w->scan = cv.take<char>(scan_ws((int64_t)(n > m ? n : m) + 1));
@@ -473,6 +506,7 @@ RwArgs make_rw(const rwt_csr* L, const int32_t* level, const int32_t* rows, cons
     a.csub = w.csub;
     a.rewritten = w.rewritten;
     a.ovf = w.ovf;
+    a.ovf2 = w.ovf2;
     a.ovf_mark = w.ovf_mark;
     a.ctrl = w.ctrl;
     a.slab = w.slab;
@@ -481,21 +515,24 @@ RwArgs make_rw(const rwt_csr* L, const int32_t* level, const int32_t* rows, cons
     return a;
 }
 
+template <typename T, bool NUMERIC>
+rwt_status launch_tiers(const RwArgs& a, hipStream_t s) {
+    const unsigned g1 = blocks_for((size_t)a.m, RW_WAVES1, 8192);
+    hipLaunchKernelGGL((k_rewrite_lds<T, NUMERIC, 1>), dim3(g1), dim3(RW_WAVES1 * WAVE), 0, s, a);
+    RWT_LAUNCHED();
+    // the second tier reads its row count on the device; a grid of one
+    // workgroup per compute unit covers the (few) rows that reach it
+    hipLaunchKernelGGL((k_rewrite_lds<T, NUMERIC, 2>), dim3(256), dim3(RW_WAVES2 * WAVE), 0, s, a);
+    RWT_LAUNCHED();
+    hipLaunchKernelGGL((k_rewrite_slab<T, NUMERIC>), dim3(NSLAB), dim3(WAVE), 0, s, a);
+    RWT_LAUNCHED();
+    return RWT_OK;
+}
+
 template <typename T>
 rwt_status launch_rows(const RwArgs& a, bool numeric, hipStream_t s) {
     if (a.m == 0) return RWT_OK;
-    const unsigned g = blocks_for((size_t)a.m, RW_WAVES, 4096);
-    if (numeric) {
-        hipLaunchKernelGGL((k_rewrite_lds<T, true>), dim3(g), dim3(RW_WAVES * WAVE), 0, s, a);
-        RWT_LAUNCHED();
-        hipLaunchKernelGGL((k_rewrite_slab<T, true>), dim3(NSLAB), dim3(WAVE), 0, s, a);
-    } else {
-        hipLaunchKernelGGL((k_rewrite_lds<T, false>), dim3(g), dim3(RW_WAVES * WAVE), 0, s, a);
-        RWT_LAUNCHED();
-        hipLaunchKernelGGL((k_rewrite_slab<T, false>), dim3(NSLAB), dim3(WAVE), 0, s, a);
-    }
-    RWT_LAUNCHED();
-    return RWT_OK;
+    return numeric ? launch_tiers<T, true>(a, s) : launch_tiers<T, false>(a, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -515,9 +552,11 @@ struct BatchRwArgsDev {
     const int32_t* pat_ptr;
     int32_t* pat;
     int32_t pat_cap;
-    int32_t* ovf;
+    int32_t* ovf;    // positions that overflowed the small LDS tier
+    int32_t* ovf2;   // positions that overflowed the large LDS tier
     unsigned char* ovf_mark;
-    int32_t* ctrl;   // [0] overflow count, [3] too large, [4] capacity error
+    int32_t* ctrl;   // [0] first overflow count, [3] too large, [4] capacity error,
+                     // [7] second overflow count
     unsigned char* cand_bad;
     unsigned char* slab;
     int64_t slab_stride;
@@ -579,55 +618,50 @@ __device__ bool batch_noop_row(const BatchRwArgsDev& ba, const RwArgs& a, int32_
     return true;
 }
 
-template <int QMODE>
-__global__ void __launch_bounds__(RW_WAVES * WAVE) k_batch_rw_lds(BatchRwArgsDev ba) {
-    constexpr int S = 8;
-    constexpr int PER_WAVE = 2 * RW_CAP * (4 + S + 1) + RW_CAPB * (4 + S) + (RW_CAPB + 1) * 4 +
-                             RW_CAPB + 64;
-    __shared__ __align__(16) unsigned char s_buf[RW_WAVES * PER_WAVE];
+// Same two LDS tiers as the single-matrix rewrite: TIER 1 over every
+// candidate position, TIER 2 over the positions that overflowed it; the
+// pattern pass (QMODE 2) follows the marks of the length pass (QMODE 1).
+template <int QMODE, int TIER>
+__global__ void __launch_bounds__((TIER == 1 ? RW_WAVES1 : RW_WAVES2) * WAVE)
+    k_batch_rw_lds(BatchRwArgsDev ba) {
+    constexpr int CAP = TIER == 1 ? RW_CAP1 : RW_CAP2;
+    constexpr int WAVES = TIER == 1 ? RW_WAVES1 : RW_WAVES2;
+    constexpr int PER_WAVE = rw_wave_bytes(CAP, 8);
+    __shared__ __align__(16) unsigned char s_buf[WAVES * PER_WAVE];
     const int w = threadIdx.x / WAVE;
-    unsigned char* base = s_buf + w * PER_WAVE;
-    Bufs bf;
-    size_t off = 0;
-    auto take = [&](size_t bytes) {
-        unsigned char* p = base + off;
-        off += (bytes + 7) & ~size_t(7);
-        return p;
-    };
-    for (int i = 0; i < 2; ++i) {
-        bf.acol[i] = reinterpret_cast<int32_t*>(take(RW_CAP * 4));
-        bf.aval[i] = reinterpret_cast<double*>(take(RW_CAP * S));
-        bf.aelig[i] = take(RW_CAP);
-    }
-    bf.bcol = reinterpret_cast<int32_t*>(take(RW_CAPB * 4));
-    bf.bval = reinterpret_cast<double*>(take(RW_CAPB * S));
-    bf.nd = reinterpret_cast<int32_t*>(take((RW_CAPB + 1) * 4));
-    bf.bdup = take(RW_CAPB);
-    bf.cap = RW_CAP;
-    bf.capb = RW_CAPB;
-    const int32_t total = min(ba.cand_ptr[ba.C], ba.qcap);
-    const int64_t wave = (int64_t)blockIdx.x * RW_WAVES + w;
-    const int64_t nw = (int64_t)gridDim.x * RW_WAVES;
-    for (int64_t q = wave; q < total; q += nw) {
-        if (ba.cand_bad[cand_of(ba.cand_ptr, ba.C, (int32_t)q)]) {
-            if (QMODE == 1 && lane_id() == 0) ba.counts_q[q] = 0;
-            continue;
+    const Bufs bf = carve_bufs<CAP, 8>(s_buf + w * PER_WAVE);
+    const int64_t count = TIER == 1 ? min(ba.cand_ptr[ba.C], ba.qcap) : ba.ctrl[0];
+    const int64_t wave = (int64_t)blockIdx.x * WAVES + w;
+    const int64_t nw = (int64_t)gridDim.x * WAVES;
+    for (int64_t idx = wave; idx < count; idx += nw) {
+        const int32_t q = TIER == 1 ? (int32_t)idx : ba.ovf[idx];
+        if (TIER == 1) {
+            if (ba.cand_bad[cand_of(ba.cand_ptr, ba.C, q)]) {
+                if (QMODE == 1 && lane_id() == 0) ba.counts_q[q] = 0;
+                continue;
+            }
         }
-        const RwArgs a = batch_row_args(ba, (int32_t)q);
-        if (batch_noop_row<QMODE>(ba, a, (int32_t)q)) continue;
-        if (QMODE == 2 && ba.ovf_mark[q]) continue;
-        const bool ok = rewrite_row<double, false, QMODE>(a, (int32_t)q, bf);
+        const RwArgs a = batch_row_args(ba, q);
+        if (TIER == 1 && batch_noop_row<QMODE>(ba, a, q)) continue;
+        if (QMODE == 2 && ba.ovf_mark[q] >= TIER) continue;
+        const bool ok = rewrite_row<double, false, QMODE>(a, q, bf);
         if (!ok && QMODE == 1 && lane_id() == 0) {
-            int slot = atomicAdd(&ba.ctrl[0], 1);
-            ba.ovf[slot] = (int32_t)q;
-            ba.ovf_mark[q] = 1;
+            if (TIER == 1) {
+                const int slot = atomicAdd(&ba.ctrl[0], 1);
+                ba.ovf[slot] = q;
+                ba.ovf_mark[q] = 1;
+            } else {
+                const int slot = atomicAdd(&ba.ctrl[7], 1);
+                ba.ovf2[slot] = q;
+                ba.ovf_mark[q] = 2;
+            }
         }
     }
 }
 
 template <int QMODE>
 __global__ void __launch_bounds__(WAVE) k_batch_rw_slab(BatchRwArgsDev ba) {
-    const int32_t cnt = ba.ctrl[0];
+    const int32_t cnt = ba.ctrl[7];
     const int S = 8;
     for (int32_t s = blockIdx.x; s < cnt; s += gridDim.x) {
         unsigned char* base = ba.slab + (int64_t)blockIdx.x * ba.slab_stride;
@@ -650,7 +684,7 @@ __global__ void __launch_bounds__(WAVE) k_batch_rw_slab(BatchRwArgsDev ba) {
         bf.bdup = take(cap);
         bf.cap = (int32_t)cap;
         bf.capb = (int32_t)cap;
-        const int32_t q = ba.ovf[s];
+        const int32_t q = ba.ovf2[s];
         const RwArgs a = batch_row_args(ba, q);
         if (!rewrite_row<double, false, QMODE>(a, q, bf) && lane_id() == 0) atomicExch(&ba.ctrl[3], 1);
     }
@@ -677,6 +711,7 @@ rwt_status batch_rewrite_pass(const BatchRwArgs& h, int qmode, hipStream_t s) {
     ba.pat = h.pat;
     ba.pat_cap = h.pat_cap;
     ba.ovf = h.ovf;
+    ba.ovf2 = h.ovf2;
     ba.ovf_mark = h.ovf_mark;
     ba.ctrl = h.ctrl;
     ba.cand_bad = h.cand_bad;
@@ -684,13 +719,17 @@ rwt_status batch_rewrite_pass(const BatchRwArgs& h, int qmode, hipStream_t s) {
     ba.slab = h.slab;
     ba.slab_stride = h.slab_stride;
     ba.slab_cap = h.slab_cap;
-    const unsigned g = blocks_for((size_t)(h.qcap > 0 ? h.qcap : 1), RW_WAVES, 8192);
+    const unsigned g = blocks_for((size_t)(h.qcap > 0 ? h.qcap : 1), RW_WAVES1, 8192);
     if (qmode == 1) {
-        hipLaunchKernelGGL(k_batch_rw_lds<1>, dim3(g), dim3(RW_WAVES * WAVE), 0, s, ba);
+        hipLaunchKernelGGL((k_batch_rw_lds<1, 1>), dim3(g), dim3(RW_WAVES1 * WAVE), 0, s, ba);
+        RWT_LAUNCHED();
+        hipLaunchKernelGGL((k_batch_rw_lds<1, 2>), dim3(256), dim3(RW_WAVES2 * WAVE), 0, s, ba);
         RWT_LAUNCHED();
         hipLaunchKernelGGL(k_batch_rw_slab<1>, dim3(h.nslab), dim3(WAVE), 0, s, ba);
     } else {
-        hipLaunchKernelGGL(k_batch_rw_lds<2>, dim3(g), dim3(RW_WAVES * WAVE), 0, s, ba);
+        hipLaunchKernelGGL((k_batch_rw_lds<2, 1>), dim3(g), dim3(RW_WAVES1 * WAVE), 0, s, ba);
+        RWT_LAUNCHED();
+        hipLaunchKernelGGL((k_batch_rw_lds<2, 2>), dim3(256), dim3(RW_WAVES2 * WAVE), 0, s, ba);
         RWT_LAUNCHED();
         hipLaunchKernelGGL(k_batch_rw_slab<2>, dim3(h.nslab), dim3(WAVE), 0, s, ba);
     }

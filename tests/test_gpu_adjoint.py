@@ -36,6 +36,23 @@ def test_apply_mt_matches_dense(orc):
     for e in range(crow.size):             # ascending e per column, as the kernel
         ref[:, ccol[e]] = ref[:, ccol[e]] - cval[e] * Y[:, crow[e]]
     assert np.array_equal(out, ref)
+    # the C^T ordering is kept with the rewrite: new multiplier values (a
+    # numeric re-run with other matrix values) and another Y reuse it
+    from paper_2609_40159_amd.api import Rewriter
+    rwr = Rewriter(G, info.level, rows, tg)
+    rwr.numeric(None, None)
+    res = rwr.result()
+    apply_MT(res, block(Y))
+    assert res.mt_ws is not None
+    vals2 = G.vals * torch.linspace(0.5, 1.5, G.nnz, dtype=G.vals.dtype, device=G.vals.device)
+    rwr.numeric(vals2, None)
+    Y2 = rng.standard_normal((2, L.n))
+    out2 = host(apply_MT(res, block(Y2)))
+    crow, ccol, cval = host(res.crow), host(res.ccol), host(res.cval)
+    ref2 = Y2.copy()
+    for e in range(crow.size):
+        ref2[:, ccol[e]] = ref2[:, ccol[e]] - cval[e] * Y2[:, crow[e]]
+    assert np.array_equal(out2, ref2)
 
 
 @pytest.mark.parametrize("rewritten", [False, True])
