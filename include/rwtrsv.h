@@ -183,7 +183,7 @@ rwt_status rwt_rewrite_numeric(const rwt_csr* L, const int32_t* d_level,
  *   RWT_ALGO_AUTO     autotuned: both candidates are timed on the plan's
  *                     matrix and the faster kept.
  * Unless fixed by the options, the sync-free block size and RHS chunk are
- * chosen by timing solves on the plan's own matrix (min(kmax, 4) columns).
+ * chosen by timing solves on the plan's own matrix (min(kmax, 64) columns).
  * The plan keeps pointers to L (pattern and values): the caller keeps them
  * alive and may change the values between solves.  The plan's device
  * state lives in the caller's workspace (rwt_plan_ws bytes).

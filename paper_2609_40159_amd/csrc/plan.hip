@@ -112,30 +112,33 @@ struct PlanLayout {
     size_t bytes;
 };
 
-constexpr int R_MIN = 32;   // smallest row block (sizes the block tables)
+constexpr int R_MIN = 32;       // smallest row block (sizes the block tables)
+constexpr int TUNE_COLS = 64;   // right-hand sides the autotuner solves with (at most)
 
 // A row block size is usable when the block's x values and step starts fit
 // the LDS budget at the largest right-hand-side count.
-bool block_rows_ok(int R, int kmax, rwt_dtype dt) {
-    return R >= R_MIN && syncfree_lds_bytes(R, kmax, dt) <= SF_LDS_BUDGET;
+bool block_rows_ok(int R, int kmax, rwt_dtype dt, int lanes) {
+    return R >= R_MIN && syncfree_lds_bytes(R, kmax, dt, lanes) <= SF_LDS_BUDGET;
 }
 
 // Block sizes to try for chains of kc right-hand-side columns.
-std::vector<int> block_candidates(const rwt_plan_opts& o, rwt_dtype dt, int32_t n, int kc) {
+std::vector<int> block_candidates(const rwt_plan_opts& o, rwt_dtype dt, int32_t n, int kc,
+                                  int lanes) {
     const int kmax = kc;
     std::vector<int> out;
     // the whole matrix in one workgroup, level after level with workgroup
     // barriers, when its x values fit in LDS
-    const bool whole = n > 0 && n <= (1 << 20) && syncfree_lds_bytes(n, kmax, dt) <= SF_LDS_BUDGET;
+    const bool whole =
+        n > 0 && n <= (1 << 20) && syncfree_lds_bytes(n, kmax, dt, lanes) <= SF_LDS_BUDGET;
     if (o.block_rows > 0) {
         int R = o.block_rows;
-        while (R > R_MIN && !block_rows_ok(R, kmax, dt)) R /= 2;
+        while (R > R_MIN && !block_rows_ok(R, kmax, dt, lanes)) R /= 2;
         out.push_back(R < R_MIN ? R_MIN : R);
         return out;
     }
     if (whole) out.push_back(n);
     for (int R : {4096, 2048, 1024, 512, 256, 128, 64, 32})
-        if (R < n && block_rows_ok(R, kmax, dt)) out.push_back(R);
+        if (R < n && block_rows_ok(R, kmax, dt, lanes)) out.push_back(R);
     if (out.empty()) out.push_back(R_MIN);
     return out;
 }
@@ -189,7 +192,7 @@ size_t carve_plan(void* base, const rwt_csr& L, int kmax, PlanPtrs* p) {
     p->desc_f = cv.take<int4>(n);
     p->desc_t = cv.take<int4>(n);
     p->xtmp = cv.take<char>((size_t)n * kmax * s);
-    p->xtmp2 = cv.take<char>((size_t)n * std::min(kmax, 4) * s);
+    p->xtmp2 = cv.take<char>((size_t)n * std::min(kmax, TUNE_COLS) * s);
     // scratch shared by the construction steps
     size_t sched = 0;
     {
@@ -275,7 +278,7 @@ rwt_status run_solve(const rwt_plan* p, bool transposed, Algo algo, const void* 
         a.kc = std::min(p->kc, k);
         kg = a.kc;
         a.desc = transposed ? p->desc_t : p->desc_f;
-        a.lds_bytes = syncfree_lds_bytes(p->R, a.kc, p->L.dt);
+        a.lds_bytes = syncfree_lds_bytes(p->R, a.kc, p->L.dt, p->lanes);
         lds = (size_t)a.lds_bytes;
     }
     unsigned grid = solve_grid(algo, p->L.dt, transposed, kg, lds, p->cus);
@@ -338,7 +341,8 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
     if (opts->rhs_chunk > 0) kcs.push_back(std::min(opts->rhs_chunk, kmax));
     else if (kmax == 1) kcs.push_back(1);
     else kcs = {std::min(kmax, 4), 1};
-    int R = block_candidates(*opts, L->dt, L->n, kcs.front()).front();
+    const int lanes = opts->lanes_per_row > 0 ? opts->lanes_per_row : default_lanes(L->nnz, L->n);
+    int R = block_candidates(*opts, L->dt, L->n, kcs.front(), lanes).front();
     PlanPtrs pp;
     const size_t need = carve_plan(nullptr, *L, kmax, &pp);
     RWT_REQUIRE(d_ws != nullptr && ws_bytes >= need, RWT_ERR_BUFFER_TOO_SMALL,
@@ -365,7 +369,7 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
     p->desc_t = pp.desc_t;
     p->xtmp = pp.xtmp;
     p->xtmp2 = pp.xtmp2;
-    p->lanes = opts->lanes_per_row > 0 ? opts->lanes_per_row : default_lanes(L->nnz, L->n);
+    p->lanes = lanes;
     p->kc = kcs.front();
     DeviceInfo di;
     rwt_status st = device_info(&di);
@@ -461,12 +465,13 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
         return RWT_OK;
     };
     // algorithm, RHS chunk and block size: measured on the plan's own matrix
-    // (with kt = min(kmax, 4) columns) unless forced
+    // (with kt = min(kmax, TUNE_COLS) columns) unless forced
     p->fwd = p->bwd = opts->algo == RWT_ALGO_LEVEL ? Algo::Level : Algo::SyncFree;
-    const int kt = std::min(kmax, 4);
+    const int kt = std::min(kmax, TUNE_COLS);
     const bool tune_algo = opts->algo == RWT_ALGO_AUTO;
     const bool tune_sf = opts->algo != RWT_ALGO_LEVEL &&
-                         (kcs.size() > 1 || block_candidates(*opts, L->dt, n, kcs.front()).size() > 1);
+                         (kcs.size() > 1 ||
+                          block_candidates(*opts, L->dt, n, kcs.front(), lanes).size() > 1);
     if (tune_algo || tune_sf) {
         const int64_t nf = (int64_t)n * kt;
         const unsigned g = blocks_for(nf, 256, 8192);
@@ -484,7 +489,7 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
             p->kc = kc;
             double best_here = 1e30;
             int worse = 0;
-            for (int Rc : block_candidates(*opts, L->dt, n, kc)) {
+            for (int Rc : block_candidates(*opts, L->dt, n, kc, lanes)) {
                 if ((st = build_blocks(Rc)) != RWT_OK) return fail(st);
                 double ms = time_solve(p, Algo::SyncFree, kt, s, 2);
                 if (ms < best_sf) { best_sf = ms; best_R = Rc; best_kc = kc; }
@@ -526,7 +531,9 @@ extern "C" rwt_status rwt_plan_get_info(const rwt_plan* p, rwt_plan_info* h) {
     h->num_blocks = p->nblocks;
     h->rhs_chunk = p->kc;
     h->grid = (int32_t)solve_grid(p->fwd, p->L.dt, false, p->fwd == Algo::SyncFree ? p->kc : 1,
-                                  p->fwd == Algo::SyncFree ? syncfree_lds_bytes(p->R, p->kc, p->L.dt) : 0,
+                                  p->fwd == Algo::SyncFree
+                                      ? syncfree_lds_bytes(p->R, p->kc, p->L.dt, p->lanes)
+                                      : 0,
                                   p->cus);
     h->tuned_ms_level = p->tuned_level;
     h->tuned_ms_syncfree = p->tuned_sf;

@@ -24,7 +24,7 @@ struct rwt_plan {
     int4* desc_f = nullptr;   // forward row descriptors in block order
     int4* desc_t = nullptr;   // transposed row descriptors in block order
     void* xtmp = nullptr;     // n * kmax values
-    void* xtmp2 = nullptr;    // n * min(kmax, 4) values (autotuning)
+    void* xtmp2 = nullptr;    // n * min(kmax, 64) values (autotuning)
     int32_t kc = 1;           // sync-free right-hand sides per chain
     rwt::Algo fwd = rwt::Algo::SyncFree;
     rwt::Algo bwd = rwt::Algo::SyncFree;

@@ -25,6 +25,7 @@
 #include "solve.hpp"
 
 #include "sf_block.hpp"
+#include "sf_staged.hpp"
 
 #include "prim.hpp"
 
@@ -230,7 +231,7 @@ __global__ void __launch_bounds__(SV_THREADS) k_solve_sf(SolveArgs a) {
         b.r1 = min(a.n, b.r0 + a.block_rows);
         b.sb = a.blk_step[blk];
         b.ns = a.blk_step[blk + 1] - b.sb;
-        sf_block<T, TRANS, KT>(b, s_raw);
+        sf_block_staged<T, TRANS, KT>(b, s_raw);
         if (ld_relaxed(&a.ctrl->err) != 0) break;
     }
 }
@@ -279,8 +280,9 @@ unsigned solve_grid(Algo algo, rwt_dtype dt, bool transposed, int k, size_t lds,
     return (unsigned)(cus * per_cu);
 }
 
-int syncfree_lds_bytes(int block_rows, int k, rwt_dtype dt) {
-    return sf_x_bytes(block_rows, k, (int)dtype_size(dt)) + (block_rows + 1) * 4;
+int syncfree_lds_bytes(int block_rows, int k, rwt_dtype dt, int lanes) {
+    const int s = (int)dtype_size(dt);
+    return sf_stage_offset(block_rows, k, s) + sf_stage_bytes(lanes, k == 1 ? 1 : 4, s);
 }
 
 rwt_status solve_prepare(const SolveArgs& a, rwt_dtype dt, hipStream_t s) {

@@ -45,9 +45,10 @@ enum class Algo { Level, SyncFree };
 rwt_status solve_prepare(const SolveArgs& a, rwt_dtype dt, hipStream_t s);
 rwt_status solve_launch(const SolveArgs& a, rwt_dtype dt, Algo algo, bool transposed,
                         unsigned grid, hipStream_t s);
-// LDS of one sync-free workgroup: the block's x values and its step starts
-int syncfree_lds_bytes(int block_rows, int k, rwt_dtype dt);
-constexpr int SF_LDS_BUDGET = 60 * 1024;
+// LDS of one sync-free workgroup: the block's x values, its step starts and
+// the helper waves' stage ring (lanes per row G)
+int syncfree_lds_bytes(int block_rows, int k, rwt_dtype dt, int lanes);
+constexpr int SF_LDS_BUDGET = 80 * 1024;   // two workgroups per compute unit
 // workgroups of a persistent solve launch (all resident); k: columns per
 // chain (sync-free) or per launch (level-scheduled)
 unsigned solve_grid(Algo algo, rwt_dtype dt, bool transposed, int k, size_t lds, int cus);
