@@ -548,6 +548,115 @@ size_t levels_ws(int32_t n, int64_t nnz) {
     return cv.used();
 }
 
+// Levels in row order, without level barriers (Section 2.1: the level of a
+// row is 0 without dependencies, else 1 + the largest level among them).
+// Waves claim chunks of WAVE/G consecutive rows in row order; a row reads
+// its dependencies' levels from level[] (-1: not known yet) and publishes
+// its own as soon as all are known.  A lane never spins on a row of its own
+// wave: the wave publishes the rows it could finish, then retries the rest
+// (a chain inside a chunk resolves one row per pass).  Every wait is for a
+// lower row, which a running wave has already claimed, so the kernel cannot
+// deadlock for any number of resident workgroups.  D (max level + 1) and
+// the number of rows reached go to ctrl->i2 and ctrl->l1.
+__global__ void __launch_bounds__(LV_THREADS) k_levels_sf(const int32_t* rowptr,
+                                                          const int32_t* colidx, int32_t n, int G,
+                                                          int32_t* level, Ctrl* ctrl, int64_t ticks) {
+    __shared__ int32_t s_max[LV_THREADS / WAVE];
+    __shared__ int64_t s_cnt[LV_THREADS / WAVE];
+    const int lane = lane_id();
+    const int w = threadIdx.x / WAVE;
+    const int gl = lane & (G - 1);
+    const int CH = WAVE / G;
+    int32_t* err = &ctrl->err;
+    int32_t wmax = -1;
+    int64_t wcnt = 0;
+    bool abort = false;
+    while (!abort) {
+        int32_t c = 0;
+        if (lane == 0) c = (int32_t)fetch_add(&ctrl->ticket, 1u);
+        c = __shfl(c, 0);
+        if ((int64_t)c * CH >= n) break;
+        const int64_t i64 = (int64_t)c * CH + lane / G;
+        const bool act = i64 < n;
+        const int32_t i = act ? (int32_t)i64 : 0;
+        const int32_t rb = act ? rowptr[i] : 0;
+        const int32_t re = act ? rowptr[i + 1] - 1 : 0;   // off-diagonal entries [rb, re)
+        bool done = !act;
+        int32_t res = 0;
+        const int64_t t0 = wall_clock64();
+        for (;;) {
+            int32_t mx = -1;
+            int miss = 0;
+            if (!done)
+                for (int32_t p = rb + gl; p < re; p += G) {
+                    const int32_t lj = ld_relaxed(&level[colidx[p]]);
+                    miss |= lj < 0 ? 1 : 0;
+                    mx = lj > mx ? lj : mx;
+                }
+            for (int o = G / 2; o > 0; o >>= 1) {
+                const int32_t m2 = __shfl_xor(mx, o);
+                mx = m2 > mx ? m2 : mx;
+                miss |= __shfl_xor(miss, o);
+            }
+            if (!done && !miss) {
+                res = mx + 1;
+                if (gl == 0) st_relaxed(&level[i], res);
+                done = true;
+            }
+            if (__ballot(!done) == 0) break;
+            // the wave's own stores complete before it reads again
+            __builtin_amdgcn_s_waitcnt(0);
+            __builtin_amdgcn_s_sleep(1);
+            if (ld_relaxed(err) != 0) {
+                abort = true;
+                break;
+            }
+            if (wall_clock64() - t0 > ticks) {
+                __hip_atomic_store(err, (int32_t)RWT_ERR_DEADLOCK, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                abort = true;
+                break;
+            }
+        }
+        if (act && gl == 0 && done) {
+            wmax = res > wmax ? res : wmax;
+            ++wcnt;
+        }
+    }
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        const int32_t m2 = __shfl_xor(wmax, o);
+        wmax = m2 > wmax ? m2 : wmax;
+        wcnt += __shfl_xor(wcnt, o);
+    }
+    if (lane == 0) {
+        s_max[w] = wmax;
+        s_cnt[w] = wcnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t m = -1;
+        int64_t cnt = 0;
+        for (int k = 0; k < LV_THREADS / WAVE; ++k) {
+            m = s_max[k] > m ? s_max[k] : m;
+            cnt += s_cnt[k];
+        }
+        if (m >= 0) atomicMax(&ctrl->i2, m + 1);
+        __hip_atomic_fetch_add(&ctrl->l1, cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Sum of dependency distances i - j over the off-diagonal entries (chooses
+// the levelization method).
+__global__ void k_dist_sum(const int32_t* rowptr, const int32_t* colidx, int32_t n,
+                           unsigned long long* sum) {
+    uint64_t acc = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        for (int32_t p = rowptr[i]; p < rowptr[i + 1] - 1; ++p) acc += (uint64_t)(i - colidx[p]);
+    for (int o = WAVE / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane_id() == 0) atomicAdd(sum, (unsigned long long)acc);
+}
+
 rwt_status compute_levels(const rwt_csr& L, const Csc& csc, const LevelOut& out, Ctrl* ctrl,
                           void* ws, hipStream_t s, int watchdog_ms) {
     const int32_t n = L.n;
@@ -564,22 +673,47 @@ rwt_status compute_levels(const rwt_csr& L, const Csc& csc, const LevelOut& out,
     void* rws = cv.take<char>(radix_ws(n));
 
     RWT_TRY(fill_u8(ctrl, sizeof(Ctrl), s));
-    RWT_TRY(fill_u8(snap, 2 * sizeof(int32_t), s));
     const unsigned gb = blocks_for(n, 256, 8192);
-    hipLaunchKernelGGL(k_lv_init, dim3(gb), dim3(256), 0, s, L.rowptr, n, indeg, queue, flag);
-    RWT_LAUNCHED();
-    RWT_TRY(scan_exclusive(flag, fpos, n, sws, s));
-    hipLaunchKernelGGL(k_lv_seed, dim3(gb), dim3(256), 0, s, flag, fpos, n, queue, ctrl);
-    RWT_LAUNCHED();
-
     DeviceInfo di;
     RWT_TRY(device_info(&di));
-    // one resident workgroup per compute unit
-    const unsigned grid = (unsigned)di.cus;
-    const int32_t narrow = 2 * LV_THREADS;
-    hipLaunchKernelGGL(k_levelize, dim3(grid), dim3(LV_THREADS), 0, s, n, csc.ptr, csc.row, indeg,
-                       queue, out.level, ctrl, snap, narrow, watchdog_ticks(watchdog_ms));
+    // Method: the row-order kernel keeps a window of consecutive rows in
+    // flight and needs no level barrier, which wins on deep DAGs whose
+    // dependencies are short-range; the frontier search works a whole level
+    // at a time, which wins when a level spans much of the row range.  The
+    // mean dependency distance against n separates the two.
+    unsigned long long* dsum = reinterpret_cast<unsigned long long*>(snap);   // 8 bytes
+    RWT_TRY(fill_u8(dsum, sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(k_dist_sum, dim3(blocks_for(n, 256, 2048)), dim3(256), 0, s, L.rowptr,
+                       L.colidx, n, dsum);
     RWT_LAUNCHED();
+    unsigned long long hsum = 0;
+    RWT_HIP(hipMemcpyAsync(&hsum, dsum, sizeof hsum, hipMemcpyDeviceToHost, s));
+    RWT_HIP(hipStreamSynchronize(s));
+    const int64_t noff = L.nnz - n;
+    const double mean_dist = noff > 0 ? (double)hsum / (double)noff : 0.0;
+    const bool row_order = noff > 0 && mean_dist * 400.0 < (double)n;
+    if (row_order) {
+        RWT_TRY(fill_i32(out.level, n, -1, s));
+        // lanes per row: a power of two near the mean dependency count
+        const double mean = (double)noff / n;
+        int G = 1;
+        while (G < 16 && G < mean) G *= 2;
+        hipLaunchKernelGGL(k_levels_sf, dim3(di.cus * 8), dim3(LV_THREADS), 0, s, L.rowptr, L.colidx,
+                           n, G, out.level, ctrl, watchdog_ticks(watchdog_ms));
+        RWT_LAUNCHED();
+    } else {
+        RWT_TRY(fill_u8(snap, 2 * sizeof(int32_t), s));
+        hipLaunchKernelGGL(k_lv_init, dim3(gb), dim3(256), 0, s, L.rowptr, n, indeg, queue, flag);
+        RWT_LAUNCHED();
+        RWT_TRY(scan_exclusive(flag, fpos, n, sws, s));
+        hipLaunchKernelGGL(k_lv_seed, dim3(gb), dim3(256), 0, s, flag, fpos, n, queue, ctrl);
+        RWT_LAUNCHED();
+        // one resident workgroup per compute unit
+        const int32_t narrow = 2 * LV_THREADS;
+        hipLaunchKernelGGL(k_levelize, dim3(di.cus), dim3(LV_THREADS), 0, s, n, csc.ptr, csc.row,
+                           indeg, queue, out.level, ctrl, snap, narrow, watchdog_ticks(watchdog_ms));
+        RWT_LAUNCHED();
+    }
 
     hipLaunchKernelGGL(k_perm_keys, dim3(gb), dim3(256), 0, s, out.level, n, keys, out.perm);
     RWT_LAUNCHED();

@@ -890,11 +890,11 @@ extern "C" rwt_status rwt_batch_capture(rwt_batch* b, rwt_stream_t stream) {
     RWT_REQUIRE(stream != nullptr, RWT_ERR_INVALID_ARG, "capture needs a non-default stream");
     hipStream_t s = hs(stream);
     if (b->exec) {
-        hipGraphExecDestroy(b->exec);
+        (void)hipGraphExecDestroy(b->exec);
         b->exec = nullptr;
     }
     if (b->graph) {
-        hipGraphDestroy(b->graph);
+        (void)hipGraphDestroy(b->graph);
         b->graph = nullptr;
     }
     RWT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -902,7 +902,7 @@ extern "C" rwt_status rwt_batch_capture(rwt_batch* b, rwt_stream_t stream) {
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s, &g);
     if (st != RWT_OK) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return st;
     }
     RWT_HIP(e);
@@ -964,8 +964,8 @@ extern "C" rwt_status rwt_batch_plan(const rwt_batch* b, int32_t m, const rwt_pl
 
 extern "C" rwt_status rwt_batch_destroy(rwt_batch* b) {
     if (!b) return RWT_OK;
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
     for (rwt_plan* p : b->plans) rwt_plan_destroy(p);
     delete b;
     return RWT_OK;

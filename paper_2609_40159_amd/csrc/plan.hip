@@ -114,6 +114,7 @@ struct PlanLayout {
 
 constexpr int R_MIN = 32;       // smallest row block (sizes the block tables)
 constexpr int TUNE_COLS = 64;   // right-hand sides the autotuner solves with (at most)
+constexpr int32_t TUNE_ROWS = 1 << 17;   // rows the sync-free candidates are timed on (at most)
 
 // A row block size is usable when the block's x values and step starts fit
 // the LDS budget at the largest right-hand-side count.
@@ -257,9 +258,15 @@ SolveArgs make_args(const rwt_plan* p) {
     return a;
 }
 
+// rows > 0: solve only the leading rows x rows block (a forward sync-free
+// solve of whole row blocks; used by the autotuner)
 rwt_status run_solve(const rwt_plan* p, bool transposed, Algo algo, const void* B, int32_t k,
-                     int64_t ldb, void* X, int64_t ldx, hipStream_t s) {
+                     int64_t ldb, void* X, int64_t ldx, hipStream_t s, int32_t rows = 0) {
     SolveArgs a = make_args(p);
+    if (rows > 0 && rows < a.n) {
+        a.n = rows;
+        a.nblocks = (rows + p->R - 1) / p->R;
+    }
     a.k = k;
     a.X = X;
     a.ldx = ldx;
@@ -285,20 +292,37 @@ rwt_status run_solve(const rwt_plan* p, bool transposed, Algo algo, const void* 
     return solve_launch(a, p->L.dt, algo, transposed, grid, s);
 }
 
+// The sync-free candidates are timed on the leading rows only: whole row
+// blocks covering up to TUNE_ROWS rows (the leading block of a lower
+// triangular matrix is one on its own, and per-level costs carry over).
+int32_t tune_rows(const rwt_plan* p) {
+    if (p->R >= p->L.n) return p->L.n;
+    const int32_t r = (TUNE_ROWS / p->R) * p->R;
+    return r > 0 && r < p->L.n ? r : p->L.n;
+}
+
+double time_solve(rwt_plan* p, Algo algo, int kt, hipStream_t s, int reps);
+
+// the sync-free schedule timed on every row
+double time_solve_full(rwt_plan* p, int kt, hipStream_t s);
+
 // Median-free timing: best of reps - 1 runs after one warm-up, on kt
 // columns of ones.
-double time_solve(rwt_plan* p, Algo algo, int kt, hipStream_t s, int reps) {
+double time_solve_rows(rwt_plan* p, Algo algo, int kt, hipStream_t s, int reps, int32_t rows) {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return 1e30;
-    if (hipEventCreate(&e1) != hipSuccess) { hipEventDestroy(e0); return 1e30; }
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return 1e30;
+    }
     double best = 1e30;
     for (int r = 0; r < reps; ++r) {
-        hipEventRecord(e0, s);
-        rwt_status st = run_solve(p, false, algo, p->xtmp, kt, p->L.n, p->xtmp2, p->L.n, s);
-        hipEventRecord(e1, s);
+        (void)hipEventRecord(e0, s);
+        rwt_status st = run_solve(p, false, algo, p->xtmp, kt, p->L.n, p->xtmp2, p->L.n, s, rows);
+        (void)hipEventRecord(e1, s);
         if (st != RWT_OK || hipEventSynchronize(e1) != hipSuccess) { best = 1e30; break; }
         float ms = 0;
-        hipEventElapsedTime(&ms, e0, e1);
+        (void)hipEventElapsedTime(&ms, e0, e1);
         Ctrl hc;
         if (hipMemcpy(&hc, p->ctrl, sizeof hc, hipMemcpyDeviceToHost) != hipSuccess || hc.err != 0) {
             best = 1e30;
@@ -307,9 +331,17 @@ double time_solve(rwt_plan* p, Algo algo, int kt, hipStream_t s, int reps) {
         if (r > 0 && ms < best) best = ms;   // the first run warms up
         if (reps == 1) best = ms;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     return best;
+}
+
+double time_solve(rwt_plan* p, Algo algo, int kt, hipStream_t s, int reps) {
+    return time_solve_rows(p, algo, kt, s, reps, algo == Algo::SyncFree ? tune_rows(p) : 0);
+}
+
+double time_solve_full(rwt_plan* p, int kt, hipStream_t s) {
+    return time_solve_rows(p, Algo::SyncFree, kt, s, 2, 0);
 }
 
 }  // namespace
@@ -502,6 +534,13 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
         R = best_R;
         p->kc = best_kc;
         if (tune_algo) {
+            // the level-scheduled solve is timed on the whole matrix: time the
+            // chosen sync-free schedule on the whole matrix as well
+            if ((st = build_blocks(R)) != RWT_OK) return fail(st);
+            if (tune_rows(p) < n) {
+                best_sf = time_solve_full(p, kt, s);
+                p->tuned_sf = best_sf;
+            }
             p->tuned_level = time_solve(p, Algo::Level, kt, s, 3);
             if (p->tuned_level >= 1e30 && best_sf >= 1e30) {
                 set_error("autotuning solves failed");
