@@ -192,13 +192,13 @@ typedef enum { RWT_ALGO_AUTO = 0, RWT_ALGO_LEVEL = 1, RWT_ALGO_SYNCFREE = 2 } rw
 
 typedef struct {
     rwt_algo algo;            /* forward and transposed solves */
-    int32_t block_rows;       /* sync-free rows per block (0: choose) */
+    int32_t block_rows;       /* sync-free rows per block (0: choose; else at most 2^20, lowered to fit LDS) */
     int32_t lanes_per_row;    /* 0: choose from the mean row length; else 1..64, power of 2 */
     int32_t narrow_rows;      /* level-scheduled: levels up to this many rows run on one workgroup (-1: choose) */
     int32_t kmax;             /* largest number of right-hand sides solved at once (>=1) */
     int32_t watchdog_ms;      /* bound on any device wait (0: 5000 ms) */
     int32_t rhs_chunk;        /* sync-free columns per chain: 0 choose, else 1..4 */
-    int32_t pad_;
+    int32_t tune_cols;        /* columns the autotuner solves with: 0 min(kmax, 64), else 1..kmax */
 } rwt_plan_opts;
 
 typedef struct rwt_plan rwt_plan;
@@ -284,10 +284,10 @@ rwt_status rwt_grad_vals(const rwt_csr* L, const void* d_gB, int64_t ldg, const 
  * from a captured hipGraph).
  *
  * Per matrix m: L (FP64 values), B / X (k columns; k may be 0 for
- * analysis-only matrices).  Its solve schedule is autotuned at creation
- * (sync-free row blocks of a measured size, or the whole matrix in one
- * workgroup, level after level, when it fits in LDS) unless block_rows
- * fixes the block size.
+ * analysis-only matrices).  Its solve runs in sync-free row blocks of the
+ * largest size whose x values fit in LDS (the whole matrix in one
+ * workgroup, level after level, when it fits), one column per chain,
+ * unless block_rows fixes the block size.
  * Per candidate c: the matrix h_cand_mat[c] and the rows
  * d_cand_rows[d_cand_ptr[c] .. d_cand_ptr[c+1]) (strictly ascending) with
  * targets d_cand_targets (NULL: level - 1).  Each launch recomputes, for

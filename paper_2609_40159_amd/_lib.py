@@ -51,7 +51,7 @@ class LevelStats(C.Structure):
 class PlanOpts(C.Structure):
     _fields_ = [("algo", C.c_int32), ("block_rows", C.c_int32), ("lanes_per_row", C.c_int32),
                 ("narrow_rows", C.c_int32), ("kmax", C.c_int32), ("watchdog_ms", C.c_int32),
-                ("rhs_chunk", C.c_int32), ("pad_", C.c_int32)]
+                ("rhs_chunk", C.c_int32), ("tune_cols", C.c_int32)]
 
 
 class PlanInfo(C.Structure):

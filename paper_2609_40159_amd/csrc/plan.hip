@@ -226,9 +226,11 @@ rwt_status check_opts(const rwt_csr* L, const rwt_plan_opts* o) {
                     (o->lanes_per_row >= 1 && o->lanes_per_row <= 64 &&
                      (o->lanes_per_row & (o->lanes_per_row - 1)) == 0),
                 RWT_ERR_INVALID_ARG, "lanes_per_row must be 0 or a power of two <= 64");
-    RWT_REQUIRE(o->block_rows >= 0, RWT_ERR_INVALID_ARG, "negative block_rows");
+    RWT_REQUIRE(o->block_rows >= 0 && o->block_rows <= (1 << 20), RWT_ERR_INVALID_ARG,
+                "block_rows outside 0..2^20");
     RWT_REQUIRE(o->rhs_chunk >= 0 && o->rhs_chunk <= 4, RWT_ERR_INVALID_ARG,
                 "rhs_chunk must be 0..4");
+    RWT_REQUIRE(o->tune_cols >= 0, RWT_ERR_INVALID_ARG, "negative tune_cols");
     return RWT_OK;
 }
 
@@ -499,7 +501,7 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
     // algorithm, RHS chunk and block size: measured on the plan's own matrix
     // (with kt = min(kmax, TUNE_COLS) columns) unless forced
     p->fwd = p->bwd = opts->algo == RWT_ALGO_LEVEL ? Algo::Level : Algo::SyncFree;
-    const int kt = std::min(kmax, TUNE_COLS);
+    const int kt = std::min(kmax, opts->tune_cols > 0 ? opts->tune_cols : TUNE_COLS);
     const bool tune_algo = opts->algo == RWT_ALGO_AUTO;
     const bool tune_sf = opts->algo != RWT_ALGO_LEVEL &&
                          (kcs.size() > 1 ||

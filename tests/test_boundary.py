@@ -72,6 +72,10 @@ def test_host_only_calls(lib):
     assert lib.rwt_plan_ws(C.byref(c), C.byref(o), C.byref(sz)) == -1   # lanes not a power of 2
     o.lanes_per_row = 0
     assert lib.rwt_plan_ws(C.byref(c), C.byref(o), C.byref(sz)) == 0
+    for field, bad in (("block_rows", (1 << 20) + 1), ("rhs_chunk", 5), ("tune_cols", -1)):
+        setattr(o, field, bad)
+        assert lib.rwt_plan_ws(C.byref(c), C.byref(o), C.byref(sz)) == -1, field
+        setattr(o, field, 0)
 
 
 def test_package_fails_loudly_without_library(tmp_path, monkeypatch):
