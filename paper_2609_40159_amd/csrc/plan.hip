@@ -114,7 +114,7 @@ struct PlanLayout {
 
 constexpr int R_MIN = 32;       // smallest row block (sizes the block tables)
 constexpr int TUNE_COLS = 64;   // right-hand sides the autotuner solves with (at most)
-constexpr int32_t TUNE_ROWS = 1 << 17;   // rows the sync-free candidates are timed on (at most)
+constexpr int32_t TUNE_ROWS = 1 << 21;   // rows the sync-free candidates are timed on (at most)
 
 // A row block size is usable when the block's x values and step starts fit
 // the LDS budget at the largest right-hand-side count.
