@@ -32,7 +32,8 @@ PEAK_HBM_GBS = 8000.0
 # sources of the solve kernels and their schedules (a change invalidates the
 # committed counter measurements)
 SOLVE_SOURCES = ["paper_2609_40159_amd/csrc/solve.hip", "paper_2609_40159_amd/csrc/solve.hpp",
-                 "paper_2609_40159_amd/csrc/sf_block.hpp", "paper_2609_40159_amd/csrc/common.hpp",
+                 "paper_2609_40159_amd/csrc/sf_block.hpp", "paper_2609_40159_amd/csrc/sf_staged.hpp",
+                 "paper_2609_40159_amd/csrc/common.hpp",
                  "paper_2609_40159_amd/csrc/plan.hip"]
 METRIC = "SpTRSV HBM GB/s & solves/s, rewritten vs original DAG, fwd+adjoint, batched"
 
