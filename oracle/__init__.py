@@ -44,6 +44,22 @@ class _Stats(C.Structure):
                 ("arl", C.c_double), ("air", C.c_double), ("thin_threshold", C.c_double)]
 
 
+class _GenParams(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("thin_stop", C.c_double), ("max_dist", C.c_int32),
+                ("max_moves", C.c_int32), ("max_steps", C.c_int32), ("pad_", C.c_int32)]
+
+
+class _GenResult(C.Structure):
+    _fields_ = [("moves", C.c_int32), ("steps", C.c_int32), ("stop", C.c_int32),
+                ("levels", C.c_int32), ("thin", C.c_int32), ("thin0", C.c_int32),
+                ("rejected", C.c_int32), ("pad_", C.c_int32), ("threshold", C.c_double),
+                ("S1", C.c_uint64), ("S2_lo", C.c_uint64), ("S2_hi", C.c_uint64),
+                ("cv", C.c_double)]
+
+
+GEN_NO_SOURCE, GEN_THIN, GEN_MOVES, GEN_STEPS = 0, 1, 2, 3
+
+
 _lib = None
 
 
@@ -67,6 +83,10 @@ def _L():
         _lib.orc_grad_vals.argtypes = [C.c_int32, P, P, C.c_int32, P, C.c_int64, P,
                                        C.c_int64, P]
         _lib.orc_grad_vals.restype = None
+        _lib.orc_generate.argtypes = [C.c_int32, P, P, C.c_int32, C.c_double, C.c_double,
+                                      C.POINTER(_GenParams), C.c_int32, P, P, P,
+                                      C.POINTER(_GenResult), P, P, P]
+        _lib.orc_generate.restype = C.c_int
     return _lib
 
 
@@ -199,3 +219,51 @@ def adjoint(n, rowptr, colidx, vals, X, G) -> tuple[np.ndarray, np.ndarray]:
     """Gradients of sum(G * X) with X = L^{-1} B: (grad_B, grad_vals)."""
     Y = solve_transpose(n, rowptr, colidx, vals, G)
     return Y, grad_vals(n, rowptr, colidx, Y, X)
+
+
+@dataclass
+class Generated:
+    rows: np.ndarray        # int32 [moves], move order
+    src: np.ndarray         # source level of each move
+    tgt: np.ndarray         # target level of each move
+    moves: int
+    steps: int
+    stop: int               # GEN_NO_SOURCE / GEN_THIN / GEN_MOVES / GEN_STEPS
+    levels: int             # non-empty levels at the end
+    thin: int
+    thin0: int
+    rejected: int
+    threshold: float
+    S1: int
+    S2: int
+    cv: float
+    level_cost: np.ndarray  # int64 [D]
+    level_rows: np.ndarray  # int32 [D]
+    level_deps: np.ndarray  # int64 [D]
+
+
+def generate(n, rowptr, level, num_levels, alc, cv, *, alpha=1.0, thin_stop=0.02, max_dist=8,
+             max_moves=0, max_steps=0, cap=None) -> Generated:
+    """Rewriting list of the fixed-policy environment run (see orc_generate)."""
+    rowptr, level = _i32(rowptr), _i32(level)
+    cap = n if cap is None else int(cap)
+    D = int(num_levels)
+    prm = _GenParams(float(alpha), float(thin_stop), int(max_dist), int(max_moves),
+                     int(max_steps), 0)
+    res = _GenResult()
+    mr = np.zeros(max(cap, 1), dtype=np.int32)
+    ms = np.zeros(max(cap, 1), dtype=np.int32)
+    mt = np.zeros(max(cap, 1), dtype=np.int32)
+    oc = np.zeros(max(D, 1), dtype=np.int64)
+    orr = np.zeros(max(D, 1), dtype=np.int32)
+    od = np.zeros(max(D, 1), dtype=np.int64)
+    st = _L().orc_generate(n, _p(rowptr), _p(level), D, float(alc), float(cv), C.byref(prm),
+                           cap, _p(mr), _p(ms), _p(mt), C.byref(res), _p(oc), _p(orr), _p(od))
+    if st != OK:
+        raise ValueError("oracle generate: " + STATUS_NAMES.get(st, str(st)))
+    m = int(res.moves)
+    return Generated(mr[:m].copy(), ms[:m].copy(), mt[:m].copy(), m, int(res.steps),
+                     int(res.stop), int(res.levels), int(res.thin), int(res.thin0),
+                     int(res.rejected), float(res.threshold), int(res.S1),
+                     int(res.S2_lo) | (int(res.S2_hi) << 64), float(res.cv), oc[:D].copy(),
+                     orr[:D].copy(), od[:D].copy())

@@ -408,3 +408,208 @@ void orc_grad_vals(int32_t n, const int32_t *rowptr, const int32_t *colidx,
             gvals[p] = 0.0 - s;
         }
 }
+
+/* ------------------------------------------------------------------------
+ * Rewrite-list generator: the environment of Section 4.1 driven by a fixed
+ * policy instead of the learned one, with the node choice of Section 4.4
+ * and the target selection of Algorithm 1.  Written as plain scans over
+ * the level table at every step.
+ *
+ * State (Section 4.1, updated after each move without touching the DAG):
+ * the level of every row, and per level its cost (sum of 2*nnz_i - 1 over
+ * its rows, the row keeping its original cost when it moves), its row count
+ * and its indegree (sum of the dependency counts nnz_i - 1 of its rows).
+ * Level numbers never change; a level whose last row leaves is empty
+ * (collapsed) and is skipped by every search.
+ *
+ * thr = ALC * (1 + alpha * max(0, 1 - CV)) with the ALC and CV of the
+ * input (Section 4.1), fixed for the whole run; a level is thin when it is
+ * non-empty and its cost < thr.  T0 = thin levels at the start.
+ *
+ * One step:
+ *   source: among levels l >= 1 that are thin, never a target and not
+ *     rejected, the one with the fewest rows, ties to the lower level (a
+ *     level keeps being chosen until it empties: its row count only falls);
+ *   node: among the source's rows, the one with the fewest dependencies,
+ *     ties to the lower row index (Section 4.4);
+ *   target (Algorithm 1): p = nearest non-empty level above the source.
+ *     p == 0: the target is level 0 when level 0 is thin, else the step
+ *     is rejected.  p > 0: the target is the nearest thin level at or above
+ *     p (all target affinities equal: the closest of the search window);
+ *     with none, the fallback is p itself (a thin source may go to a thick
+ *     level).  A target farther than max_dist levels rejects the step;
+ *   a rejected step marks the source rejected (no later state change can
+ *     make it acceptable: levels above a source only gain cost or empty);
+ *   a move puts the node on the target level, updates the three per-level
+ *     sums of source and target, marks the target as a target level, and
+ *     appends <node, source, target> to the list.
+ * Before each step, in this order: stop THIN when T0 > 0 and
+ * thin / T0 < thin_stop; stop MOVES when the move limit (max_moves, 0 =
+ * cap, never above cap) is reached; stop STEPS when max_steps steps (0 =
+ * max(2 D, 3 * 2048)) were taken; stop NO_SOURCE when no source is left.
+ *
+ * Outputs: mv_row/mv_src/mv_tgt[cap] in move order; res (final non-empty
+ * levels, thin levels, and S1, exact S2 and CV of the non-empty levels'
+ * costs); out_cost/out_rows/out_deps[D] the final per-level sums (each
+ * nullable).
+ * ---------------------------------------------------------------------- */
+enum { ORC_GEN_NO_SOURCE = 0, ORC_GEN_THIN = 1, ORC_GEN_MOVES = 2, ORC_GEN_STEPS = 3 };
+
+typedef struct {
+    double alpha;
+    double thin_stop;
+    int32_t max_dist;
+    int32_t max_moves;
+    int32_t max_steps;
+    int32_t pad_;
+} orc_gen_params;
+
+typedef struct {
+    int32_t moves, steps, stop, levels, thin, thin0, rejected, pad_;
+    double threshold;
+    uint64_t S1, S2_lo, S2_hi;
+    double cv;
+} orc_gen_result;
+
+int orc_generate(int32_t n, const int32_t *rowptr, const int32_t *level, int32_t D,
+                 double alc, double cv, const orc_gen_params *prm, int32_t cap,
+                 int32_t *mv_row, int32_t *mv_src, int32_t *mv_tgt, orc_gen_result *res,
+                 int64_t *out_cost, int32_t *out_rows, int64_t *out_deps)
+{
+    memset(res, 0, sizeof *res);
+    if (n < 0 || D < 0 || cap < 0 || prm->max_dist < 0 || prm->max_moves < 0 ||
+        prm->max_steps < 0 || !(prm->alpha >= 0.0) || !(prm->thin_stop >= 0.0) ||
+        (n > 0 && D < 1))
+        return ORC_INVALID_ARG;
+    if (n == 0) return ORC_OK;
+
+    int32_t *lev = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t *cost = (int64_t *)calloc((size_t)D, sizeof(int64_t));
+    int64_t *deps = (int64_t *)calloc((size_t)D, sizeof(int64_t));
+    int32_t *rows = (int32_t *)calloc((size_t)D, sizeof(int32_t));
+    unsigned char *is_target = (unsigned char *)calloc((size_t)D, 1);
+    unsigned char *rejected = (unsigned char *)calloc((size_t)D, 1);
+    /* rows of each original level, ascending (counting sort) */
+    int32_t *optr = (int32_t *)calloc((size_t)D + 1, sizeof(int32_t));
+    int32_t *orows = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    for (int32_t i = 0; i < n; ++i) optr[level[i] + 1] += 1;
+    for (int32_t l = 0; l < D; ++l) optr[l + 1] += optr[l];
+    int32_t *cur = (int32_t *)malloc(sizeof(int32_t) * (size_t)D);
+    for (int32_t l = 0; l < D; ++l) cur[l] = optr[l];
+    for (int32_t i = 0; i < n; ++i) orows[cur[level[i]]++] = i;
+    free(cur);
+    for (int32_t i = 0; i < n; ++i) {
+        int64_t d = rowptr[i + 1] - rowptr[i] - 1;
+        lev[i] = level[i];
+        cost[lev[i]] += 2 * d + 1;
+        deps[lev[i]] += d;
+        rows[lev[i]] += 1;
+    }
+    double relax = 1.0 - cv;
+    if (relax < 0.0) relax = 0.0;
+    double scaled = prm->alpha * relax;
+    double factor = 1.0 + scaled;
+    const double thr = alc * factor;
+#define THIN(l) (rows[(l)] > 0 && (double)cost[(l)] < thr)
+    int32_t T0 = 0;
+    for (int32_t l = 0; l < D; ++l) T0 += THIN(l) ? 1 : 0;
+    int32_t max_moves = prm->max_moves > 0 && prm->max_moves < cap ? prm->max_moves : cap;
+    int64_t steps_default = 2 * (int64_t)D < 6144 ? 6144 : 2 * (int64_t)D;
+    if (steps_default > INT32_MAX) steps_default = INT32_MAX;
+    int32_t max_steps = prm->max_steps > 0 ? prm->max_steps : (int32_t)steps_default;
+    int32_t moves = 0, steps = 0, nrej = 0, stop;
+
+    for (;;) {
+        int32_t thin = 0;
+        for (int32_t l = 0; l < D; ++l) thin += THIN(l) ? 1 : 0;
+        if (T0 > 0 && (double)thin / (double)T0 < prm->thin_stop) { stop = ORC_GEN_THIN; break; }
+        if (moves >= max_moves) { stop = ORC_GEN_MOVES; break; }
+        if (steps >= max_steps) { stop = ORC_GEN_STEPS; break; }
+        int32_t src = -1;
+        for (int32_t l = 1; l < D; ++l) {
+            if (!THIN(l) || is_target[l] || rejected[l]) continue;
+            if (src < 0 || rows[l] < rows[src]) src = l;
+        }
+        if (src < 0) { stop = ORC_GEN_NO_SOURCE; break; }
+        steps += 1;
+
+        /* a source never received rows (it is not a target), so its rows
+         * are the unmoved ones among its original rows */
+        int32_t node = -1;
+        int64_t node_deps = 0;
+        for (int32_t q = optr[src]; q < optr[src + 1]; ++q) {
+            int32_t i = orows[q];
+            if (lev[i] != src) continue;
+            int64_t d = rowptr[i + 1] - rowptr[i] - 1;
+            if (node < 0 || d < node_deps) { node = i; node_deps = d; }
+        }
+
+        int32_t p = src - 1;
+        while (p > 0 && rows[p] == 0) --p;
+        int32_t tgt;
+        if (p == 0) {
+            tgt = THIN(0) ? 0 : -1;
+        } else {
+            tgt = -1;
+            for (int32_t l = p; l >= 0; --l)
+                if (THIN(l)) { tgt = l; break; }
+            if (tgt < 0) tgt = p;
+        }
+        if (tgt >= 0 && src - tgt > prm->max_dist) tgt = -1;
+        if (tgt < 0) {
+            rejected[src] = 1;
+            nrej += 1;
+            continue;
+        }
+
+        lev[node] = tgt;
+        cost[src] -= 2 * node_deps + 1;
+        deps[src] -= node_deps;
+        rows[src] -= 1;
+        cost[tgt] += 2 * node_deps + 1;
+        deps[tgt] += node_deps;
+        rows[tgt] += 1;
+        is_target[tgt] = 1;
+        mv_row[moves] = node;
+        mv_src[moves] = src;
+        mv_tgt[moves] = tgt;
+        moves += 1;
+    }
+
+    int32_t nonempty = 0, thin = 0;
+    int64_t *ne = (int64_t *)malloc(sizeof(int64_t) * (size_t)D);
+    for (int32_t l = 0; l < D; ++l) {
+        if (rows[l] > 0) ne[nonempty++] = cost[l];
+        thin += THIN(l) ? 1 : 0;
+    }
+#undef THIN
+    u128 S2;
+    uint64_t S1;
+    res->cv = cv_of(ne, nonempty, &S1, &S2);
+    res->S1 = S1;
+    res->S2_lo = (uint64_t)S2;
+    res->S2_hi = (uint64_t)(S2 >> 64);
+    res->moves = moves;
+    res->steps = steps;
+    res->stop = stop;
+    res->levels = nonempty;
+    res->thin = thin;
+    res->thin0 = T0;
+    res->rejected = nrej;
+    res->threshold = thr;
+    for (int32_t l = 0; l < D; ++l) {
+        if (out_cost) out_cost[l] = cost[l];
+        if (out_rows) out_rows[l] = rows[l];
+        if (out_deps) out_deps[l] = deps[l];
+    }
+    free(ne);
+    free(optr);
+    free(orows);
+    free(lev);
+    free(cost);
+    free(deps);
+    free(rows);
+    free(is_target);
+    free(rejected);
+    return ORC_OK;
+}
