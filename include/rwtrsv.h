@@ -276,6 +276,98 @@ rwt_status rwt_grad_vals(const rwt_csr* L, const void* d_gB, int64_t ldg, const 
                          int64_t ldx, int32_t k, void* d_gvals, rwt_stream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Rewrite-list generator: the environment of Section 4.1 run with a fixed
+ * policy in place of the learned one, one environment per parameter set,
+ * all over one matrix in one launch.  Each returns a rewriting list of
+ * <node, source level, target level> triplets (Algorithm 1) that
+ * rwt_rewrite_* or a batch's candidate lists take directly.
+ *
+ * State (Section 4.1, updated per move without touching the DAG): the level
+ * of every row and, per level, its cost (sum of 2*nnz_i - 1; a moved row
+ * keeps its original cost), row count and indegree (sum of nnz_i - 1).
+ * Level numbers never change; an emptied level is skipped by the searches.
+ * thr = ALC * (1 + alpha * max(0, 1 - CV)) from the input's ALC and CV,
+ * fixed for the run; thin = non-empty and cost < thr.
+ * One step:
+ *   source  the thin level >= 1 that never received a row and was never
+ *           rejected, with the fewest rows (ties: lower level);
+ *   node    its row with the fewest dependencies (ties: lower row),
+ *           Section 4.4;
+ *   target  Algorithm 1 with equal affinities: p = nearest non-empty level
+ *           above the source; p == 0: level 0 if thin, else reject; p > 0:
+ *           the nearest thin level at or above p, else p itself; reject when
+ *           source - target > max_dist (MAX_REWRITE_DISTANCE).  A rejected
+ *           source is not chosen again;
+ *   move    the row joins the target level; both levels' sums change; the
+ *           triplet is appended.
+ * Before each step, in this order: stop RWT_GEN_THIN when the initial thin
+ * count T0 > 0 and thin/T0 < thin_stop; RWT_GEN_MOVES at the move limit;
+ * RWT_GEN_STEPS at the step limit (rejected steps count); RWT_GEN_NO_SOURCE
+ * when no source is left.
+ *
+ * Inputs: L (pattern only), and from rwt_analyze of L: d_level[n],
+ * d_level_ptr[D+1], d_cost[D], d_stats (device) and D = num_levels.
+ * h_params[num_env] (host).  Outputs (device, caller-allocated): for
+ * environment e, moves q < d_res[e].moves at d_mv_row/src/tgt[e*cap + q] in
+ * move order; d_res[num_env]; optionally (nullable) the final per-level
+ * sums d_lev_cost/d_lev_rows/d_lev_deps[e*D + l].  Workspace:
+ * rwt_generate_ws bytes.  Asynchronous on the stream (the parameters are
+ * copied from the host before return).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    double alpha;        /* threshold relaxation, >= 0 (the paper uses 1.0) */
+    double thin_stop;    /* stop below this thin-level ratio (the paper: 0.02) */
+    int32_t max_dist;    /* largest source - target distance, >= 0 */
+    int32_t max_moves;   /* 0: cap */
+    int32_t max_steps;   /* 0: max(2 D, 3 * 2048) */
+    int32_t pad_;
+} rwt_gen_params;
+
+typedef enum {
+    RWT_GEN_NO_SOURCE = 0,
+    RWT_GEN_THIN = 1,
+    RWT_GEN_MOVES = 2,
+    RWT_GEN_STEPS = 3
+} rwt_gen_stop;
+
+typedef struct {
+    int32_t moves;
+    int32_t steps;       /* moves + rejected */
+    int32_t stop;        /* rwt_gen_stop */
+    int32_t levels;      /* non-empty levels at the end */
+    int32_t thin;        /* thin levels at the end */
+    int32_t thin0;       /* thin levels at the start */
+    int32_t rejected;
+    int32_t pad_;
+    double threshold;
+    uint64_t S1;         /* sum of the non-empty levels' costs */
+    uint64_t S2_lo;      /* sum of their squares, 128 bit */
+    uint64_t S2_hi;
+    double cv;           /* their CV, as in rwt_level_stats */
+} rwt_gen_result;
+
+rwt_status rwt_generate_ws(int32_t n, int32_t num_levels, int32_t num_env, size_t* h_bytes);
+rwt_status rwt_generate(const rwt_csr* L, const int32_t* d_level, const int32_t* d_level_ptr,
+                        const int64_t* d_cost, const rwt_level_stats* d_stats,
+                        int32_t num_levels, int32_t num_env, const rwt_gen_params* h_params,
+                        int32_t cap, int32_t* d_mv_row, int32_t* d_mv_src, int32_t* d_mv_tgt,
+                        rwt_gen_result* d_res, int64_t* d_lev_cost, int32_t* d_lev_rows,
+                        int64_t* d_lev_deps, void* d_ws, size_t ws_bytes,
+                        rwt_stream_t stream);
+
+/* Candidate row sets from generated lists, in the form the rewrite and the
+ * batch take: d_cand_ptr[num_env+1] (exclusive offsets of each
+ * environment's moves), d_cand_rows / d_cand_targets[num_env*cap] (each
+ * environment's moved rows ascending, with their target levels; targets
+ * nullable).  No host synchronization (graph-capturable).  Workspace:
+ * rwt_gen_rowsets_ws bytes; num_env*cap < 2^31. */
+rwt_status rwt_gen_rowsets_ws(int32_t num_env, int32_t cap, size_t* h_bytes);
+rwt_status rwt_gen_rowsets(int32_t n, int32_t num_env, int32_t cap, const rwt_gen_result* d_res,
+                           const int32_t* d_mv_row, const int32_t* d_mv_tgt,
+                           int32_t* d_cand_ptr, int32_t* d_cand_rows, int32_t* d_cand_targets,
+                           void* d_ws, size_t ws_bytes, rwt_stream_t stream);
+
+/* ------------------------------------------------------------------------
  * Batched launch: many matrices of uneven size, each with its own block of
  * right-hand sides, plus many candidate rewrite sets (rewriting lists in
  * the sense of Algorithm 1, one per environment step of the paper's agent)

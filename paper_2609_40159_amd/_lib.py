@@ -85,6 +85,24 @@ class BatchInfo(C.Structure):
                 ("captured", C.c_int32), ("create_ms", C.c_double)]
 
 
+class GenParams(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("thin_stop", C.c_double), ("max_dist", C.c_int32),
+                ("max_moves", C.c_int32), ("max_steps", C.c_int32), ("pad_", C.c_int32)]
+
+
+class GenResult(C.Structure):
+    _fields_ = [("moves", C.c_int32), ("steps", C.c_int32), ("stop", C.c_int32),
+                ("levels", C.c_int32), ("thin", C.c_int32), ("thin0", C.c_int32),
+                ("rejected", C.c_int32), ("pad_", C.c_int32), ("threshold", C.c_double),
+                ("S1", C.c_uint64), ("S2_lo", C.c_uint64), ("S2_hi", C.c_uint64),
+                ("cv", C.c_double)]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("pad_", "S2_lo", "S2_hi")}
+        d["S2"] = int(self.S2_lo) | (int(self.S2_hi) << 64)
+        return d
+
+
 P = C.c_void_p
 I32 = C.c_int32
 I64 = C.c_int64
@@ -126,6 +144,11 @@ SIGNATURES = {
     "rwt_batch_get_info": (C.c_int, [P, C.POINTER(BatchInfo)]),
     "rwt_batch_plan": (C.c_int, [P, I32, C.POINTER(P)]),
     "rwt_batch_destroy": (C.c_int, [P]),
+    "rwt_generate_ws": (C.c_int, [I32, I32, I32, C.POINTER(SZ)]),
+    "rwt_generate": (C.c_int, [C.POINTER(Csr), P, P, P, P, I32, I32, C.POINTER(GenParams), I32,
+                               P, P, P, P, P, P, P, P, SZ, P]),
+    "rwt_gen_rowsets_ws": (C.c_int, [I32, I32, C.POINTER(SZ)]),
+    "rwt_gen_rowsets": (C.c_int, [I32, I32, I32, P, P, P, P, P, P, P, SZ, P]),
 }
 
 _lib = None

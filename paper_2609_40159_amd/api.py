@@ -329,6 +329,91 @@ def grad_vals(L: CSRMatrix, gB: torch.Tensor, X: torch.Tensor) -> torch.Tensor:
     return out
 
 
+GEN_STOPS = {0: "no_source", 1: "thin", 2: "moves", 3: "steps"}
+
+
+@dataclass
+class Generated:
+    """Rewriting lists of num_env environments over one matrix (move order)."""
+    rows: torch.Tensor        # int32 (num_env, cap); environment e uses [:moves[e]]
+    src: torch.Tensor
+    tgt: torch.Tensor
+    results: list             # per environment: moves, steps, stop, levels, thin, ...
+    level_cost: torch.Tensor | None   # int64 (num_env, D) final per-level sums
+    level_rows: torch.Tensor | None
+    level_deps: torch.Tensor | None
+    d_res: torch.Tensor       # device copy of the results (rwt_gen_result array)
+    n: int
+    cap: int
+
+
+def _gen_params(params: dict) -> _lib.GenParams:
+    return _lib.GenParams(float(params.get("alpha", 1.0)), float(params.get("thin_stop", 0.02)),
+                          int(params.get("max_dist", 8)), int(params.get("max_moves", 0)),
+                          int(params.get("max_steps", 0)), 0)
+
+
+def generate(L: CSRMatrix, info: LevelInfo, params, cap: int, level_sums: bool = False,
+             sync: bool = True) -> Generated:
+    """Run one environment per parameter dict (keys alpha, thin_stop, max_dist,
+    max_moves, max_steps) on L; each keeps at most cap moves."""
+    lib = _lib.load()
+    if isinstance(params, dict):
+        params = [params]
+    ne = len(params)
+    n, D = L.n, info.num_levels
+    dev = L.device
+    sz = C.c_size_t(0)
+    check(lib.rwt_generate_ws(n, D, ne, C.byref(sz)))
+    ws = _workspace(sz.value, dev)
+    hp = (_lib.GenParams * max(ne, 1))(*[_gen_params(q) for q in params])
+    mr = torch.empty((ne, max(cap, 1)), dtype=torch.int32, device=dev)
+    ms = torch.empty_like(mr)
+    mt = torch.empty_like(mr)
+    d_res = torch.empty(max(ne, 1) * C.sizeof(_lib.GenResult), dtype=torch.uint8, device=dev)
+    lc = lr = ld = None
+    if level_sums:
+        lc = torch.empty((ne, max(D, 1)), dtype=torch.int64, device=dev)
+        lr = torch.empty((ne, max(D, 1)), dtype=torch.int32, device=dev)
+        ld = torch.empty((ne, max(D, 1)), dtype=torch.int64, device=dev)
+    check(lib.rwt_generate(C.byref(L.view()), _ptr(info.level), _ptr(info.level_ptr),
+                           _ptr(info.cost), _ptr(info.device_stats), D, ne, hp, cap, _ptr(mr),
+                           _ptr(ms), _ptr(mt), _ptr(d_res), _ptr(lc), _ptr(lr), _ptr(ld),
+                           _ptr(ws), ws.numel(), _stream()))
+    results = []
+    if sync and ne > 0:
+        raw = d_res.cpu().numpy().tobytes()
+        for e in range(ne):
+            r = _lib.GenResult.from_buffer_copy(raw, e * C.sizeof(_lib.GenResult))
+            d = r.as_dict()
+            d["stop_name"] = GEN_STOPS.get(d["stop"], "?")
+            results.append(d)
+    return Generated(mr[:, :cap], ms[:, :cap], mt[:, :cap], results,
+                     None if lc is None else lc[:, :D], None if lr is None else lr[:, :D],
+                     None if ld is None else ld[:, :D], d_res, n, cap)
+
+
+def gen_rowsets(g: Generated) -> tuple[torch.Tensor, torch.Tensor, torch.Tensor]:
+    """(cand_ptr, cand_rows, cand_targets): each environment's moved rows in
+    ascending order with their targets, concatenated (batch candidate form)."""
+    lib = _lib.load()
+    ne = g.rows.shape[0]
+    dev = g.rows.device
+    sz = C.c_size_t(0)
+    check(lib.rwt_gen_rowsets_ws(ne, g.cap, C.byref(sz)))
+    ws = _workspace(sz.value, dev)
+    ptr = torch.empty(ne + 1, dtype=torch.int32, device=dev)
+    rows = torch.empty(max(ne * g.cap, 1), dtype=torch.int32, device=dev)
+    tg = torch.empty_like(rows)
+    # the move arrays are (ne, cap) with row stride cap: contiguous only when
+    # cap >= 1 (the allocation keeps one column for cap == 0)
+    mr = g.rows.contiguous()
+    mt = g.tgt.contiguous()
+    check(lib.rwt_gen_rowsets(g.n, ne, g.cap, _ptr(g.d_res), _ptr(mr), _ptr(mt), _ptr(ptr),
+                              _ptr(rows), _ptr(tg), _ptr(ws), ws.numel(), _stream()))
+    return ptr, rows, tg
+
+
 class Batch:
     """Many matrices (each with k right-hand sides) and many candidate rewrite
     sets, run as one persistent launch (optionally a captured graph).

@@ -72,6 +72,10 @@ def test_host_only_calls(lib):
     assert lib.rwt_plan_ws(C.byref(c), C.byref(o), C.byref(sz)) == -1   # lanes not a power of 2
     o.lanes_per_row = 0
     assert lib.rwt_plan_ws(C.byref(c), C.byref(o), C.byref(sz)) == 0
+    assert lib.rwt_generate_ws(10, 11, 1, C.byref(sz)) == -1      # more levels than rows
+    assert lib.rwt_generate_ws(10, 3, 4, C.byref(sz)) == 0 and sz.value > 0
+    assert lib.rwt_gen_rowsets_ws(1 << 16, 1 << 16, C.byref(sz)) == -8
+    assert lib.rwt_gen_rowsets_ws(4, 100, C.byref(sz)) == 0 and sz.value > 0
     for field, bad in (("block_rows", (1 << 20) + 1), ("rhs_chunk", 5), ("tune_cols", -1)):
         setattr(o, field, bad)
         assert lib.rwt_plan_ws(C.byref(c), C.byref(o), C.byref(sz)) == -1, field
