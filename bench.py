@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the comparison solves (original DAG, forced schedules)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
+    ap.add_argument("--no-generator", action="store_true",
+                    help="skip the rewrite-list generator section")
     ap.add_argument("--batch-count", type=int, default=256, help="matrices in the batch")
     ap.add_argument("--batch-steps", type=int, default=5, help="timed batched launches")
     ap.add_argument("--gen-workers", type=int, default=min(16, os.cpu_count() or 1),
@@ -258,6 +260,118 @@ def run_batched(args, man, gen, dev):
     res["speedup_candidates_batched_vs_plain"] = res["candidates_per_s_batched"] * t_plain
     res["plain_candidate_sample"] = len(sample)
     res["batched_stats_equal_plain"] = bool(same)
+    return res
+
+
+def gen_grid():
+    """1024 parameter sets of the rewrite-list generator: MAX_REWRITE_DISTANCE,
+    threshold relaxation alpha, thin-ratio stop, move limit."""
+    import itertools
+    md = [1, 2, 3, 4, 6, 8, 12, 16]
+    al = [0.0, 0.25, 0.5, 0.75, 1.0, 1.5, 2.0, 3.0]
+    ts = [0.02, 0.3, 0.5, 0.7, 0.8, 0.85, 0.9, 0.95]
+    mm = [0, 2048]
+    return [dict(max_dist=a, alpha=b, thin_stop=c, max_moves=d)
+            for a, b, c, d in itertools.product(md, al, ts, mm)]
+
+
+def run_generator(args, L, Lh, info, dev):
+    """Rewrite-list generation for a grid of parameter sets on the workload's
+    matrix (one launch, one wave per environment), the lists turned into
+    candidate row sets and scored in one batched launch (levels and CV of
+    each rewritten matrix); a sample checked against the oracle."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2609_40159_amd import _lib
+    from paper_2609_40159_amd.api import Batch, gen_rowsets, generate
+
+    params = gen_grid()
+    ne, cap = len(params), 8192
+    res = {"workload": "matrix of the main workload", "envs": ne, "cap": cap}
+    generate(L, info, params[:4], cap)          # warm-up
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(3):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        g = generate(L, info, params, cap, sync=False)
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    g = generate(L, info, params, cap)
+    steps = sum(r["steps"] for r in g.results)
+    moves = sum(r["moves"] for r in g.results)
+    res.update({"generate_ms": float(np.median(ts)), "steps_total": steps, "moves_total": moves})
+    res["steps_per_s"] = steps / res["generate_ms"] * 1e3
+    res["envs_per_s"] = ne / res["generate_ms"] * 1e3
+    ts = []
+    for _ in range(3):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        ptr, rows, tg = gen_rowsets(g)
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    res["rowsets_ms"] = float(np.median(ts))
+    log("generator timed")
+    # scoring: every list as a batch candidate (L' is not formed)
+    total = int(ptr[-1])
+    pcap = 16 * max(1, total) + (1 << 20)
+    bt = None
+    for _ in range(4):
+        try:
+            bt = Batch([(L, None, None)], [0] * ne, ptr, rows, tg, cand_rows_cap=max(1, rows.numel()),
+                       pattern_cap=pcap)
+            bt.run()
+            st = bt.stats()
+            break
+        except _lib.RwtError as e:
+            if e.name != "TOO_LARGE":
+                raise
+            bt = None
+            pcap *= 4
+    res["pattern_cap"] = pcap
+    bt.capture()
+    ts = []
+    for _ in range(3):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(bt.stream)
+        bt.launch()
+        b.record(bt.stream)
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    st = bt.stats()
+    res["score_ms"] = float(np.median(ts))
+    res["candidates_per_s"] = ne / res["score_ms"] * 1e3
+    best = min(range(ne), key=lambda e: (st[e]["num_levels"], st[e]["cv"]))
+    res["best"] = {"params": params[best], "moves": g.results[best]["moves"],
+                   "levels": st[best]["num_levels"], "cv": st[best]["cv"],
+                   "levels_original": info.num_levels, "cv_original": info.stats["cv"],
+                   "env_levels": g.results[best]["levels"], "env_cv": g.results[best]["cv"]}
+    log("generated lists scored")
+    # oracle on a sample of environments (parity and single-core rate)
+    lv = info.level.cpu().numpy()
+    sample = list(range(0, ne, ne // 16))[:16]
+    t_or, steps_or, same = 0.0, 0, True
+    rows_h, src_h, tgt_h = g.rows.cpu().numpy(), g.src.cpu().numpy(), g.tgt.cpu().numpy()
+    for e in sample:
+        t1 = time.perf_counter()
+        o = oracle.generate(Lh.n, Lh.rowptr, lv, info.num_levels, info.stats["alc"],
+                            info.stats["cv"], cap=cap, **params[e])
+        t_or += time.perf_counter() - t1
+        steps_or += o.steps
+        m = o.moves
+        same = same and m == g.results[e]["moves"] and o.steps == g.results[e]["steps"] \
+            and np.array_equal(rows_h[e, :m], o.rows) and np.array_equal(src_h[e, :m], o.src) \
+            and np.array_equal(tgt_h[e, :m], o.tgt) and o.cv == g.results[e]["cv"]
+    res["oracle"] = {"envs_sampled": len(sample), "steps_per_s": steps_or / t_or, "cores": 1,
+                     "sample_equal": bool(same)}
+    del bt
     return res
 
 
@@ -482,6 +596,7 @@ def main():
             "latency_floor_note": f"{Dp} dependent levels on the critical path"}
     dom = "fwd" if ms["fwd"] >= ms["bwd"] else "bwd"
     roof = roofs[dom]
+    generator = None if args.no_generator else run_generator(args, L, Lh, info, dev)
     batched = run_batched(args, man, gen, dev) if man is not None else None
     if batched is not None:
         batched["host_generation_s"] = gen_s
@@ -516,6 +631,7 @@ def main():
         "relerr_vs_xstar": err,
         "roofline": roof,
         "roofline_other": roofs["bwd" if dom == "fwd" else "fwd"],
+        "generator": generator,
         "batched": batched,
         "cpu_baseline": cpu,
     }

@@ -128,8 +128,34 @@ struct GenArgs {
     int64_t* out_deps;
 };
 
-__device__ __forceinline__ bool thin_of(int32_t r, int64_t c, double thr) {
-    return r > 0 && (double)c < thr;
+// A level cost c is an integer below 2^32, exact in double, so
+// (double)c < thr holds exactly when c < ceil(thr): the comparison is done
+// on integers against that bound.
+__device__ __forceinline__ int64_t cost_bound(double thr) {
+    if (!(thr > 0.0)) return 0;
+    const double b = ceil(thr);
+    return b >= 9.0e18 ? INT64_MAX : (int64_t)b;
+}
+
+__device__ __forceinline__ bool thin_of(int32_t r, int64_t c, int64_t cb) {
+    return r > 0 && c < cb;
+}
+
+// The stop test thin / T0 < thin_stop (double division) is monotone in the
+// thin count, which only falls: it holds exactly when thin <= the largest
+// k in [0, T0] that passes it (-1 when none does).
+__device__ __forceinline__ int32_t thin_stop_count(int32_t T0, double ts) {
+    if (T0 <= 0) return -1;
+    auto pass = [&](int32_t k) { return (double)k / (double)T0 < ts; };
+    if (!pass(0)) return -1;
+    int32_t lo = 0, hi = T0;            // pass(lo) holds
+    if (pass(hi)) return hi;
+    while (hi - lo > 1) {                // pass(hi) fails
+        const int32_t mid = lo + (hi - lo) / 2;
+        if (pass(mid)) lo = mid;
+        else hi = mid;
+    }
+    return lo;
 }
 
 // a value that lane 0 stored earlier, read by lane 0 and given to every lane
@@ -137,7 +163,10 @@ template <typename T>
 __device__ __forceinline__ T lane0_load(const T* p) {
     T v = T(0);
     if (lane_id() == 0) v = *p;
-    return __shfl(v, 0);
+    if constexpr (sizeof(T) < 4)
+        return (T)__shfl((int)v, 0);
+    else
+        return __shfl(v, 0);
 }
 
 __global__ void __launch_bounds__(WAVE) k_gen_env(GenArgs a) {
@@ -157,6 +186,7 @@ __global__ void __launch_bounds__(WAVE) k_gen_env(GenArgs a) {
     const double scaled = prm.alpha * relax;
     const double factor = 1.0 + scaled;
     const double thr = a.stats->alc * factor;
+    const int64_t cb = cost_bound(thr);
 
     int32_t T0 = 0;
     for (int32_t l = lane; l < D; l += WAVE) {
@@ -166,9 +196,10 @@ __global__ void __launch_bounds__(WAVE) k_gen_env(GenArgs a) {
         cost[l] = c;
         deps[l] = a.deps0[l];
         flags[l] = 0;
-        T0 += thin_of(r, c, thr) ? 1 : 0;
+        T0 += thin_of(r, c, cb) ? 1 : 0;
     }
     T0 = wave_sum(T0);
+    const int32_t kstop = thin_stop_count(T0, prm.thin_stop);
     const int32_t maxm = prm.max_moves > 0 && prm.max_moves < a.cap ? prm.max_moves : a.cap;
     int64_t ms = prm.max_steps > 0 ? prm.max_steps : 2 * (int64_t)D;
     if (prm.max_steps <= 0 && ms < 6144) ms = 6144;
@@ -179,11 +210,13 @@ __global__ void __launch_bounds__(WAVE) k_gen_env(GenArgs a) {
     int32_t s_rows = 0;
     int64_t s_cost = 0, s_deps = 0;
     int32_t tc = -1;                  // target: level >= 0, -1 unknown, -2 fallback p
-    int32_t t_rows = 0;
+    int32_t t_rows = 0, t_flags = 0;
     int64_t t_cost = 0, t_deps = 0;
+    int32_t pf_q = -1;                // table position of the prefetched entry
+    int2 pf_en = make_int2(0, 0);
     __syncthreads();
     for (;;) {
-        if (T0 > 0 && (double)thin / (double)T0 < prm.thin_stop) {
+        if (thin <= kstop) {
             stop = RWT_GEN_THIN;
             break;
         }
@@ -205,7 +238,7 @@ __global__ void __launch_bounds__(WAVE) k_gen_env(GenArgs a) {
                 bool ok = false;
                 if (q < D - 1) {
                     l = a.lorder[q];
-                    ok = flags[l] == 0 && thin_of(rows[l], cost[l], thr);
+                    ok = flags[l] == 0 && thin_of(rows[l], cost[l], cb);
                 }
                 const uint64_t m = __ballot(ok);
                 if (m) {
@@ -238,6 +271,7 @@ __global__ void __launch_bounds__(WAVE) k_gen_env(GenArgs a) {
                 t_rows = lane0_load(&rows[0]);
                 t_cost = lane0_load(&cost[0]);
                 t_deps = lane0_load(&deps[0]);
+                t_flags = lane0_load(&flags[0]);
             }
         }
         // next row of the source in (deps, row) order; an index outside the
@@ -248,21 +282,25 @@ __global__ void __launch_bounds__(WAVE) k_gen_env(GenArgs a) {
             break;
         }
         ++steps;
-        const int2 en = a.ent[qn];
+        // the entry was loaded one step ahead while the source stays the
+        // same; the load of the next one is in flight during this step
+        const int2 en = qn == pf_q ? pf_en : a.ent[qn];
+        pf_q = qn + 1 < a.n ? qn + 1 : qn;
+        pf_en = a.ent[pf_q];
 
         // Algorithm 1
         int32_t t = -1;
         if (p == 0) {
-            if (thin_of(t_rows, t_cost, thr)) t = 0;
+            if (thin_of(t_rows, t_cost, cb)) t = 0;
         } else {
-            if (tc == -1 || (tc >= 0 && !thin_of(t_rows, t_cost, thr))) {
+            if (tc == -1 || (tc >= 0 && !thin_of(t_rows, t_cost, cb))) {
                 const int32_t start = tc == -1 ? p : tc - 1;
                 const int32_t lo = src - prm.max_dist > 0 ? src - prm.max_dist : 0;
                 __syncthreads();
                 int32_t f = -1;
                 for (int32_t base = start; base >= lo && f < 0; base -= WAVE) {
                     const int32_t l = base - lane;
-                    const uint64_t m = __ballot(l >= lo && thin_of(rows[l], cost[l], thr));
+                    const uint64_t m = __ballot(l >= lo && thin_of(rows[l], cost[l], cb));
                     if (m) f = base - __builtin_ctzll(m);
                 }
                 if (f >= 0) {
@@ -272,7 +310,7 @@ __global__ void __launch_bounds__(WAVE) k_gen_env(GenArgs a) {
                     bool beyond = false;
                     while (mt < lo) {
                         const int32_t l = mt + lane;
-                        const uint64_t m = __ballot(l < lo && thin_of(rows[l], cost[l], thr));
+                        const uint64_t m = __ballot(l < lo && thin_of(rows[l], cost[l], cb));
                         if (m) {
                             mt += __builtin_ctzll(m);
                             beyond = true;
@@ -287,13 +325,14 @@ __global__ void __launch_bounds__(WAVE) k_gen_env(GenArgs a) {
                     t_rows = lane0_load(&rows[tl]);
                     t_cost = lane0_load(&cost[tl]);
                     t_deps = lane0_load(&deps[tl]);
+                    t_flags = lane0_load(&flags[tl]);
                 }
             }
             t = tc >= 0 ? tc : (tc == -2 ? p : -1);
         }
         if (t >= 0 && src - t > prm.max_dist) t = -1;
         if (t < 0) {
-            if (lane == 0) flags[src] = (uint8_t)(flags[src] | GEN_REJ);
+            if (lane == 0) flags[src] = GEN_REJ;   // a valid source had no flag
             ++rej;
             src = -1;
             continue;
@@ -301,14 +340,14 @@ __global__ void __launch_bounds__(WAVE) k_gen_env(GenArgs a) {
 
         // the move: state of Section 4.1, the row keeping its original cost
         const int64_t d = en.y, c = 2 * d + 1;
-        const int32_t before = (thin_of(s_rows, s_cost, thr) ? 1 : 0) + (thin_of(t_rows, t_cost, thr) ? 1 : 0);
+        const int32_t before = (thin_of(s_rows, s_cost, cb) ? 1 : 0) + (thin_of(t_rows, t_cost, cb) ? 1 : 0);
         s_rows -= 1;
         s_cost -= c;
         s_deps -= d;
         t_rows += 1;
         t_cost += c;
         t_deps += d;
-        thin += (thin_of(s_rows, s_cost, thr) ? 1 : 0) + (thin_of(t_rows, t_cost, thr) ? 1 : 0) - before;
+        thin += (thin_of(s_rows, s_cost, cb) ? 1 : 0) + (thin_of(t_rows, t_cost, cb) ? 1 : 0) - before;
         if (lane == 0) {
             rows[src] = s_rows;
             cost[src] = s_cost;
@@ -316,12 +355,13 @@ __global__ void __launch_bounds__(WAVE) k_gen_env(GenArgs a) {
             rows[t] = t_rows;
             cost[t] = t_cost;
             deps[t] = t_deps;
-            flags[t] = (uint8_t)(flags[t] | GEN_TGT);
+            if (!(t_flags & GEN_TGT)) flags[t] = (uint8_t)(t_flags | GEN_TGT);
             const size_t o = (size_t)e * a.cap + moves;
             a.mv_row[o] = en.x;
             a.mv_src[o] = src;
             a.mv_tgt[o] = t;
         }
+        t_flags |= GEN_TGT;
         ++moves;
         if (s_rows == 0) src = -1;
     }
@@ -338,7 +378,7 @@ __global__ void __launch_bounds__(WAVE) k_gen_env(GenArgs a) {
             s1 += (uint64_t)c;
             s2 = u128_add(s2, u128_sq((uint64_t)c));
         }
-        th += thin_of(r, c, thr) ? 1 : 0;
+        th += thin_of(r, c, cb) ? 1 : 0;
         if (a.out_cost) a.out_cost[(size_t)e * D + l] = c;
         if (a.out_rows) a.out_rows[(size_t)e * D + l] = r;
         if (a.out_deps) a.out_deps[(size_t)e * D + l] = deps[l];
