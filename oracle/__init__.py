@@ -80,6 +80,8 @@ def _L():
         _lib.orc_solve.restype = None
         _lib.orc_solve_transpose.argtypes = _lib.orc_solve.argtypes
         _lib.orc_solve_transpose.restype = None
+        _lib.orc_solve_upper.argtypes = _lib.orc_solve.argtypes
+        _lib.orc_solve_upper.restype = None
         _lib.orc_grad_vals.argtypes = [C.c_int32, P, P, C.c_int32, P, C.c_int64, P,
                                        C.c_int64, P]
         _lib.orc_grad_vals.restype = None
@@ -195,6 +197,23 @@ def solve(n, rowptr, colidx, vals, B) -> np.ndarray:
     _L().orc_solve(n, _p(_i32(rowptr)), _p(_i32(colidx)), _p(_f64(vals)), B.shape[0],
                    _p(B), n, _p(X), n)
     return X
+
+
+def solve_upper(n, rowptr, colidx, vals, B) -> np.ndarray:
+    """X = U^{-1} B for an upper-triangular CSR U (diagonal first in each row);
+    B has shape (k, n)."""
+    B = _f64(np.atleast_2d(B))
+    X = np.zeros_like(B)
+    _L().orc_solve_upper(n, _p(_i32(rowptr)), _p(_i32(colidx)), _p(_f64(vals)), B.shape[0],
+                         _p(B), n, _p(X), n)
+    return X
+
+
+def solve_pair(n, l_rowptr, l_colidx, l_vals, u_rowptr, u_colidx, u_vals, B) -> np.ndarray:
+    """X = U^{-1} (L^{-1} B): the preconditioner application of an incomplete
+    LU factorization."""
+    Y = solve(n, l_rowptr, l_colidx, l_vals, B)
+    return solve_upper(n, u_rowptr, u_colidx, u_vals, Y)
 
 
 def solve_transpose(n, rowptr, colidx, vals, G) -> np.ndarray:

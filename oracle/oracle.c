@@ -367,6 +367,32 @@ void orc_solve(int32_t n, const int32_t *rowptr, const int32_t *colidx,
 }
 
 /* ------------------------------------------------------------------------
+ * solve_upper: backward substitution U X = B for an upper-triangular CSR U
+ * whose rows hold the diagonal first, then ascending columns (the U factor
+ * of an incomplete LU, applied after L in a preconditioned iteration).  For
+ * i descending and each right-hand side: s = b_i, s -= U_ij x_j over the
+ * off-diagonal entries in ascending column order, x_i = s / U_ii.
+ * ---------------------------------------------------------------------- */
+void orc_solve_upper(int32_t n, const int32_t *rowptr, const int32_t *colidx,
+                     const double *vals, int32_t k, const double *B, int64_t ldb,
+                     double *X, int64_t ldx)
+{
+    for (int32_t c = 0; c < k; ++c) {
+        const double *b = B + c * ldb;
+        double *x = X + c * ldx;
+        for (int32_t i = n - 1; i >= 0; --i) {
+            double s = b[i];
+            int32_t d = rowptr[i];
+            for (int32_t p = d + 1; p < rowptr[i + 1]; ++p) {
+                double prod = vals[p] * x[colidx[p]];
+                s = s - prod;
+            }
+            x[i] = s / vals[d];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------
  * Adjoint of x = L^{-1} b.  With y = L^{-T} g (backward substitution on the
  * transposed system) the gradients are grad_b = y and
  * grad_L[i][j] = -y_i x_j, summed over right-hand sides, on L's stored

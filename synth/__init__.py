@@ -211,6 +211,26 @@ def random_lower(n: int, density: float, seed: int, *, diag_lo: float = 1.0,
     return _assemble(n, None, rowptr, colidx, vals)
 
 
+def transpose_upper(L: CSR, seed: int | None = None) -> CSR:
+    """U = L^T as an upper-triangular CSR (rows hold the diagonal first, then
+    ascending columns).  With a seed, the values are redrawn: off-diagonal
+    N(0,1)/(entries in the row), diagonal U[1,2] -- the second factor of an
+    incomplete-LU-like pair with the pattern of L^T."""
+    n = L.n
+    rows = L.row_of_entry()
+    order = np.argsort(L.colidx, kind="stable")     # by U row, then by U column
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(L.colidx, minlength=n), out=rowptr[1:])
+    colidx = rows[order].astype(np.int32)
+    vals = L.vals[order].copy()
+    if seed is not None:
+        rng = np.random.default_rng([seed, 11])
+        cnt = np.diff(rowptr)
+        vals = rng.standard_normal(colidx.size) / np.maximum(1, np.repeat(cnt - 1, cnt))
+        vals[rowptr[:-1]] = rng.uniform(1.0, 2.0, n)
+    return CSR(n, rowptr.astype(np.int32), colidx, vals)
+
+
 def rhs(L: CSR, k: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
     """x* ~ U[-1,1] (shape (k, n), column q contiguous) and B = L x* in FP64.
 

@@ -543,6 +543,59 @@ def test_solve_special_cases(orc):
 
 
 # ---------------------------------------------------------------------------
+# upper-triangular solve and the L-then-U pair
+# ---------------------------------------------------------------------------
+
+def _uppers():
+    return [("lap2d", synth.transpose_upper(synth.laplacian_2d(40, 30))),
+            ("powerlaw", synth.transpose_upper(synth.power_law(3000, 4), seed=1)),
+            ("random", synth.transpose_upper(synth.random_lower(400, 0.03, 5), seed=2)),
+            ("lap3d", synth.transpose_upper(synth.laplacian_3d(12, 10, 9), seed=3))]
+
+
+@pytest.mark.parametrize("i", range(4))
+def test_solve_upper_matches_scipy_and_known_solution(orc, i):
+    name, U = _uppers()[i]
+    A = scipy.sparse.csr_matrix((U.vals, U.colidx, U.rowptr), shape=(U.n, U.n))
+    assert scipy.sparse.tril(A, -1).nnz == 0
+    rng = np.random.default_rng(i)
+    B = rng.standard_normal((2, U.n))
+    x = orc.solve_upper(U.n, U.rowptr, U.colidx, U.vals, B)
+    ref = scipy.sparse.linalg.spsolve_triangular(A, B.T, lower=False).T
+    assert _relerr(x, ref) <= 1e-12, name
+    xs, Bs = synth.rhs(U, 3, 10 + i)
+    assert _relerr(orc.solve_upper(U.n, U.rowptr, U.colidx, U.vals, Bs), xs) <= 1e-12, name
+
+
+def test_solve_upper_special_cases(orc):
+    x = orc.solve_upper(1, np.array([0, 1]), np.array([0]), np.array([4.0]), np.array([[3.0]]))
+    assert x[0, 0] == 0.75
+    # U = I - 0.5 * superdiagonal, b = 1: x_i = 2 - 2^-(n-1-i)
+    n = 30
+    rowptr = np.concatenate([[0], np.cumsum([2] * (n - 1) + [1])])
+    cols = np.concatenate([[i, i + 1] for i in range(n - 1)] + [[n - 1]])
+    vals = np.concatenate([[1.0, -0.5] for _ in range(n - 1)] + [[1.0]])
+    x = orc.solve_upper(n, rowptr, cols, vals, np.ones((1, n)))
+    assert np.allclose(x[0], 2 - 0.5 ** (n - 1 - np.arange(n)), rtol=0, atol=1e-15)
+    # U = L^T: the upper solve is the transposed solve of L
+    L = synth.power_law(2000, 8)
+    U = synth.transpose_upper(L)
+    G = np.random.default_rng(3).standard_normal((2, L.n))
+    assert _relerr(orc.solve_upper(U.n, U.rowptr, U.colidx, U.vals, G),
+                   orc.solve_transpose(L.n, L.rowptr, L.colidx, L.vals, G)) <= 1e-13
+
+
+def test_solve_pair_matches_dense_product(orc):
+    L = synth.random_lower(200, 0.05, 21)
+    U = synth.transpose_upper(synth.random_lower(200, 0.05, 22), seed=23)
+    B = np.random.default_rng(4).standard_normal((3, 200))
+    x = orc.solve_pair(200, L.rowptr, L.colidx, L.vals, U.rowptr, U.colidx, U.vals, B)
+    M = L.to_dense() @ U.to_dense()
+    ref = np.linalg.solve(M, B.T).T
+    assert _relerr(x, ref) <= 1e-10
+
+
+# ---------------------------------------------------------------------------
 # adjoint
 # ---------------------------------------------------------------------------
 
