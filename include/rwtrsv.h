@@ -242,6 +242,49 @@ rwt_status rwt_solve_transpose(const rwt_plan* plan, const void* d_G, int32_t k,
 rwt_status rwt_plan_check(const rwt_plan* plan, rwt_stream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Upper-triangular solves and the L-then-U pair: applying an incomplete LU
+ * preconditioner M = L U in an iterative solver means one forward solve
+ * with L and one backward solve with U per iteration, which is the use the
+ * cost of rewriting is amortized over (a few hundred iterations).
+ *
+ * U: CSR, each row holding its diagonal first, then strictly ascending
+ * columns above it (FP64 or FP32 values, non-zero diagonal).  The upper
+ * plan solves through the lower matrix J U J (J reverses the index order),
+ * with every schedule and the autotuner of rwt_plan_create (opts as there).
+ * rwt_upper_create checks U (synchronizes): a violation is reported with
+ * the status of the matching lower check -- RWT_ERR_NOT_LOWER for an entry
+ * below the diagonal or a column out of range, RWT_ERR_UNSORTED_OR_DUP,
+ * RWT_ERR_MISSING_DIAG (first entry not the diagonal), RWT_ERR_ZERO_DIAG --
+ * and the U row in rwt_last_error_string; RWT_ERR_INVALID_ARG for row
+ * pointers that are not a CSR index.  The plan keeps U's pointers and a
+ * copy of its values in the reversed order: after changing U's values call
+ * rwt_upper_refresh.  Workspace: rwt_upper_ws bytes (holds the reversed
+ * pattern, an n x kmax block and the inner plan).
+ *
+ * rwt_upper_solve:           X = U^{-1} B   (backward substitution)
+ * rwt_upper_solve_transpose: Y = U^{-T} G
+ * rwt_solve_pair:            X = U^{-1} (L^{-1} B), L a lower plan of the
+ *                            same size and value type; k <= both kmax.
+ * d_X may equal d_B.  Dense blocks column-major, ld >= n.
+ * ---------------------------------------------------------------------- */
+typedef struct rwt_upper rwt_upper;
+
+rwt_status rwt_upper_ws(const rwt_csr* U, const rwt_plan_opts* opts, size_t* h_bytes);
+rwt_status rwt_upper_create(const rwt_csr* U, const rwt_plan_opts* opts, void* d_ws,
+                            size_t ws_bytes, rwt_upper** out, rwt_stream_t stream);
+rwt_status rwt_upper_refresh(rwt_upper* up, rwt_stream_t stream);
+rwt_status rwt_upper_get_info(const rwt_upper* up, rwt_plan_info* h_info);
+rwt_status rwt_upper_solve(const rwt_upper* up, const void* d_B, int32_t k, int64_t ldb,
+                           void* d_X, int64_t ldx, rwt_stream_t stream);
+rwt_status rwt_upper_solve_transpose(const rwt_upper* up, const void* d_G, int32_t k,
+                                     int64_t ldg, void* d_Y, int64_t ldy, rwt_stream_t stream);
+rwt_status rwt_solve_pair(const rwt_plan* L, const rwt_upper* U, const void* d_B, int32_t k,
+                          int64_t ldb, void* d_X, int64_t ldx, rwt_stream_t stream);
+/* device error word of the last solve (as rwt_plan_check; synchronizes) */
+rwt_status rwt_upper_check(const rwt_upper* up, rwt_stream_t stream);
+rwt_status rwt_upper_destroy(rwt_upper* up);
+
+/* ------------------------------------------------------------------------
  * Adjoint helpers.  With X = L^{-1} B, G = dLoss/dX and the rewritten system
  * L' = M L, B' = M B (M = I - C):  Y = L'^{-T} G, grad_B = M^T Y = Y - C^T Y
  * and grad_L = -grad_B X^T restricted to L's pattern.

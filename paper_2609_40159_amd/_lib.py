@@ -144,6 +144,15 @@ SIGNATURES = {
     "rwt_batch_get_info": (C.c_int, [P, C.POINTER(BatchInfo)]),
     "rwt_batch_plan": (C.c_int, [P, I32, C.POINTER(P)]),
     "rwt_batch_destroy": (C.c_int, [P]),
+    "rwt_upper_ws": (C.c_int, [C.POINTER(Csr), C.POINTER(PlanOpts), C.POINTER(SZ)]),
+    "rwt_upper_create": (C.c_int, [C.POINTER(Csr), C.POINTER(PlanOpts), P, SZ, C.POINTER(P), P]),
+    "rwt_upper_refresh": (C.c_int, [P, P]),
+    "rwt_upper_get_info": (C.c_int, [P, C.POINTER(PlanInfo)]),
+    "rwt_upper_solve": (C.c_int, [P, P, I32, I64, P, I64, P]),
+    "rwt_upper_solve_transpose": (C.c_int, [P, P, I32, I64, P, I64, P]),
+    "rwt_solve_pair": (C.c_int, [P, P, P, I32, I64, P, I64, P]),
+    "rwt_upper_check": (C.c_int, [P, P]),
+    "rwt_upper_destroy": (C.c_int, [P]),
     "rwt_generate_ws": (C.c_int, [I32, I32, I32, C.POINTER(SZ)]),
     "rwt_generate": (C.c_int, [C.POINTER(Csr), P, P, P, P, I32, I32, C.POINTER(GenParams), I32,
                                P, P, P, P, P, P, P, P, SZ, P]),

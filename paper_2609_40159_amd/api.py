@@ -297,6 +297,80 @@ class Plan:
         check(self._lib.rwt_plan_check(self._h, _stream()))
 
 
+class UpperPlan(Plan):
+    """Solves U X = B and U^T Y = G for an upper-triangular CSR U (diagonal
+    first in each row), through the reversed lower matrix J U J."""
+
+    def __init__(self, U: CSRMatrix, algo: str = "auto", kmax: int = 1, block_rows: int = 0,
+                 lanes_per_row: int = 0, narrow_rows: int = -1, watchdog_ms: int = 0,
+                 rhs_chunk: int = 0):
+        lib = _lib.load()
+        self.L = U
+        self._lib = lib
+        o = _lib.PlanOpts()
+        o.algo = _lib.ALGO[algo]
+        o.block_rows = block_rows
+        o.lanes_per_row = lanes_per_row
+        o.narrow_rows = narrow_rows
+        o.kmax = kmax
+        o.watchdog_ms = watchdog_ms
+        o.rhs_chunk = rhs_chunk
+        self.opts = o
+        sz = C.c_size_t(0)
+        check(lib.rwt_upper_ws(C.byref(U.view()), C.byref(o), C.byref(sz)))
+        self.ws = _workspace(sz.value, U.device)
+        h = C.c_void_p()
+        check(lib.rwt_upper_create(C.byref(U.view()), C.byref(o), _ptr(self.ws),
+                                   self.ws.numel(), C.byref(h), _stream()))
+        self._h = h
+        self.kmax = kmax
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.rwt_upper_destroy(h)
+            self._h = None
+
+    @property
+    def info(self) -> dict:
+        inf = _lib.PlanInfo()
+        check(self._lib.rwt_upper_get_info(self._h, C.byref(inf)))
+        d = {f: getattr(inf, f) for f, _ in inf._fields_ if f not in ("stats", "pad_")}
+        d["algo_fwd"] = _lib.ALGO_NAME[d["algo_fwd"]]
+        d["algo_bwd"] = _lib.ALGO_NAME[d["algo_bwd"]]
+        d["stats"] = inf.stats.as_dict()
+        return d
+
+    def levels(self):
+        raise NotImplementedError("the levels of an upper plan belong to its reversed matrix")
+
+    def refresh(self) -> None:
+        """Take U's current values (after they were changed in place)."""
+        check(self._lib.rwt_upper_refresh(self._h, _stream()))
+
+    def solve(self, B: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        return self._run(self._lib.rwt_upper_solve, B, out)
+
+    def solve_transpose(self, G: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        return self._run(self._lib.rwt_upper_solve_transpose, G, out)
+
+    def check(self) -> None:
+        check(self._lib.rwt_upper_check(self._h, _stream()))
+
+
+def solve_pair(Lp: Plan, Up: UpperPlan, B: torch.Tensor,
+               out: torch.Tensor | None = None) -> torch.Tensor:
+    """X = U^{-1} (L^{-1} B): one application of the preconditioner M = L U."""
+    lib = _lib.load()
+    n = Lp.L.n
+    B2, k = _block(B, n, Lp.L.dtype)
+    X = torch.empty_like(B2) if out is None else out
+    if X.shape != B2.shape or not X.is_contiguous():
+        raise ValueError("output must match the right-hand side block")
+    check(lib.rwt_solve_pair(Lp._h, Up._h, _ptr(B2), k, n, _ptr(X), n, _stream()))
+    return X.reshape(B.shape)
+
+
 def apply_MT(rw: Rewrite, Y: torch.Tensor) -> torch.Tensor:
     """Y - C^T Y for the multipliers of a rewrite (grad_B of the rewritten system)."""
     lib = _lib.load()
