@@ -53,6 +53,7 @@ def parse():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the comparison solves (original DAG, forced schedules)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
+    ap.add_argument("--no-pair", action="store_true", help="skip the L-then-U pair section")
     ap.add_argument("--no-generator", action="store_true",
                     help="skip the rewrite-list generator section")
     ap.add_argument("--batch-count", type=int, default=256, help="matrices in the batch")
@@ -375,6 +376,70 @@ def run_generator(args, L, Lh, info, dev):
     return res
 
 
+def run_pair(args, L, Lh, dev, k, plan_rw=None, rwres=None):
+    """The L-then-U pair of an incomplete factorization M = L L^T (U = L^T, an
+    upper CSR with the diagonal first): one preconditioner application per
+    call, and the upper solve alone."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import synth
+    from paper_2609_40159_amd.api import CSRMatrix, Plan, UpperPlan, apply_M, solve_pair
+
+    Uh = synth.transpose_upper(Lh)
+    U = CSRMatrix.from_arrays(Uh.rowptr, Uh.colidx, Uh.vals, device=dev, dtype=L.dtype)
+    t0 = time.perf_counter()
+    Up = UpperPlan(U, kmax=k)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    Lp = Plan(L, kmax=k)
+    rng = np.random.default_rng(5)
+    Bh = rng.standard_normal((k, Lh.n))
+    B = torch.as_tensor(Bh).to(device=dev, dtype=L.dtype).contiguous()
+    X = torch.empty_like(B)
+
+    def timed(fn, reps=20):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts))
+
+    pair_ms = timed(lambda: solve_pair(Lp, Up, B, out=X))
+    up_ms = timed(lambda: Up.solve(B, out=X))
+    rw_pair_ms = rw_err = None
+    if plan_rw is not None:
+        # with the rewritten factor: X = U^-1 L'^-1 (M B) = U^-1 L^-1 B
+        rw_pair_ms = timed(lambda: solve_pair(plan_rw, Up, apply_M(rwres, B), out=X))
+    Up.check()
+    s = 8 if L.dtype == torch.float64 else 4
+    b_pair = bytes_solve(Lh.n, Lh.nnz, k, s) * 2
+    t1 = time.perf_counter()
+    ref = oracle.solve_pair(Lh.n, Lh.rowptr, Lh.colidx, Lh.vals, Uh.rowptr, Uh.colidx, Uh.vals, Bh)
+    t_or = time.perf_counter() - t1
+    Xh = solve_pair(Lp, Up, B, out=X).double().cpu().numpy()
+    err = float(np.max(np.abs(Xh - ref)) / np.max(np.abs(ref)))
+    if plan_rw is not None:
+        Xr = solve_pair(plan_rw, Up, apply_M(rwres, B)).double().cpu().numpy()
+        rw_err = float(np.max(np.abs(Xr - ref)) / np.max(np.abs(ref)))
+    return {"what": "X = U^-1 L^-1 B with U = L^T (upper CSR), main workload's original factor",
+            "rhs": k, "upper_plan_ms": plan_ms, "upper_algo": Up.info["algo_fwd"],
+            "upper_block_rows": Up.info["block_rows"], "pair_ms": pair_ms, "upper_ms": up_ms,
+            "pair_gbs": b_pair / pair_ms / 1e6, "applications_per_s": 1e3 / pair_ms,
+            "relerr_vs_oracle": err, "oracle_pair_ms": t_or * 1e3, "oracle_cores": 1,
+            "rewritten_pair_ms": rw_pair_ms, "rewritten_relerr_vs_oracle": rw_err,
+            "speedup_rewritten_pair": None if rw_pair_ms is None else pair_ms / rw_pair_ms}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -597,6 +662,7 @@ def main():
     dom = "fwd" if ms["fwd"] >= ms["bwd"] else "bwd"
     roof = roofs[dom]
     generator = None if args.no_generator else run_generator(args, L, Lh, info, dev)
+    pair = None if args.no_pair else run_pair(args, L, Lh, dev, k, plan, rwres)
     batched = run_batched(args, man, gen, dev) if man is not None else None
     if batched is not None:
         batched["host_generation_s"] = gen_s
@@ -632,6 +698,7 @@ def main():
         "roofline": roof,
         "roofline_other": roofs["bwd" if dom == "fwd" else "fwd"],
         "generator": generator,
+        "pair": pair,
         "batched": batched,
         "cpu_baseline": cpu,
     }

@@ -297,6 +297,19 @@ rwt_status rwt_upper_destroy(rwt_upper* up);
  * rwt_grad_vals: d_gvals[p] = -sum_q d_gB[row_p, q] * d_X[col_p, q] for every
  * stored entry p of the pattern of L (diagonal included).
  * ---------------------------------------------------------------------- */
+/* rwt_apply_M: d_out = M d_B = d_B - C d_B for the multipliers of a rewrite
+ * (grouped by d_crow ascending, as rwt_rewrite_numeric writes them; each
+ * row's substitutions applied in their order, so the result equals the B'
+ * of the rewrite bit for bit).  This is the right-hand side transform of
+ * the rewritten system for a new B: solving L' X = M B gives L^{-1} B, e.g.
+ * in each application of a preconditioner with the rewritten factor.
+ * Workspace: rwt_apply_M_ws(n) bytes (row offsets of the multipliers,
+ * rebuilt by every call).  d_out may not alias d_B. */
+rwt_status rwt_apply_M_ws(int32_t n, size_t* h_bytes);
+rwt_status rwt_apply_M(int32_t n, int64_t nC, const int32_t* d_crow, const int32_t* d_ccol,
+                       const void* d_cval, rwt_dtype dt, const void* d_B, int32_t k,
+                       int64_t ldb, void* d_out, int64_t ldo, void* d_ws, size_t ws_bytes,
+                       rwt_stream_t stream);
 rwt_status rwt_apply_MT_ws(int32_t n, int64_t nC, size_t* h_bytes);
 rwt_status rwt_apply_MT(int32_t n, int64_t nC, const int32_t* d_crow, const int32_t* d_ccol,
                         const void* d_cval, rwt_dtype dt, const void* d_Y, int32_t k, int64_t ldy,
@@ -423,6 +436,13 @@ rwt_status rwt_gen_rowsets(int32_t n, int32_t num_env, int32_t cap, const rwt_ge
  * largest size whose x values fit in LDS (the whole matrix in one
  * workgroup, level after level, when it fits), one column per chain,
  * unless block_rows fixes the block size.
+ * Candidate levels are computed either as a chain of row-block tasks (the
+ * blocks of the matrix's solve schedule, waiting on each other's levels)
+ * or by one workgroup sweeping the original levels in order (every row of
+ * an original level at once: a rewritten row's new dependencies lie on
+ * earlier original levels too).  With cand_mode 0 a matrix's candidates
+ * take the sweep when its block chain has at least four times as many
+ * level steps as the matrix has levels (wide levels), else the chain.
  * Per candidate c: the matrix h_cand_mat[c] and the rows
  * d_cand_rows[d_cand_ptr[c] .. d_cand_ptr[c+1]) (strictly ascending) with
  * targets d_cand_targets (NULL: level - 1).  Each launch recomputes, for
@@ -457,7 +477,8 @@ typedef struct {
     int32_t cand_rows_cap;              /* capacity of the concatenated row lists */
     int32_t pattern_cap;                /* capacity of rewritten-row patterns (0: 64 per row) */
     int32_t watchdog_ms;
-    int32_t pad_;
+    int32_t cand_mode;                  /* candidate levels: 0 choose per matrix, 1 row-block
+                                           chains, 2 one level sweep per candidate */
 } rwt_batch_desc;
 
 typedef struct {
@@ -470,11 +491,13 @@ typedef struct {
 } rwt_cand_stats;
 
 typedef struct {
-    int32_t tasks;        /* row-block tasks of the persistent launch */
+    int32_t tasks;        /* tasks of the persistent launch */
     int32_t solve_tasks;
     int32_t grid;
     int32_t captured;     /* a graph is instantiated */
     double create_ms;
+    int32_t sweep_cands;  /* candidates scored by one level sweep */
+    int32_t pad_;
 } rwt_batch_info;
 
 typedef struct rwt_batch rwt_batch;

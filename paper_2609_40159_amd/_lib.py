@@ -72,7 +72,7 @@ class BatchDesc(C.Structure):
                 ("h_cand_mat", C.c_void_p), ("d_cand_ptr", C.c_void_p),
                 ("d_cand_rows", C.c_void_p), ("d_cand_targets", C.c_void_p),
                 ("cand_rows_cap", C.c_int32), ("pattern_cap", C.c_int32),
-                ("watchdog_ms", C.c_int32), ("pad_", C.c_int32)]
+                ("watchdog_ms", C.c_int32), ("cand_mode", C.c_int32)]
 
 
 class CandStats(C.Structure):
@@ -82,7 +82,8 @@ class CandStats(C.Structure):
 
 class BatchInfo(C.Structure):
     _fields_ = [("tasks", C.c_int32), ("solve_tasks", C.c_int32), ("grid", C.c_int32),
-                ("captured", C.c_int32), ("create_ms", C.c_double)]
+                ("captured", C.c_int32), ("create_ms", C.c_double), ("sweep_cands", C.c_int32),
+                ("pad_", C.c_int32)]
 
 
 class GenParams(C.Structure):
@@ -135,6 +136,8 @@ SIGNATURES = {
     "rwt_apply_MT_prepare": (C.c_int, [I32, I64, P, P, SZ, P]),
     "rwt_apply_MT_apply": (C.c_int, [I32, I64, P, P, I32, P, I32, I64, P, I64, P, SZ, P]),
     "rwt_grad_vals": (C.c_int, [C.POINTER(Csr), P, I64, P, I64, I32, P, P]),
+    "rwt_apply_M_ws": (C.c_int, [I32, C.POINTER(SZ)]),
+    "rwt_apply_M": (C.c_int, [I32, I64, P, P, P, I32, P, I32, I64, P, I64, P, SZ, P]),
     "rwt_batch_ws": (C.c_int, [C.POINTER(BatchDesc), C.POINTER(SZ)]),
     "rwt_batch_create": (C.c_int, [C.POINTER(BatchDesc), P, SZ, C.POINTER(P), P]),
     "rwt_batch_run": (C.c_int, [P, P]),

@@ -390,6 +390,21 @@ def apply_MT(rw: Rewrite, Y: torch.Tensor) -> torch.Tensor:
     return out.reshape(Y.shape)
 
 
+def apply_M(rw: Rewrite, B: torch.Tensor) -> torch.Tensor:
+    """M B = B - C B: the right-hand side of the rewritten system for a new B."""
+    lib = _lib.load()
+    n = rw.L.n
+    B2, k = _block(B, n, rw.L.dtype)
+    sz = C.c_size_t(0)
+    check(lib.rwt_apply_M_ws(n, C.byref(sz)))
+    ws = _workspace(sz.value, B.device)
+    out = torch.empty_like(B2)
+    check(lib.rwt_apply_M(n, rw.crow.numel(), _ptr(rw.crow), _ptr(rw.ccol), _ptr(rw.cval),
+                          _dt(rw.L.dtype), _ptr(B2), k, n, _ptr(out), n, _ptr(ws), ws.numel(),
+                          _stream()))
+    return out.reshape(B.shape)
+
+
 def grad_vals(L: CSRMatrix, gB: torch.Tensor, X: torch.Tensor) -> torch.Tensor:
     """-sum_q gB[row_p, q] * X[col_p, q] on every stored entry of L."""
     lib = _lib.load()
@@ -502,7 +517,7 @@ class Batch:
 
     def __init__(self, mats, cand_mat, cand_ptr, cand_rows, cand_targets=None,
                  cand_rows_cap: int | None = None, pattern_cap: int = 0, watchdog_ms: int = 0,
-                 block_rows=None):
+                 block_rows=None, cand_mode: str = "auto"):
         lib = _lib.load()
         self._lib = lib
         self.mats = list(mats)
@@ -545,6 +560,7 @@ class Batch:
                               else (cand_rows.numel() if cand_rows is not None else 0))
         d.pattern_cap = pattern_cap
         d.watchdog_ms = watchdog_ms
+        d.cand_mode = {"auto": 0, "blocks": 1, "sweep": 2}[cand_mode]
         self.desc = d
         sz = C.c_size_t(0)
         check(lib.rwt_batch_ws(C.byref(d), C.byref(sz)))
@@ -604,7 +620,7 @@ class Batch:
     def info(self) -> dict:
         i = _lib.BatchInfo()
         check(self._lib.rwt_batch_get_info(self._h, C.byref(i)))
-        return {f: getattr(i, f) for f, _ in i._fields_}
+        return {f: getattr(i, f) for f, _ in i._fields_ if f != "pad_"}
 
     def solve_plain(self, which=None) -> None:
         """Solve the given matrices (default: all) one launch each with their

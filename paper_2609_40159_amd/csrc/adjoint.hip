@@ -55,6 +55,24 @@ __global__ void k_apply_mt(const int32_t* ptr, const int32_t* ent, const int32_t
     }
 }
 
+// out[r,q] = B[r,q] - sum over the substitutions e of row r, in their order,
+// of cval[e] * B[ccol[e], q]  (B' = M B; rows without substitutions copied)
+template <typename T>
+__global__ void k_apply_m(const int32_t* ptr, const int32_t* ccol, const T* cval, const T* B,
+                          int64_t ldb, T* out, int64_t ldo, int32_t n, int32_t k) {
+    const int64_t total = (int64_t)n * k;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = t / n, r = t - q * n;
+        T v = B[r + q * ldb];
+        for (int32_t e = ptr[r]; e < ptr[r + 1]; ++e) {
+            const int32_t j = ccol[e];
+            if ((uint32_t)j < (uint32_t)n) v = sub_rn(v, mul_rn(cval[e], B[j + q * ldb]));
+        }
+        out[r + q * ldo] = v;
+    }
+}
+
 // grad_vals[p] = 0 - sum_q gB[row_p, q] * X[col_p, q]: a workgroup takes 256
 // rows and their contiguous entries; each thread finds its row by binary
 // search in the workgroup's slice of row pointers.
@@ -188,6 +206,45 @@ extern "C" rwt_status rwt_apply_MT(int32_t n, int64_t nC, const int32_t* d_crow,
     RWT_TRY(rwt_apply_MT_prepare(n, nC, d_ccol, d_ws, ws_bytes, stream));
     return rwt_apply_MT_apply(n, nC, d_crow, d_cval, dt, d_Y, k, ldy, d_out, ldo, d_ws, ws_bytes,
                               stream);
+}
+
+extern "C" rwt_status rwt_apply_M_ws(int32_t n, size_t* h_bytes) {
+    RWT_REQUIRE(h_bytes != nullptr && n >= 0, RWT_ERR_INVALID_ARG, "bad argument");
+    *h_bytes = (((size_t)n + 1) * sizeof(int32_t) + 255) & ~size_t(255);
+    return RWT_OK;
+}
+
+extern "C" rwt_status rwt_apply_M(int32_t n, int64_t nC, const int32_t* d_crow,
+                                  const int32_t* d_ccol, const void* d_cval, rwt_dtype dt,
+                                  const void* d_B, int32_t k, int64_t ldb, void* d_out,
+                                  int64_t ldo, void* d_ws, size_t ws_bytes, rwt_stream_t stream) {
+    RWT_REQUIRE(n >= 0 && nC >= 0 && k >= 0, RWT_ERR_INVALID_ARG, "negative size");
+    RWT_REQUIRE(nC < (int64_t(1) << 31), RWT_ERR_TOO_LARGE, "too many multipliers");
+    RWT_REQUIRE(dt == RWT_F64 || dt == RWT_F32, RWT_ERR_INVALID_ARG, "bad dtype");
+    RWT_REQUIRE(nC == 0 || (d_crow && d_ccol && d_cval), RWT_ERR_INVALID_ARG, "null multipliers");
+    RWT_REQUIRE(k == 0 || (d_B && d_out && ldb >= n && ldo >= n), RWT_ERR_INVALID_ARG,
+                "bad dense blocks");
+    RWT_REQUIRE(k == 0 || d_B != d_out, RWT_ERR_INVALID_ARG, "output may not alias B");
+    size_t need = 0;
+    RWT_TRY(rwt_apply_M_ws(n, &need));
+    RWT_REQUIRE(d_ws && ws_bytes >= need, RWT_ERR_BUFFER_TOO_SMALL,
+                "apply_M workspace must hold %zu bytes", need);
+    if (n == 0 || k == 0) return RWT_OK;
+    hipStream_t s = hs(stream);
+    int32_t* ptr = static_cast<int32_t*>(d_ws);
+    // the multipliers come grouped by row, rows ascending (rwt_rewrite_numeric)
+    RWT_TRY(segment_starts(reinterpret_cast<const uint32_t*>(d_crow), nC, n, ptr, nullptr, s));
+    const unsigned g = blocks_for((size_t)n * k, 256, 8192);
+    if (dt == RWT_F64)
+        hipLaunchKernelGGL(k_apply_m<double>, dim3(g), dim3(256), 0, s, ptr, d_ccol,
+                           static_cast<const double*>(d_cval), static_cast<const double*>(d_B), ldb,
+                           static_cast<double*>(d_out), ldo, n, k);
+    else
+        hipLaunchKernelGGL(k_apply_m<float>, dim3(g), dim3(256), 0, s, ptr, d_ccol,
+                           static_cast<const float*>(d_cval), static_cast<const float*>(d_B), ldb,
+                           static_cast<float*>(d_out), ldo, n, k);
+    RWT_LAUNCHED();
+    return RWT_OK;
 }
 
 extern "C" rwt_status rwt_grad_vals(const rwt_csr* L, const void* d_gB, int64_t ldg,

@@ -45,7 +45,10 @@ constexpr int NSLAB_B = 2;
 
 struct BatchMatDev {
     int32_t n, R, lanes, nblocks, k, kc;   // kc: right-hand sides per solve chain
+    int32_t D, sweep;                      // levels; candidates take the level sweep
     int64_t ldb, ldx;
+    const int32_t* perm;                   // rows in (level, row) order
+    const int32_t* lptr;                   // level offsets in perm
     const int32_t* rowptr;
     const int32_t* colidx;
     const int32_t* level;
@@ -205,6 +208,98 @@ __device__ __forceinline__ void level_block(const BatchKArgs& a, const BatchMatD
     }
 }
 
+// All levels of candidate c by one workgroup: the original levels in order,
+// each one's rows all at once (one lane per row).  A row's dependencies --
+// its own, or a rewritten row's new list -- lie on earlier original levels,
+// published by this workgroup before the barrier that ended their level; a
+// load that still shows another launch's tag (a stale cache line) is
+// repeated with a device-scope load.
+__device__ __forceinline__ void sweep_cand(const BatchKArgs& a, const BatchMatDev& M,
+                                           const BatchCandDev& Cd, int32_t c, uint32_t tag) {
+    const int32_t qb = a.cand_ptr[c], qe = a.cand_ptr[c + 1];
+    const bool bad = a.cand_bad[c] != 0;
+    int32_t* err = &a.ctrl->err;
+    // each thread takes SR rows of a level at a time; every stage's loads
+    // (positions, row extents, bitmap words, dependencies, their levels) are
+    // issued for all SR rows before any is used
+    constexpr int SR = 4, U = 4;
+    const int32_t span = (int32_t)blockDim.x * SR;
+    for (int32_t l = 0; l < M.D; ++l) {
+        const int32_t beg = M.lptr[l], end = M.lptr[l + 1];
+        for (int32_t base = beg + threadIdx.x; base < end; base += span) {
+            int32_t row[SR], db[SR], de[SR], mx[SR];
+            const int32_t* dep[SR];
+#pragma unroll
+            for (int r = 0; r < SR; ++r) {
+                const int32_t pos = base + r * (int32_t)blockDim.x;
+                row[r] = M.perm[pos < end ? pos : beg];
+            }
+#pragma unroll
+            for (int r = 0; r < SR; ++r) {
+                db[r] = M.rowptr[row[r]];
+                de[r] = M.rowptr[row[r] + 1] - 1;   // without the diagonal
+                dep[r] = M.colidx;
+                mx[r] = -1;
+            }
+            uint32_t bw[SR];
+#pragma unroll
+            for (int r = 0; r < SR; ++r) bw[r] = Cd.bitmap[row[r] >> 5];
+#pragma unroll
+            for (int r = 0; r < SR; ++r) {
+                if (!bad && ((bw[r] >> (row[r] & 31)) & 1u)) {
+                    const int32_t q = lower_bound_g(a.rows, qb, qe, row[r]);
+                    db[r] = a.pat_ptr[q];
+                    de[r] = a.pat_ptr[q + 1] - 1;
+                    dep[r] = a.pat;
+                }
+            }
+            // dependencies, U per row per round
+            bool more = true;
+            for (int32_t p0 = 0; more; p0 += U) {
+                int32_t jv[SR][U];
+#pragma unroll
+                for (int r = 0; r < SR; ++r)
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int32_t p = db[r] + p0 + u;
+                        const bool in = p < de[r];
+                        const int32_t jj = dep[r][in ? p : db[r]];
+                        const bool ok = in && jj >= 0 && jj < row[r];
+                        if (in && !ok)
+                            __hip_atomic_store(err, (int32_t)RWT_ERR_INVALID_ARG, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                        jv[r][u] = ok ? jj : -1;
+                    }
+                int32_t lvv[SR][U];
+#pragma unroll
+                for (int r = 0; r < SR; ++r)
+#pragma unroll
+                    for (int u = 0; u < U; ++u) lvv[r][u] = Cd.lev[jv[r][u] < 0 ? row[r] : jv[r][u]];
+                more = false;
+#pragma unroll
+                for (int r = 0; r < SR; ++r) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        if (jv[r][u] < 0) continue;
+                        const int32_t v = lvv[r][u];
+                        const int32_t lj = ((uint32_t)v >> 24) == tag
+                                               ? (v & 0xffffff)
+                                               : wait_level(&Cd.lev[jv[r][u]], tag, err, a.ticks);
+                        mx[r] = lj > mx[r] ? lj : mx[r];
+                    }
+                    more = more || db[r] + p0 + U < de[r];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < SR; ++r)
+                if (base + r * (int32_t)blockDim.x < end)
+                    st_relaxed(&Cd.lev[row[r]], (int32_t)((tag << 24) | (uint32_t)(mx[r] + 1)));
+        }
+        __syncthreads();
+        if (ld_relaxed(err) != 0) return;
+    }
+}
+
 __device__ U128 block_sum_u128_bt(U128 v, unsigned char* scratch) {
     uint64_t* s = reinterpret_cast<uint64_t*>(scratch);
     for (int o = WAVE / 2; o > 0; o >>= 1) {
@@ -337,6 +432,13 @@ __global__ void __launch_bounds__(BT_THREADS) k_batch_main(BatchKArgs a) {
             b.lds_rows = M.R;
             if (M.kc == 1) sf_block<double, false, 1>(b, s_raw);
             else sf_block<double, false, 4>(b, s_raw);
+        } else if (tk.x == 2) {
+            const int32_t c = tk.y;
+            const BatchCandDev& Cd = a.cands[c];
+            const BatchMatDev& M = a.mats[Cd.m];
+            sweep_cand(a, M, Cd, c, tag);
+            __syncthreads();
+            finalize_cand(a, M, Cd, c, tag, s_raw);
         } else {
             const int32_t c = tk.y;
             const BatchCandDev& Cd = a.cands[c];
@@ -474,7 +576,7 @@ struct rwt_batch {
     BatchRwMat* d_rwmats = nullptr;
     int32_t* d_cand_mat = nullptr;
     int4* d_tasks = nullptr;
-    int32_t ntasks = 0, solve_tasks = 0;
+    int32_t ntasks = 0, solve_tasks = 0, sweep_cands = 0;
     uint32_t* bitmaps = nullptr;
     int64_t bitmap_words = 0;
     int32_t* levs = nullptr;
@@ -534,6 +636,8 @@ rwt_status layout_batch(const rwt_batch_desc* d, BatchLayout* L) {
     RWT_REQUIRE(d != nullptr && d->count >= 0 && d->num_cand >= 0, RWT_ERR_INVALID_ARG,
                 "bad batch descriptor");
     RWT_REQUIRE(d->count == 0 || d->mats != nullptr, RWT_ERR_INVALID_ARG, "null matrix list");
+    RWT_REQUIRE(d->cand_mode >= 0 && d->cand_mode <= 2, RWT_ERR_INVALID_ARG,
+                "cand_mode must be 0, 1 or 2");
     RWT_REQUIRE(d->num_cand == 0 ||
                     (d->h_cand_mat && d->d_cand_ptr && d->d_cand_rows && d->cand_rows_cap >= 0),
                 RWT_ERR_INVALID_ARG, "null candidate arrays");
@@ -750,6 +854,9 @@ extern "C" rwt_status rwt_batch_create(const rwt_batch_desc* desc, void* d_ws, s
         d.desc = p->desc_f;
         d.step_pos = p->step_pos;
         d.blk_step = p->blk_step;
+        d.D = p->D;
+        d.perm = p->perm;
+        d.lptr = p->level_ptr;
         d.B = static_cast<const double*>(M.B);
         d.X = static_cast<double*>(M.X);
         hr[m].n = M.L.n;
@@ -830,6 +937,25 @@ extern "C" rwt_status rwt_batch_create(const rwt_batch_desc* desc, void* d_ws, s
             }
         }
     }
+    // candidate mode per matrix: the level sweep when the block chain has
+    // many more level steps than the matrix has levels
+    {
+        std::vector<int32_t> steps(desc->count, 0);
+        for (int32_t m = 0; m < desc->count; ++m)
+            if (hm[m].nblocks > 0 &&
+                hipMemcpyAsync(&steps[m], hm[m].blk_step + hm[m].nblocks, sizeof(int32_t),
+                               hipMemcpyDeviceToHost, s) != hipSuccess) {
+                set_hip_error(hipGetLastError(), "batch step counts");
+                return fail(RWT_ERR_HIP);
+            }
+        if (hipStreamSynchronize(s) != hipSuccess) {
+            set_hip_error(hipGetLastError(), "batch step counts");
+            return fail(RWT_ERR_HIP);
+        }
+        for (int32_t m = 0; m < desc->count; ++m)
+            hm[m].sweep = desc->cand_mode == 2 ||
+                          (desc->cand_mode == 0 && (int64_t)steps[m] >= 4 * (int64_t)hm[m].D);
+    }
     struct T {
         int32_t key;
         int4 t;
@@ -846,7 +972,15 @@ extern "C" rwt_status rwt_batch_create(const rwt_batch_desc* desc, void* d_ws, s
     for (int32_t m = 0; m < desc->count; ++m)
         for (int32_t c = 0; c * hm[m].kc < b->mats[m].k; ++c) add_chain(m, 0, m, c);
     b->solve_tasks = (int32_t)tv.size();
-    for (int32_t c = 0; c < desc->num_cand; ++c) add_chain(hc[c].m, 1, c, 0);
+    b->sweep_cands = 0;
+    for (int32_t c = 0; c < desc->num_cand; ++c) {
+        if (hm[hc[c].m].sweep) {
+            tv.push_back({0, make_int4(2, c, 0, 0)});   // one task, ready at once
+            ++b->sweep_cands;
+        } else {
+            add_chain(hc[c].m, 1, c, 0);
+        }
+    }
     std::stable_sort(tv.begin(), tv.end(), [](const T& x, const T& y) { return x.key < y.key; });
     std::vector<int4> tasks(tv.size());
     for (size_t i = 0; i < tv.size(); ++i) tasks[i] = tv[i].t;
@@ -960,6 +1094,8 @@ extern "C" rwt_status rwt_batch_get_info(const rwt_batch* b, rwt_batch_info* h) 
     h->grid = b->grid;
     h->captured = b->exec != nullptr;
     h->create_ms = b->create_ms;
+    h->sweep_cands = b->sweep_cands;
+    h->pad_ = 0;
     return RWT_OK;
 }
 

@@ -64,7 +64,7 @@ def pack(cands, with_targets):
     return [m for m, _, _ in cands], ptr.astype(np.int32), rows, tg
 
 
-def make_batch(mats, cands, with_targets=False, cap_extra=0, pattern_cap=0):
+def make_batch(mats, cands, with_targets=False, cap_extra=0, pattern_cap=0, cand_mode="auto"):
     from paper_2609_40159_amd.api import Batch
     gm, rhs = [], []
     for _, L, k in mats:
@@ -87,7 +87,8 @@ def make_batch(mats, cands, with_targets=False, cap_extra=0, pattern_cap=0):
     if with_targets:
         d_t = torch.zeros(max(cap, 1), dtype=torch.int32, device=DEV)
         d_t[:tg.size] = torch.as_tensor(tg, device=DEV)
-    bt = Batch(gm, cm, d_ptr, d_rows, d_t, cand_rows_cap=cap, pattern_cap=pattern_cap)
+    bt = Batch(gm, cm, d_ptr, d_rows, d_t, cand_rows_cap=cap, pattern_cap=pattern_cap,
+               cand_mode=cand_mode)
     return bt, gm, rhs
 
 
@@ -312,3 +313,32 @@ def test_batch_argument_errors():
     rows = torch.zeros(1, dtype=torch.int32, device=DEV)
     with pytest.raises(RwtError):
         Batch([(L, None, None)], [3], ptr, rows)                      # bad matrix index
+
+
+def test_batch_candidate_modes_agree(orc):
+    """Row-block chains and per-candidate level sweeps give the same
+    statistics (both equal to the oracle's), for every matrix and mode."""
+    mats = mixed_matrices()
+    cands = explicit(candidate_sets(orc, mats, 5), levels_of(orc, mats))
+    levels = levels_of(orc, mats)
+    need = pattern_need(orc, mats, cands, levels)
+    got = {}
+    for mode in ("blocks", "sweep", "auto"):
+        bt, gm, rhs = make_batch(mats, cands, with_targets=True, pattern_cap=need, cand_mode=mode)
+        info = bt.info
+        if mode == "blocks":
+            assert info["sweep_cands"] == 0
+        elif mode == "sweep":
+            assert info["sweep_cands"] == len(cands)
+        bt.run()
+        check_solves(orc, mats, gm, rhs)
+        got[mode] = bt.stats()
+        check_cands(orc, mats, cands, got[mode], levels)
+        if mode == "sweep":
+            # replays reuse the level arrays under new launch tags
+            bt.capture()
+            for _ in range(3):
+                bt.launch()
+                torch.cuda.synchronize()
+                assert bt.stats() == got[mode]
+    assert got["blocks"] == got["sweep"] == got["auto"]

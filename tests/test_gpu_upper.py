@@ -153,3 +153,31 @@ def test_upper_validation_reports_rows():
             UpperPlan(make(rows, vals))
         assert ei.value.name == code, (rows, ei.value)
         assert f"U row {row}" in str(ei.value), (rows, ei.value)
+
+
+@pytest.mark.parametrize("which", ["lap3d_20x18x16", "powerlaw_30k", "lap3d_128"])
+def test_apply_M_and_pair_with_rewritten_factor(orc, which):
+    """M B equals the rewrite's B' bit for bit, and the pair with the
+    rewritten factor, U^{-1} L'^{-1} (M B), equals U^{-1} L^{-1} B."""
+    from paper_2609_40159_amd.api import Plan, UpperPlan, analyze, apply_M, rewrite, solve_pair
+    Lh = {"lap3d_20x18x16": lambda: synth.laplacian_3d(20, 18, 16),
+          "powerlaw_30k": lambda: synth.power_law(30000, 17),
+          "lap3d_128": lambda: synth.laplacian_3d(128, 128, 128)}[which]()
+    Uh = synth.transpose_upper(Lh, seed=5)
+    print(f"rewritten pair: {which}", flush=True)
+    k = 1 if which == "lap3d_128" else 3
+    G = to_gpu(Lh)
+    info = analyze(G)
+    lv = host(info.level)
+    rows, targets = synth.thin_first_rows(lv, 0.01 if which != "powerlaw_30k" else 0.008)
+    B = np.random.default_rng(11).standard_normal((k, Lh.n))
+    rw = rewrite(G, info.level, torch.as_tensor(rows, device=DEV),
+                 torch.as_tensor(targets, device=DEV), block(B))
+    MB = apply_M(rw, block(B))
+    assert torch.equal(MB, rw.B.reshape(MB.shape))
+    Lp = Plan(rw.L, kmax=k)
+    Up = UpperPlan(to_gpu(Uh), kmax=k)
+    X = solve_pair(Lp, Up, MB)
+    Lp.check()
+    ref = orc.solve_pair(Lh.n, Lh.rowptr, Lh.colidx, Lh.vals, Uh.rowptr, Uh.colidx, Uh.vals, B)
+    assert relerr(host(X), ref) <= 1e-12
