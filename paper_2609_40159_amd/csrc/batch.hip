@@ -84,6 +84,8 @@ struct BatchKArgs {
     Ctrl* ctrl;
     const uint32_t* epoch;
     int64_t ticks;
+    int32_t hist_cap;   // level-cost histogram entries that fit the launch's LDS
+    int32_t pad;
 };
 
 __device__ __forceinline__ uint32_t epoch_tag(uint32_t e) { return (e % 255u) + 1u; }
@@ -349,7 +351,7 @@ __device__ __forceinline__ void finalize_cand(const BatchKArgs& a, const BatchMa
     const int32_t D = block_max_bt(mx, reinterpret_cast<int32_t*>(s_raw)) + 1;
     const int32_t qb = a.cand_ptr[c], qe = a.cand_ptr[c + 1];
     uint32_t* hist = reinterpret_cast<uint32_t*>(s_raw + 256);
-    const int32_t HC = (BT_LDS - 256) / 4;
+    const int32_t HC = a.hist_cap;
     uint64_t s1 = 0;
     U128 s2{0, 0};
     for (int32_t lb = 0; lb < D; lb += HC) {
@@ -577,6 +579,7 @@ struct rwt_batch {
     int32_t* d_cand_mat = nullptr;
     int4* d_tasks = nullptr;
     int32_t ntasks = 0, solve_tasks = 0, sweep_cands = 0;
+    int32_t lds_bytes = BT_LDS;   // dynamic LDS of the persistent launch
     uint32_t* bitmaps = nullptr;
     int64_t bitmap_words = 0;
     int32_t* levs = nullptr;
@@ -787,8 +790,10 @@ rwt_status enqueue_run(rwt_batch* b, hipStream_t s) {
     ka.ctrl = b->ctrl;
     ka.epoch = b->epoch;
     ka.ticks = watchdog_ticks(d.watchdog_ms);
+    ka.hist_cap = (b->lds_bytes - 256) / 4;
+    ka.pad = 0;
     if (b->ntasks > 0) {
-        hipLaunchKernelGGL(k_batch_main, dim3(b->grid), dim3(BT_THREADS), BT_LDS, s, ka);
+        hipLaunchKernelGGL(k_batch_main, dim3(b->grid), dim3(BT_THREADS), b->lds_bytes, s, ka);
         RWT_LAUNCHED();
     }
     return RWT_OK;
@@ -937,6 +942,7 @@ extern "C" rwt_status rwt_batch_create(const rwt_batch_desc* desc, void* d_ws, s
             }
         }
     }
+    std::vector<int32_t> cand_count(desc->count, 0);
     // candidate mode per matrix: the level sweep when the block chain has
     // many more level steps than the matrix has levels
     {
@@ -952,6 +958,7 @@ extern "C" rwt_status rwt_batch_create(const rwt_batch_desc* desc, void* d_ws, s
             set_hip_error(hipGetLastError(), "batch step counts");
             return fail(RWT_ERR_HIP);
         }
+        for (int32_t c = 0; c < desc->num_cand; ++c) cand_count[hc[c].m] += 1;
         for (int32_t m = 0; m < desc->count; ++m)
             hm[m].sweep = desc->cand_mode == 2 ||
                           (desc->cand_mode == 0 && (int64_t)steps[m] >= 4 * (int64_t)hm[m].D);
@@ -1006,9 +1013,25 @@ extern "C" rwt_status rwt_batch_create(const rwt_batch_desc* desc, void* d_ws, s
         return fail(st);
     DeviceInfo di;
     if ((st = device_info(&di)) != RWT_OK) return fail(st);
+    // LDS of the launch: what its task bodies use (solve blocks: x values
+    // and step starts; level blocks: levels and step starts), at least
+    // 16 KB for the histogram of the statistics -- not the whole budget,
+    // so that more workgroups fit on a compute unit
+    {
+        size_t need = 16384;
+        for (int32_t m = 0; m < desc->count; ++m) {
+            const size_t R = (size_t)hm[m].R;
+            if (b->mats[m].k > 0)
+                need = std::max(need, (size_t)sf_x_bytes((int)R, hm[m].kc, 8) + (R + 1) * 4 + 16);
+            if (!hm[m].sweep && cand_count[m] > 0)
+                need = std::max(need, ((R * 4 + 15) & ~size_t(15)) + (R + 1) * 4 + 16);
+        }
+        need = (need + 255) & ~size_t(255);
+        b->lds_bytes = (int32_t)std::min<size_t>(need, BT_LDS);
+    }
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_batch_main, BT_THREADS,
-                                                      BT_LDS) != hipSuccess ||
+                                                      b->lds_bytes) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     b->grid = di.cus * std::min(per_cu, 8);
