@@ -442,7 +442,11 @@ rwt_status rwt_gen_rowsets(int32_t n, int32_t num_env, int32_t cap, const rwt_ge
  * an original level at once: a rewritten row's new dependencies lie on
  * earlier original levels too).  With cand_mode 0 a matrix's candidates
  * take the sweep when its block chain has at least four times as many
- * level steps as the matrix has levels (wide levels), else the chain.
+ * level steps as the matrix has levels (wide levels), else the chain
+ * (always the chain for a matrix of 2^23 levels or more).  Sweeps of
+ * consecutive candidates of one matrix run up to eight to a workgroup,
+ * their levels interleaved row by row, so that one read of a dependency's
+ * levels serves all of them.
  * Per candidate c: the matrix h_cand_mat[c] and the rows
  * d_cand_rows[d_cand_ptr[c] .. d_cand_ptr[c+1]) (strictly ascending) with
  * targets d_cand_targets (NULL: level - 1).  Each launch recomputes, for

@@ -210,92 +210,140 @@ __device__ __forceinline__ void level_block(const BatchKArgs& a, const BatchMatD
     }
 }
 
-// All levels of candidate c by one workgroup: the original levels in order,
-// each one's rows all at once (one lane per row).  A row's dependencies --
-// its own, or a rewritten row's new list -- lie on earlier original levels,
-// published by this workgroup before the barrier that ended their level; a
-// load that still shows another launch's tag (a stale cache line) is
-// repeated with a device-scope load.
-__device__ __forceinline__ void sweep_cand(const BatchKArgs& a, const BatchMatDev& M,
-                                           const BatchCandDev& Cd, int32_t c, uint32_t tag) {
-    const int32_t qb = a.cand_ptr[c], qe = a.cand_ptr[c + 1];
-    const bool bad = a.cand_bad[c] != 0;
+// All levels of a group of gs <= SG candidates of one matrix by one
+// workgroup: the original levels in order, each one's rows all at once (one
+// lane per row).  A row's dependencies -- its own, or a rewritten row's new
+// list -- lie on earlier original levels, published by this workgroup before
+// the barrier that ended their level.  The group's levels are interleaved,
+// lev[i*gs + s] for candidate c0+s, so one dependency read serves every
+// candidate that keeps the row's original list.  A load that still shows
+// another launch's tag (a stale cache line) is repeated with a device-scope
+// load.
+constexpr int SG = 8;
+// Before the sweep, each rewritten row's slot holds its position in the
+// candidate's row list: this launch's tag, bit 23 set, the offset below it
+// (levels stay below 2^23 on this path, so bit 23 tells the two apart).
+constexpr uint32_t MARK = 0x800000u;
+
+// a level published in this launch (tag, bit 23 clear), waiting for it
+__device__ int32_t wait_level_sw(const int32_t* p, uint32_t tag, int32_t* err, int64_t ticks) {
+    int32_t v = ld_relaxed(p);
+    if (((uint32_t)v >> 24) == tag && !((uint32_t)v & MARK)) return v & 0x7fffff;
+    int64_t t0 = wall_clock64();
+    for (;;) {
+        __builtin_amdgcn_s_sleep(0);
+        v = ld_relaxed(p);
+        if (((uint32_t)v >> 24) == tag && !((uint32_t)v & MARK)) return v & 0x7fffff;
+        if (ld_relaxed(err) != 0) return 0;
+        if (wall_clock64() - t0 > ticks) {
+            __hip_atomic_store(err, (int32_t)RWT_ERR_DEADLOCK, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            return 0;
+        }
+    }
+}
+
+__device__ __forceinline__ int32_t level_of(int32_t* lev, int32_t idx, int32_t v, uint32_t tag,
+                                            int32_t* err, int64_t ticks) {
+    return (((uint32_t)v >> 24) == tag && !((uint32_t)v & MARK)) ? (v & 0x7fffff)
+                                                                 : wait_level_sw(&lev[idx], tag, err, ticks);
+}
+
+__device__ __forceinline__ void sweep_group(const BatchKArgs& a, const BatchMatDev& M, int32_t c0,
+                                            int32_t gs, int32_t* lev, uint32_t tag) {
     int32_t* err = &a.ctrl->err;
-    // each thread takes SR rows of a level at a time; every stage's loads
-    // (positions, row extents, bitmap words, dependencies, their levels) are
-    // issued for all SR rows before any is used
-    constexpr int SR = 4, U = 4;
-    const int32_t span = (int32_t)blockDim.x * SR;
+    const bool marks = M.D < (int32_t)MARK;
+    if (marks) {
+        for (int32_t s = 0; s < gs; ++s) {
+            const int32_t c = c0 + s;
+            if (a.cand_bad[c]) continue;
+            const BatchCandDev& Cd = a.cands[c];
+            const int32_t qb = a.cand_ptr[c], qe = a.cand_ptr[c + 1];
+            for (int32_t q = qb + threadIdx.x; q < qe; q += blockDim.x) {
+                const int32_t r = a.rows[q];
+                if (q - qb < (int32_t)MARK && ((Cd.bitmap[r >> 5] >> (r & 31)) & 1u))
+                    st_relaxed(&lev[r * gs + s], (int32_t)((tag << 24) | MARK | (uint32_t)(q - qb)));
+            }
+        }
+        __syncthreads();
+    }
     for (int32_t l = 0; l < M.D; ++l) {
         const int32_t beg = M.lptr[l], end = M.lptr[l + 1];
-        for (int32_t base = beg + threadIdx.x; base < end; base += span) {
-            int32_t row[SR], db[SR], de[SR], mx[SR];
-            const int32_t* dep[SR];
+        for (int32_t pos = beg + threadIdx.x; pos < end; pos += blockDim.x) {
+            const int32_t i = M.perm[pos];
+            const int32_t db = M.rowptr[i], de = M.rowptr[i + 1] - 1;   // without the diagonal
+            uint32_t rw = 0;   // candidates of the group that rewrite row i
 #pragma unroll
-            for (int r = 0; r < SR; ++r) {
-                const int32_t pos = base + r * (int32_t)blockDim.x;
-                row[r] = M.perm[pos < end ? pos : beg];
+            for (int s = 0; s < SG; ++s) {
+                if (s >= gs) break;
+                const BatchCandDev& Cd = a.cands[c0 + s];
+                if (!a.cand_bad[c0 + s] && ((Cd.bitmap[i >> 5] >> (i & 31)) & 1u)) rw |= 1u << s;
             }
+            int32_t mx[SG];
 #pragma unroll
-            for (int r = 0; r < SR; ++r) {
-                db[r] = M.rowptr[row[r]];
-                de[r] = M.rowptr[row[r] + 1] - 1;   // without the diagonal
-                dep[r] = M.colidx;
-                mx[r] = -1;
-            }
-            uint32_t bw[SR];
-#pragma unroll
-            for (int r = 0; r < SR; ++r) bw[r] = Cd.bitmap[row[r] >> 5];
-#pragma unroll
-            for (int r = 0; r < SR; ++r) {
-                if (!bad && ((bw[r] >> (row[r] & 31)) & 1u)) {
-                    const int32_t q = lower_bound_g(a.rows, qb, qe, row[r]);
-                    db[r] = a.pat_ptr[q];
-                    de[r] = a.pat_ptr[q + 1] - 1;
-                    dep[r] = a.pat;
-                }
-            }
-            // dependencies, U per row per round
-            bool more = true;
-            for (int32_t p0 = 0; more; p0 += U) {
-                int32_t jv[SR][U];
-#pragma unroll
-                for (int r = 0; r < SR; ++r)
+            for (int s = 0; s < SG; ++s) mx[s] = -1;
+            const uint32_t all = (1u << gs) - 1u;
+            if (rw != all) {
+                // U dependencies at a time: their columns, then all their
+                // slots' levels, are loaded together
+                constexpr int U = 4;
+                for (int32_t p0 = db; p0 < de; p0 += U) {
+                    int32_t jv[U];
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
-                        const int32_t p = db[r] + p0 + u;
-                        const bool in = p < de[r];
-                        const int32_t jj = dep[r][in ? p : db[r]];
-                        const bool ok = in && jj >= 0 && jj < row[r];
-                        if (in && !ok)
+                        const int32_t p = p0 + u;
+                        const int32_t jj = M.colidx[p < de ? p : p0];
+                        const bool ok = p < de && jj >= 0 && jj < i;
+                        if (p < de && !ok)
                             __hip_atomic_store(err, (int32_t)RWT_ERR_INVALID_ARG, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT);
-                        jv[r][u] = ok ? jj : -1;
+                        jv[u] = ok ? jj : -1;
                     }
-                int32_t lvv[SR][U];
+                    int32_t v[U][SG];
 #pragma unroll
-                for (int r = 0; r < SR; ++r)
+                    for (int u = 0; u < U; ++u)
 #pragma unroll
-                    for (int u = 0; u < U; ++u) lvv[r][u] = Cd.lev[jv[r][u] < 0 ? row[r] : jv[r][u]];
-                more = false;
-#pragma unroll
-                for (int r = 0; r < SR; ++r) {
+                        for (int s = 0; s < SG; ++s)
+                            v[u][s] = (s < gs && jv[u] >= 0) ? lev[jv[u] * gs + s] : 0;
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
-                        if (jv[r][u] < 0) continue;
-                        const int32_t v = lvv[r][u];
-                        const int32_t lj = ((uint32_t)v >> 24) == tag
-                                               ? (v & 0xffffff)
-                                               : wait_level(&Cd.lev[jv[r][u]], tag, err, a.ticks);
-                        mx[r] = lj > mx[r] ? lj : mx[r];
+                        if (jv[u] < 0) continue;
+#pragma unroll
+                        for (int s = 0; s < SG; ++s) {
+                            if (s >= gs || ((rw >> s) & 1u)) continue;
+                            const int32_t lj = level_of(lev, jv[u] * gs + s, v[u][s], tag, err, a.ticks);
+                            mx[s] = lj > mx[s] ? lj : mx[s];
+                        }
                     }
-                    more = more || db[r] + p0 + U < de[r];
                 }
             }
+            for (uint32_t m = rw; m != 0; m &= m - 1) {
+                const int s = __builtin_ctz(m);
+                const int32_t c = c0 + s;
+                const int32_t qb = a.cand_ptr[c];
+                const uint32_t mv = marks ? (uint32_t)ld_relaxed(&lev[i * gs + s]) : 0u;
+                const int32_t q = ((mv >> 24) == tag && (mv & MARK))
+                                      ? qb + (int32_t)(mv & (MARK - 1))
+                                      : lower_bound_g(a.rows, qb, a.cand_ptr[c + 1], i);
+                const int32_t nb = a.pat_ptr[q], ne = a.pat_ptr[q + 1] - 1;   // new diagonal last
+                int32_t best = -1;
+                for (int32_t p = nb; p < ne; ++p) {
+                    const int32_t j = a.pat[p];
+                    if (j < 0 || j >= i) {
+                        __hip_atomic_store(err, (int32_t)RWT_ERR_INVALID_ARG, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                        continue;
+                    }
+                    const int32_t lj = level_of(lev, j * gs + s, lev[j * gs + s], tag, err, a.ticks);
+                    best = lj > best ? lj : best;
+                }
 #pragma unroll
-            for (int r = 0; r < SR; ++r)
-                if (base + r * (int32_t)blockDim.x < end)
-                    st_relaxed(&Cd.lev[row[r]], (int32_t)((tag << 24) | (uint32_t)(mx[r] + 1)));
+                for (int t = 0; t < SG; ++t)
+                    if (t == s) mx[t] = best;
+            }
+#pragma unroll
+            for (int s = 0; s < SG; ++s)
+                if (s < gs) st_relaxed(&lev[i * gs + s], (int32_t)((tag << 24) | (uint32_t)(mx[s] + 1)));
         }
         __syncthreads();
         if (ld_relaxed(err) != 0) return;
@@ -344,9 +392,23 @@ __device__ __forceinline__ void finalize_cand(const BatchKArgs& a, const BatchMa
     int32_t* err = &a.ctrl->err;
     const int32_t n = M.n;
     int32_t mx = -1;
-    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
-        const int32_t L = wait_level(&Cd.lev[i], tag, err, a.ticks);
-        mx = L > mx ? L : mx;
+    // four rows per thread per round: their loads are issued together and
+    // only a value not yet visible here is waited for
+    for (int32_t i0 = threadIdx.x; i0 < n; i0 += 4 * blockDim.x) {
+        int32_t v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int32_t i = i0 + r * (int32_t)blockDim.x;
+            v[r] = ld_relaxed(&Cd.lev[i < n ? i : i0]);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int32_t i = i0 + r * (int32_t)blockDim.x;
+            if (i >= n) break;
+            const int32_t L = ((uint32_t)v[r] >> 24) == tag ? (v[r] & 0xffffff)
+                                                            : wait_level(&Cd.lev[i], tag, err, a.ticks);
+            mx = L > mx ? L : mx;
+        }
     }
     const int32_t D = block_max_bt(mx, reinterpret_cast<int32_t*>(s_raw)) + 1;
     const int32_t qb = a.cand_ptr[c], qe = a.cand_ptr[c + 1];
@@ -397,6 +459,110 @@ __device__ __forceinline__ void finalize_cand(const BatchKArgs& a, const BatchMa
     }
 }
 
+// statistics of the gs candidates of a sweep group (levels interleaved):
+// each candidate's level count, then its level-cost histogram in LDS level
+// range by level range, and the exact S1 / S2 / CV
+__device__ __forceinline__ void finalize_group(const BatchKArgs& a, const BatchMatDev& M,
+                                               int32_t c0, int32_t gs, int32_t* lev, uint32_t tag,
+                                               unsigned char* s_raw) {
+    int32_t* err = &a.ctrl->err;
+    const int32_t n = M.n;
+    int32_t D[SG];
+    int32_t dmax = 0;
+    {
+        int32_t mx[SG];
+#pragma unroll
+        for (int s = 0; s < SG; ++s) mx[s] = -1;
+        // every level is published (the sweep ended with a barrier): the
+        // loads of a row's slots are issued together and only a value not
+        // yet visible here is waited for
+        for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
+            int32_t v[SG];
+#pragma unroll
+            for (int s = 0; s < SG; ++s) v[s] = s < gs ? ld_relaxed(&lev[i * gs + s]) : 0;
+#pragma unroll
+            for (int s = 0; s < SG; ++s) {
+                if (s >= gs) break;
+                const int32_t L = level_of(lev, i * gs + s, v[s], tag, err, a.ticks);
+                mx[s] = L > mx[s] ? L : mx[s];
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < SG; ++s) {
+            D[s] = s < gs ? block_max_bt(mx[s], reinterpret_cast<int32_t*>(s_raw)) + 1 : 0;
+            dmax = D[s] > dmax ? D[s] : dmax;
+        }
+    }
+    uint32_t* hist = reinterpret_cast<uint32_t*>(s_raw + 256);
+    const int32_t W = a.hist_cap / gs;   // levels per range, per candidate
+    uint64_t s1[SG];
+    U128 s2[SG];
+#pragma unroll
+    for (int s = 0; s < SG; ++s) {
+        s1[s] = 0;
+        s2[s] = U128{0, 0};
+    }
+    for (int32_t lb = 0; lb < dmax; lb += W) {
+        const int32_t le = min(dmax, lb + W);
+        for (int32_t e = threadIdx.x; e < gs * W; e += blockDim.x) hist[e] = 0u;
+        __syncthreads();
+        for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
+            const uint32_t cost = (uint32_t)(2 * (M.rowptr[i + 1] - M.rowptr[i]) - 1);
+            int32_t v[SG];
+#pragma unroll
+            for (int s = 0; s < SG; ++s) v[s] = s < gs ? ld_relaxed(&lev[i * gs + s]) : 0;
+#pragma unroll
+            for (int s = 0; s < SG; ++s) {
+                if (s >= gs) break;
+                const int32_t L = v[s] & 0x7fffff;
+                if (L >= lb && L < le) atomicAdd(&hist[s * W + (L - lb)], cost);
+            }
+        }
+        // rewritten rows: cost of the new row instead of the old one (a
+        // rejected candidate's list is never read: its bounds may be invalid)
+        for (int32_t s = 0; s < gs; ++s) {
+            const int32_t c = c0 + s;
+            const BatchCandDev& Cd = a.cands[c];
+            const int32_t qb = a.cand_ptr[c], qe = a.cand_bad[c] ? qb : a.cand_ptr[c + 1];
+            for (int32_t q = qb + threadIdx.x; q < qe; q += blockDim.x) {
+                const int32_t r = a.rows[q];
+                if (!((Cd.bitmap[r >> 5] >> (r & 31)) & 1u)) continue;
+                const int32_t L = ld_relaxed(&lev[r * gs + s]) & 0x7fffff;
+                if (L >= lb && L < le)
+                    atomicAdd(&hist[s * W + (L - lb)],
+                              (uint32_t)(2 * (a.counts_q[q] - (M.rowptr[r + 1] - M.rowptr[r]))));
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < SG; ++s) {
+            if (s >= gs) break;
+            for (int32_t l = threadIdx.x; l < le - lb; l += blockDim.x) {
+                const uint64_t v = hist[s * W + l];
+                s1[s] += v;
+                s2[s] = u128_add(s2[s], U128{v * v, __umul64hi(v, v)});
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int s = 0; s < SG; ++s) {
+        if (s >= gs) break;
+        const U128 s1w = block_sum_u128_bt(U128{s1[s], 0}, s_raw);
+        const U128 s2w = block_sum_u128_bt(s2[s], s_raw);
+        if (threadIdx.x == 0) {
+            rwt_cand_stats o;
+            o.num_levels = D[s];
+            o.valid = a.cand_bad[c0 + s] ? 0 : 1;
+            o.S1 = s1w.lo;
+            o.S2_lo = s2w.lo;
+            o.S2_hi = s2w.hi;
+            o.cv = cv_exact((uint64_t)D[s], s1w.lo, s2w);
+            a.stats[c0 + s] = o;
+        }
+    }
+}
+
 __global__ void __launch_bounds__(BT_THREADS) k_batch_main(BatchKArgs a) {
     extern __shared__ __align__(16) unsigned char s_raw[];
     __shared__ int32_t s_task;
@@ -435,12 +601,14 @@ __global__ void __launch_bounds__(BT_THREADS) k_batch_main(BatchKArgs a) {
             if (M.kc == 1) sf_block<double, false, 1>(b, s_raw);
             else sf_block<double, false, 4>(b, s_raw);
         } else if (tk.x == 2) {
-            const int32_t c = tk.y;
-            const BatchCandDev& Cd = a.cands[c];
+            // a sweep group: candidates tk.y .. tk.y + tk.z - 1 of one matrix,
+            // levels interleaved in the first one's (and its neighbours')
+            // level arrays
+            const BatchCandDev& Cd = a.cands[tk.y];
             const BatchMatDev& M = a.mats[Cd.m];
-            sweep_cand(a, M, Cd, c, tag);
+            sweep_group(a, M, tk.y, tk.z, Cd.lev, tag);
             __syncthreads();
-            finalize_cand(a, M, Cd, c, tag, s_raw);
+            finalize_group(a, M, tk.y, tk.z, Cd.lev, tag, s_raw);
         } else {
             const int32_t c = tk.y;
             const BatchCandDev& Cd = a.cands[c];
@@ -960,8 +1128,36 @@ extern "C" rwt_status rwt_batch_create(const rwt_batch_desc* desc, void* d_ws, s
         }
         for (int32_t c = 0; c < desc->num_cand; ++c) cand_count[hc[c].m] += 1;
         for (int32_t m = 0; m < desc->count; ++m)
-            hm[m].sweep = desc->cand_mode == 2 ||
-                          (desc->cand_mode == 0 && (int64_t)steps[m] >= 4 * (int64_t)hm[m].D);
+            hm[m].sweep = hm[m].D < (1 << 23) &&
+                          (desc->cand_mode == 2 ||
+                           (desc->cand_mode == 0 && (int64_t)steps[m] >= 4 * (int64_t)hm[m].D));
+    }
+    {
+        DeviceInfo di;
+        rwt_status st0 = device_info(&di);
+        if (st0 != RWT_OK) return fail(st0);
+        // LDS of the launch: what its task bodies use (solve blocks: x values
+        // and step starts; level blocks: levels and step starts), at least
+        // 16 KB for the histogram of the statistics -- not the whole budget,
+        // so that more workgroups fit on a compute unit
+        {
+            size_t need = 16384;
+            for (int32_t m = 0; m < desc->count; ++m) {
+                const size_t R = (size_t)hm[m].R;
+                if (b->mats[m].k > 0)
+                    need = std::max(need, (size_t)sf_x_bytes((int)R, hm[m].kc, 8) + (R + 1) * 4 + 16);
+                if (!hm[m].sweep && cand_count[m] > 0)
+                    need = std::max(need, ((R * 4 + 15) & ~size_t(15)) + (R + 1) * 4 + 16);
+            }
+            need = (need + 255) & ~size_t(255);
+            b->lds_bytes = (int32_t)std::min<size_t>(need, BT_LDS);
+        }
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_batch_main, BT_THREADS,
+                                                          b->lds_bytes) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        b->grid = di.cus * std::min(per_cu, 8);
     }
     struct T {
         int32_t key;
@@ -979,14 +1175,27 @@ extern "C" rwt_status rwt_batch_create(const rwt_batch_desc* desc, void* d_ws, s
     for (int32_t m = 0; m < desc->count; ++m)
         for (int32_t c = 0; c * hm[m].kc < b->mats[m].k; ++c) add_chain(m, 0, m, c);
     b->solve_tasks = (int32_t)tv.size();
+    // sweep candidates go in groups: up to gmax consecutive candidates of one
+    // matrix (their level arrays are adjacent), one task each, ready at once.
+    // Larger groups read less (one read of a dependency serves the group)
+    // but leave fewer tasks; gmax keeps about two thirds of the grid busy.
+    int32_t nsweep = 0;
+    for (int32_t c = 0; c < desc->num_cand; ++c) nsweep += hm[hc[c].m].sweep ? 1 : 0;
+    const int32_t gmax = std::max<int32_t>(
+        1, std::min<int32_t>(SG, (nsweep + (2 * b->grid / 3) - 1) / std::max(1, 2 * b->grid / 3)));
     b->sweep_cands = 0;
-    for (int32_t c = 0; c < desc->num_cand; ++c) {
-        if (hm[hc[c].m].sweep) {
-            tv.push_back({0, make_int4(2, c, 0, 0)});   // one task, ready at once
-            ++b->sweep_cands;
-        } else {
-            add_chain(hc[c].m, 1, c, 0);
+    for (int32_t c = 0; c < desc->num_cand;) {
+        const int32_t m = hc[c].m;
+        if (!hm[m].sweep) {
+            add_chain(m, 1, c, 0);
+            ++c;
+            continue;
         }
+        int32_t gs = 1;
+        while (gs < gmax && c + gs < desc->num_cand && hc[c + gs].m == m) ++gs;
+        tv.push_back({0, make_int4(2, c, gs, 0)});
+        b->sweep_cands += gs;
+        c += gs;
     }
     std::stable_sort(tv.begin(), tv.end(), [](const T& x, const T& y) { return x.key < y.key; });
     std::vector<int4> tasks(tv.size());
@@ -1011,30 +1220,6 @@ extern "C" rwt_status rwt_batch_create(const rwt_batch_desc* desc, void* d_ws, s
             RWT_OK ||
         (st = fill_u8(b->epoch, sizeof(uint32_t), s)) != RWT_OK)
         return fail(st);
-    DeviceInfo di;
-    if ((st = device_info(&di)) != RWT_OK) return fail(st);
-    // LDS of the launch: what its task bodies use (solve blocks: x values
-    // and step starts; level blocks: levels and step starts), at least
-    // 16 KB for the histogram of the statistics -- not the whole budget,
-    // so that more workgroups fit on a compute unit
-    {
-        size_t need = 16384;
-        for (int32_t m = 0; m < desc->count; ++m) {
-            const size_t R = (size_t)hm[m].R;
-            if (b->mats[m].k > 0)
-                need = std::max(need, (size_t)sf_x_bytes((int)R, hm[m].kc, 8) + (R + 1) * 4 + 16);
-            if (!hm[m].sweep && cand_count[m] > 0)
-                need = std::max(need, ((R * 4 + 15) & ~size_t(15)) + (R + 1) * 4 + 16);
-        }
-        need = (need + 255) & ~size_t(255);
-        b->lds_bytes = (int32_t)std::min<size_t>(need, BT_LDS);
-    }
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_batch_main, BT_THREADS,
-                                                      b->lds_bytes) != hipSuccess ||
-        per_cu < 1)
-        per_cu = 1;
-    b->grid = di.cus * std::min(per_cu, 8);
     if (hipStreamSynchronize(s) != hipSuccess) {
         set_hip_error(hipGetLastError(), "batch creation");
         return fail(RWT_ERR_HIP);
