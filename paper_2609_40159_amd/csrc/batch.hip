@@ -129,87 +129,6 @@ __device__ int32_t lower_bound_g(const int32_t* a, int32_t lo, int32_t hi, int32
     return lo;
 }
 
-__device__ __forceinline__ void level_block(const BatchKArgs& a, const BatchMatDev& M, const BatchCandDev& Cd,
-                            int32_t c, int32_t blk, uint32_t tag, unsigned char* s_raw) {
-    const int32_t R = M.R;
-    const int32_t r0 = blk * R, r1 = min(M.n, r0 + R);
-    const int32_t sb = M.blk_step[blk], ns = M.blk_step[blk + 1] - sb;
-    int32_t* lv = reinterpret_cast<int32_t*>(s_raw);
-    int32_t* sp = reinterpret_cast<int32_t*>(s_raw + ((R * 4 + 15) & ~15));
-    for (int32_t u = threadIdx.x; u <= ns; u += blockDim.x) sp[u] = M.step_pos[sb + u] - r0;
-    __syncthreads();
-    const int32_t qb = a.cand_ptr[c], qe = a.cand_ptr[c + 1];
-    const int G = M.lanes;
-    const int gl = threadIdx.x & (G - 1);
-    const int lane = lane_id();
-    const int gpw = WAVE / G;
-    const int wib = threadIdx.x / WAVE;
-    const int32_t stride = (blockDim.x / WAVE) * gpw;
-    int32_t* err = &a.ctrl->err;
-    for (int32_t u = 0; u < ns; ++u) {
-        const int32_t beg = sp[u], end = sp[u + 1];
-        for (int32_t base = beg + wib * gpw; base < end; base += stride) {
-            const int32_t pos = base + lane / G;
-            const bool act = pos < end;
-            int32_t i = r0, db = 0, de = 0;
-            const int32_t* dep = M.colidx;
-            if (act) {
-                const int4 d = M.desc[r0 + pos];
-                i = d.x;
-                db = d.y;
-                de = d.z;   // forward pattern without the diagonal
-                if (!a.cand_bad[c] && ((Cd.bitmap[i >> 5] >> (i & 31)) & 1u)) {
-                    const int32_t q = lower_bound_g(a.rows, qb, qe, i);
-                    db = a.pat_ptr[q];
-                    de = a.pat_ptr[q + 1] - 1;   // the new row's diagonal is last
-                    dep = a.pat;
-                }
-            }
-            // levels of U dependencies are loaded together, then checked
-            constexpr int U = 8;
-            int32_t mx = -1;
-            for (int32_t p0 = db + gl; p0 < de; p0 += U * G) {
-                int32_t jv[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int32_t p = p0 + u * G;
-                    const int32_t jj = dep[p < de ? p : p0];   // p0 < de: a valid entry
-                    // out of range cannot happen for a consistent batch; never index with it
-                    const bool ok = p < de && jj >= 0 && jj < i;
-                    if (p < de && !ok)
-                        __hip_atomic_store(err, (int32_t)RWT_ERR_INVALID_ARG, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                    jv[u] = ok ? jj : -1;
-                }
-                int32_t lvv[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int32_t j = jv[u];
-                    lvv[u] = j < 0 ? 0 : (j >= r0 ? lv[j - r0] : ld_relaxed(&Cd.lev[j]));
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int32_t j = jv[u];
-                    if (j < 0) continue;
-                    int32_t lj = lvv[u];
-                    if (j < r0) {
-                        lj = (((uint32_t)lj >> 24) == tag) ? (lj & 0xffffff)
-                                                           : wait_level(&Cd.lev[j], tag, err, a.ticks);
-                    }
-                    mx = lj > mx ? lj : mx;
-                }
-            }
-            mx = group_max_i(mx, G);
-            if (act && gl == 0) {
-                const int32_t L = mx + 1;
-                lv[i - r0] = L;
-                st_relaxed(&Cd.lev[i], (int32_t)((tag << 24) | (uint32_t)L));
-            }
-        }
-        lds_sync();
-    }
-}
-
 // All levels of a group of gs <= SG candidates of one matrix by one
 // workgroup: the original levels in order, each one's rows all at once (one
 // lane per row).  A row's dependencies -- its own, or a rewritten row's new
@@ -350,6 +269,152 @@ __device__ __forceinline__ void sweep_group(const BatchKArgs& a, const BatchMatD
     }
 }
 
+// One row block of the level chains of a group of gs <= SG candidates of one
+// matrix: the block's rows in the original (level, row) order, step by
+// step, G lanes per row.  Levels of the block's rows live in LDS (lv[(i -
+// r0) * gs + s]); rows before the block are read from the group's
+// interleaved level arrays, published by earlier blocks (tag-checked, waited
+// for).  Before the steps, each rewritten row's LDS slot holds its position
+// in its candidate's row list (top bit set), so its new dependency list is
+// found without a search.
+constexpr uint32_t LDS_MARK = 0x80000000u;
+
+__device__ __forceinline__ int32_t level_blk(const int32_t* lev, int32_t idx, uint32_t tag,
+                                             int32_t* err, int64_t ticks) {
+    const int32_t v = ld_relaxed(&lev[idx]);
+    return ((uint32_t)v >> 24) == tag ? (v & 0xffffff) : wait_level(&lev[idx], tag, err, ticks);
+}
+
+__device__ __forceinline__ void level_block_group(const BatchKArgs& a, const BatchMatDev& M,
+                                                  int32_t c0, int32_t gs, int32_t* lev, int32_t blk,
+                                                  uint32_t tag, unsigned char* s_raw) {
+    const int32_t R = M.R;
+    const int32_t r0 = blk * R, r1 = min(M.n, r0 + R);
+    const int32_t sb = M.blk_step[blk], ns = M.blk_step[blk + 1] - sb;
+    int32_t* lv = reinterpret_cast<int32_t*>(s_raw);
+    int32_t* sp = reinterpret_cast<int32_t*>(s_raw + ((R * gs * 4 + 15) & ~15));
+    int32_t* qr = sp + ((ns + 1 + 3) & ~3);   // [2 * SG]: the block's range of each list
+    int32_t* err = &a.ctrl->err;
+    for (int32_t u = threadIdx.x; u <= ns; u += blockDim.x) sp[u] = M.step_pos[sb + u] - r0;
+    if (threadIdx.x < (unsigned)gs) {
+        const int32_t c = c0 + (int32_t)threadIdx.x;
+        int32_t lo = 0, hi = 0;
+        if (!a.cand_bad[c]) {
+            const int32_t qb = a.cand_ptr[c], qe = a.cand_ptr[c + 1];
+            lo = lower_bound_g(a.rows, qb, qe, r0);
+            hi = lower_bound_g(a.rows, lo, qe, r1);
+        }
+        qr[2 * threadIdx.x] = lo;
+        qr[2 * threadIdx.x + 1] = hi;
+    }
+    __syncthreads();
+    for (int32_t s = 0; s < gs; ++s) {
+        const BatchCandDev& Cd = a.cands[c0 + s];
+        const int32_t qb = a.cand_ptr[c0 + s];
+        for (int32_t q = qr[2 * s] + threadIdx.x; q < qr[2 * s + 1]; q += blockDim.x) {
+            const int32_t r = a.rows[q];
+            if ((Cd.bitmap[r >> 5] >> (r & 31)) & 1u)
+                lv[(r - r0) * gs + s] = (int32_t)(LDS_MARK | (uint32_t)(q - qb));
+        }
+    }
+    __syncthreads();
+    const int G = M.lanes;
+    const int gl = threadIdx.x & (G - 1);
+    const int lane = lane_id();
+    const int gpw = WAVE / G;
+    const int wib = threadIdx.x / WAVE;
+    const int32_t stride = (blockDim.x / WAVE) * gpw;
+    const uint32_t all = (1u << gs) - 1u;
+    for (int32_t u = 0; u < ns; ++u) {
+        const int32_t beg = sp[u], end = sp[u + 1];
+        for (int32_t base = beg + wib * gpw; base < end; base += stride) {
+            const int32_t pos = base + lane / G;
+            const bool act = pos < end;
+            int32_t i = r0, db = 0, de = 0;
+            uint32_t rw = 0;
+            if (act) {
+                const int4 d = M.desc[r0 + pos];
+                i = d.x;
+                db = d.y;
+                de = d.z;   // forward pattern without the diagonal
+#pragma unroll
+                for (int s = 0; s < SG; ++s) {
+                    if (s >= gs) break;
+                    const BatchCandDev& Cd = a.cands[c0 + s];
+                    if (!a.cand_bad[c0 + s] && ((Cd.bitmap[i >> 5] >> (i & 31)) & 1u))
+                        rw |= 1u << s;
+                }
+            }
+            int32_t mx[SG];
+#pragma unroll
+            for (int s = 0; s < SG; ++s) mx[s] = -1;
+            if (act && rw != all) {
+                constexpr int U = 4;
+                for (int32_t p0 = db + gl; p0 < de; p0 += U * G) {
+                    int32_t jv[U];
+#pragma unroll
+                    for (int u2 = 0; u2 < U; ++u2) {
+                        const int32_t p = p0 + u2 * G;
+                        const int32_t jj = M.colidx[p < de ? p : p0];
+                        const bool ok = p < de && jj >= 0 && jj < i;
+                        if (p < de && !ok)
+                            __hip_atomic_store(err, (int32_t)RWT_ERR_INVALID_ARG, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                        jv[u2] = ok ? jj : -1;
+                    }
+#pragma unroll
+                    for (int u2 = 0; u2 < U; ++u2) {
+                        const int32_t j = jv[u2];
+                        if (j < 0) continue;
+#pragma unroll
+                        for (int s = 0; s < SG; ++s) {
+                            if (s >= gs || ((rw >> s) & 1u)) continue;
+                            const int32_t lj = j >= r0 ? lv[(j - r0) * gs + s]
+                                                       : level_blk(lev, j * gs + s, tag, err, a.ticks);
+                            mx[s] = lj > mx[s] ? lj : mx[s];
+                        }
+                    }
+                }
+            }
+            for (uint32_t m = act ? rw : 0u; m != 0; m &= m - 1) {
+                const int s = __builtin_ctz(m);
+                const int32_t q = a.cand_ptr[c0 + s] + (int32_t)((uint32_t)lv[(i - r0) * gs + s] & ~LDS_MARK);
+                const int32_t nb = a.pat_ptr[q], ne = a.pat_ptr[q + 1] - 1;   // new diagonal last
+                int32_t best = -1;
+                for (int32_t p = nb + gl; p < ne; p += G) {
+                    const int32_t j = a.pat[p];
+                    if (j < 0 || j >= i) {
+                        __hip_atomic_store(err, (int32_t)RWT_ERR_INVALID_ARG, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                        continue;
+                    }
+                    const int32_t lj = j >= r0 ? lv[(j - r0) * gs + s]
+                                               : level_blk(lev, j * gs + s, tag, err, a.ticks);
+                    best = lj > best ? lj : best;
+                }
+#pragma unroll
+                for (int t = 0; t < SG; ++t)
+                    if (t == s) mx[t] = best;
+            }
+#pragma unroll
+            for (int s = 0; s < SG; ++s) {
+                if (s >= gs) break;
+                mx[s] = group_max_i(mx[s], G);
+            }
+            if (act && gl == 0) {
+#pragma unroll
+                for (int s = 0; s < SG; ++s) {
+                    if (s >= gs) break;
+                    const int32_t L = mx[s] + 1;
+                    lv[(i - r0) * gs + s] = L;
+                    st_relaxed(&lev[i * gs + s], (int32_t)((tag << 24) | (uint32_t)L));
+                }
+            }
+        }
+        lds_sync();
+    }
+}
+
 __device__ U128 block_sum_u128_bt(U128 v, unsigned char* scratch) {
     uint64_t* s = reinterpret_cast<uint64_t*>(scratch);
     for (int o = WAVE / 2; o > 0; o >>= 1) {
@@ -386,85 +451,14 @@ __device__ int32_t block_max_bt(int32_t v, int32_t* scratch) {
     return r;
 }
 
-// statistics of candidate c (its levels are all published)
-__device__ __forceinline__ void finalize_cand(const BatchKArgs& a, const BatchMatDev& M, const BatchCandDev& Cd,
-                              int32_t c, uint32_t tag, unsigned char* s_raw) {
-    int32_t* err = &a.ctrl->err;
-    const int32_t n = M.n;
-    int32_t mx = -1;
-    // four rows per thread per round: their loads are issued together and
-    // only a value not yet visible here is waited for
-    for (int32_t i0 = threadIdx.x; i0 < n; i0 += 4 * blockDim.x) {
-        int32_t v[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int32_t i = i0 + r * (int32_t)blockDim.x;
-            v[r] = ld_relaxed(&Cd.lev[i < n ? i : i0]);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int32_t i = i0 + r * (int32_t)blockDim.x;
-            if (i >= n) break;
-            const int32_t L = ((uint32_t)v[r] >> 24) == tag ? (v[r] & 0xffffff)
-                                                            : wait_level(&Cd.lev[i], tag, err, a.ticks);
-            mx = L > mx ? L : mx;
-        }
-    }
-    const int32_t D = block_max_bt(mx, reinterpret_cast<int32_t*>(s_raw)) + 1;
-    const int32_t qb = a.cand_ptr[c], qe = a.cand_ptr[c + 1];
-    uint32_t* hist = reinterpret_cast<uint32_t*>(s_raw + 256);
-    const int32_t HC = a.hist_cap;
-    uint64_t s1 = 0;
-    U128 s2{0, 0};
-    for (int32_t lb = 0; lb < D; lb += HC) {
-        const int32_t le = min(D, lb + HC);
-        for (int32_t l = threadIdx.x; l < le - lb; l += blockDim.x) hist[l] = 0u;
-        __syncthreads();
-        for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
-            const int32_t L = ld_relaxed(&Cd.lev[i]) & 0xffffff;
-            if (L >= lb && L < le)
-                atomicAdd(&hist[L - lb], (uint32_t)(2 * (M.rowptr[i + 1] - M.rowptr[i]) - 1));
-        }
-        // rewritten rows: cost of the new row instead of the old one (a
-        // rejected candidate's list is never read: its bounds may be invalid)
-        const int32_t qe_ok = a.cand_bad[c] ? qb : qe;
-        for (int32_t q = qb + threadIdx.x; q < qe_ok; q += blockDim.x) {
-            const int32_t r = a.rows[q];
-            if (!((Cd.bitmap[r >> 5] >> (r & 31)) & 1u)) continue;
-            const int32_t L = ld_relaxed(&Cd.lev[r]) & 0xffffff;
-            if (L >= lb && L < le)
-                atomicAdd(&hist[L - lb],
-                          (uint32_t)(2 * (a.counts_q[q] - (M.rowptr[r + 1] - M.rowptr[r]))));
-        }
-        __syncthreads();
-        for (int32_t l = threadIdx.x; l < le - lb; l += blockDim.x) {
-            const uint64_t v = hist[l];
-            s1 += v;
-            s2 = u128_add(s2, U128{v * v, __umul64hi(v, v)});
-        }
-        __syncthreads();
-    }
-    // sums across the workgroup (s1 fits 64 bits: it is 2 nnz' - n)
-    U128 s1w = block_sum_u128_bt(U128{s1, 0}, s_raw);
-    U128 s2w = block_sum_u128_bt(s2, s_raw);
-    if (threadIdx.x == 0) {
-        rwt_cand_stats o;
-        o.num_levels = D;
-        o.valid = a.cand_bad[c] ? 0 : 1;
-        o.S1 = s1w.lo;
-        o.S2_lo = s2w.lo;
-        o.S2_hi = s2w.hi;
-        o.cv = cv_exact((uint64_t)D, s1w.lo, s2w);
-        a.stats[c] = o;
-    }
-}
-
 // statistics of the gs candidates of a sweep group (levels interleaved):
 // each candidate's level count, then its level-cost histogram in LDS level
 // range by level range, and the exact S1 / S2 / CV
 __device__ __forceinline__ void finalize_group(const BatchKArgs& a, const BatchMatDev& M,
                                                int32_t c0, int32_t gs, int32_t* lev, uint32_t tag,
-                                               unsigned char* s_raw) {
+                                               bool marks, unsigned char* s_raw) {
+    // sweeps mark slots with bit 23 (levels below 2^23); chains use 24 bits
+    const int32_t lmask = marks ? 0x7fffff : 0xffffff;
     int32_t* err = &a.ctrl->err;
     const int32_t n = M.n;
     int32_t D[SG];
@@ -483,7 +477,10 @@ __device__ __forceinline__ void finalize_group(const BatchKArgs& a, const BatchM
 #pragma unroll
             for (int s = 0; s < SG; ++s) {
                 if (s >= gs) break;
-                const int32_t L = level_of(lev, i * gs + s, v[s], tag, err, a.ticks);
+                const int32_t L =
+                    marks ? level_of(lev, i * gs + s, v[s], tag, err, a.ticks)
+                          : (((uint32_t)v[s] >> 24) == tag ? (v[s] & 0xffffff)
+                                                           : wait_level(&lev[i * gs + s], tag, err, a.ticks));
                 mx[s] = L > mx[s] ? L : mx[s];
             }
         }
@@ -514,7 +511,7 @@ __device__ __forceinline__ void finalize_group(const BatchKArgs& a, const BatchM
 #pragma unroll
             for (int s = 0; s < SG; ++s) {
                 if (s >= gs) break;
-                const int32_t L = v[s] & 0x7fffff;
+                const int32_t L = v[s] & lmask;
                 if (L >= lb && L < le) atomicAdd(&hist[s * W + (L - lb)], cost);
             }
         }
@@ -527,7 +524,7 @@ __device__ __forceinline__ void finalize_group(const BatchKArgs& a, const BatchM
             for (int32_t q = qb + threadIdx.x; q < qe; q += blockDim.x) {
                 const int32_t r = a.rows[q];
                 if (!((Cd.bitmap[r >> 5] >> (r & 31)) & 1u)) continue;
-                const int32_t L = ld_relaxed(&lev[r * gs + s]) & 0x7fffff;
+                const int32_t L = ld_relaxed(&lev[r * gs + s]) & lmask;
                 if (L >= lb && L < le)
                     atomicAdd(&hist[s * W + (L - lb)],
                               (uint32_t)(2 * (a.counts_q[q] - (M.rowptr[r + 1] - M.rowptr[r]))));
@@ -608,17 +605,18 @@ __global__ void __launch_bounds__(BT_THREADS) k_batch_main(BatchKArgs a) {
             const BatchMatDev& M = a.mats[Cd.m];
             sweep_group(a, M, tk.y, tk.z, Cd.lev, tag);
             __syncthreads();
-            finalize_group(a, M, tk.y, tk.z, Cd.lev, tag, s_raw);
+            finalize_group(a, M, tk.y, tk.z, Cd.lev, tag, true, s_raw);
         } else {
-            const int32_t c = tk.y;
-            const BatchCandDev& Cd = a.cands[c];
+            // one row block of the level chains of candidates tk.y .. tk.y + tk.w - 1
+            const int32_t c0 = tk.y;
+            const BatchCandDev& Cd = a.cands[c0];
             const BatchMatDev& M = a.mats[Cd.m];
-            level_block(a, M, Cd, c, tk.z, tag, s_raw);
+            level_block_group(a, M, c0, tk.w, Cd.lev, tk.z, tag, s_raw);
             __syncthreads();
             if (threadIdx.x == 0)
-                s_last = (fetch_add(&a.cand_done[c], 1) == M.nblocks - 1) ? 1 : 0;
+                s_last = (fetch_add(&a.cand_done[c0], 1) == M.nblocks - 1) ? 1 : 0;
             __syncthreads();
-            if (s_last) finalize_cand(a, M, Cd, c, tag, s_raw);
+            if (s_last) finalize_group(a, M, c0, tk.w, Cd.lev, tag, false, s_raw);
         }
         __syncthreads();
         if (ld_relaxed(&a.ctrl->err) != 0) break;
@@ -969,6 +967,19 @@ rwt_status enqueue_run(rwt_batch* b, hipStream_t s) {
 
 }  // namespace
 
+// LDS of a row-block level task of gs candidates (levels, step starts, list
+// ranges) and the group size of a matrix's chains: as many candidates as fit
+// in half the LDS budget, so that the launch keeps four workgroups per CU
+size_t chain_lds(size_t R, int32_t gs) {
+    return ((R * (size_t)gs * 4 + 15) & ~size_t(15)) + (((R + 1 + 3) & ~size_t(3)) * 4) +
+           2 * SG * 4 + 16;
+}
+int32_t chain_group(int32_t R) {
+    int32_t gs = SG;
+    while (gs > 1 && chain_lds((size_t)R, gs) > (size_t)BT_LDS / 2) --gs;
+    return gs;
+}
+
 extern "C" rwt_status rwt_batch_ws(const rwt_batch_desc* desc, size_t* h_bytes) {
     RWT_REQUIRE(h_bytes != nullptr, RWT_ERR_INVALID_ARG, "h_bytes is NULL");
     BatchLayout L;
@@ -1147,7 +1158,7 @@ extern "C" rwt_status rwt_batch_create(const rwt_batch_desc* desc, void* d_ws, s
                 if (b->mats[m].k > 0)
                     need = std::max(need, (size_t)sf_x_bytes((int)R, hm[m].kc, 8) + (R + 1) * 4 + 16);
                 if (!hm[m].sweep && cand_count[m] > 0)
-                    need = std::max(need, ((R * 4 + 15) & ~size_t(15)) + (R + 1) * 4 + 16);
+                    need = std::max(need, chain_lds(R, chain_group(R)));
             }
             need = (need + 255) & ~size_t(255);
             b->lds_bytes = (int32_t)std::min<size_t>(need, BT_LDS);
@@ -1187,8 +1198,13 @@ extern "C" rwt_status rwt_batch_create(const rwt_batch_desc* desc, void* d_ws, s
     for (int32_t c = 0; c < desc->num_cand;) {
         const int32_t m = hc[c].m;
         if (!hm[m].sweep) {
-            add_chain(m, 1, c, 0);
-            ++c;
+            // level chains in groups too: up to chain_group(R) consecutive
+            // candidates of the matrix share each row-block task
+            const int32_t gb = chain_group(hm[m].R);
+            int32_t gs = 1;
+            while (gs < gb && c + gs < desc->num_cand && hc[c + gs].m == m) ++gs;
+            add_chain(m, 1, c, gs);
+            c += gs;
             continue;
         }
         int32_t gs = 1;
