@@ -342,3 +342,47 @@ def test_batch_candidate_modes_agree(orc):
                 torch.cuda.synchronize()
                 assert bt.stats() == got[mode]
     assert got["blocks"] == got["sweep"] == got["auto"]
+
+
+@pytest.mark.parametrize("mode", ["blocks", "sweep"])
+def test_batch_candidate_groups(orc, mode):
+    """Groups of candidates of one matrix (up to eight per task): many
+    candidates per matrix, runs broken by other matrices' candidates, and a
+    rejected list inside a group -- every statistic equal to the oracle's."""
+    mats = [("lap2d_48x40", synth.laplacian_2d(48, 40), 0),
+            ("powerlaw_6k", synth.power_law(6000, 61), 0),
+            ("lap3d_11x10x9", synth.laplacian_3d(11, 10, 9), 0)]
+    levels = levels_of(orc, mats)
+    rng = np.random.default_rng(62)
+    per = []
+    for m, (_, L, _) in enumerate(mats):
+        lst = []
+        for c in range(19):
+            rows, _ = synth.random_rowset(levels[m], 0.01 + 0.002 * c, int(rng.integers(1 << 30)))
+            t = np.array([int(rng.integers(max(0, lv - 3), lv + 1)) for lv in levels[m][rows]],
+                         np.int32)
+            lst.append((m, rows, t))
+        per.append(lst)
+    # 12 consecutive candidates of matrix 0, then the matrices interleaved
+    cands = per[0][:12]
+    for c in range(7):
+        cands += [per[1][c], per[2][c], per[0][12 + c]]
+    cands += per[1][7:] + per[2][7:]
+    bad_at = 5
+    m_bad = cands[bad_at][0]
+    cands[bad_at] = (m_bad, np.array([9, 3], np.int32), np.zeros(2, np.int32))   # unsorted
+    good = [x for i, x in enumerate(cands) if i != bad_at]
+    need = pattern_need(orc, mats, good, levels) + 64
+    bt, _, _ = make_batch(mats, cands, with_targets=True, pattern_cap=need, cand_mode=mode)
+    assert bt.info["sweep_cands"] == (len(cands) if mode == "sweep" else 0)
+    for rep in range(2):
+        bt.run()
+        st = bt.stats()
+        assert bt.last_status == "BAD_ROWSET"
+        for c, (m, r, t) in enumerate(cands):
+            if c == bad_at:
+                assert not st[c]["valid"]
+                a = orc.analyze(mats[m][1].n, mats[m][1].rowptr, mats[m][1].colidx)
+                assert st[c]["num_levels"] == a.num_levels and st[c]["S1"] == a.S1
+            else:
+                same_stats(st[c], oracle_cand(orc, mats[m][1], levels[m], r, t))
