@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="approximate CPU budget of the oracle baseline")
-    ap.add_argument("--copy-probe", action="store_true",
+    ap.add_argument("--copy-probe", action="store_true",   # kept for scripts; the copy always runs
                     help="also run a plain 1 GiB device copy (counter scaling for profiles)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the comparison solves (original DAG, forced schedules)")
@@ -602,20 +602,20 @@ def main():
     else:
         compare(cmp, time_solve, plan, plan_orig, rw, B, Bp, G, k, Plan)
 
-    copy_probe = None
-    if args.copy_probe:
-        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
-        b2 = torch.empty_like(a)
-        a.fill_(1.0)
-        torch.cuda.synchronize()
-        e0, e1 = ev(), ev()
-        e0.record()
-        for _ in range(5):
-            b2.copy_(a)
-        e1.record()
-        torch.cuda.synchronize()
-        copy_probe = {"bytes_each": 2 * a.numel() * 8, "ms_each": e0.elapsed_time(e1) / 5}
-        del a, b2
+    # stream-copy rate of the device, reported with every run (a reference
+    # for the roofline; the counter runs also scale FETCH/WRITE_SIZE by it)
+    a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    b2 = torch.empty_like(a)
+    a.fill_(1.0)
+    torch.cuda.synchronize()
+    e0, e1 = ev(), ev()
+    e0.record()
+    for _ in range(5):
+        b2.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_probe = {"bytes_each": 2 * a.numel() * 8, "ms_each": e0.elapsed_time(e1) / 5}
+    del a, b2
 
     log("main workload timed")
     # ---------------- CPU oracle baseline ----------------
@@ -661,6 +661,14 @@ def main():
             "latency_floor_note": f"{Dp} dependent levels on the critical path"}
     dom = "fwd" if ms["fwd"] >= ms["bwd"] else "bwd"
     roof = roofs[dom]
+    # floors of the solves: HBM time of their algorithmic bytes, and one
+    # measured cross-workgroup hand-off per dependent level
+    from paper_2609_40159_amd.api import probe_handoff
+    hop_ns = probe_handoff(2000)
+    for rf in roofs.values():
+        rf["bandwidth_floor_ms"] = rf["algorithmic_bytes_per_launch"] / (PEAK_HBM_GBS * 1e9) * 1e3
+        rf["handoff_ns"] = hop_ns
+        rf["latency_floor_ms"] = Dp * hop_ns * 1e-6
     generator = None if args.no_generator else run_generator(args, L, Lh, info, dev)
     pair = None if args.no_pair else run_pair(args, L, Lh, dev, k, plan, rwres)
     batched = run_batched(args, man, gen, dev) if man is not None else None
@@ -704,6 +712,7 @@ def main():
     }
     if copy_probe:
         out["copy_probe"] = copy_probe
+        out["stream_copy_gbs"] = copy_probe["bytes_each"] / (copy_probe["ms_each"] * 1e-3) / 1e9
     print(json.dumps(out))
 
 

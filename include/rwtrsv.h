@@ -518,6 +518,20 @@ rwt_status rwt_batch_get_info(const rwt_batch* batch, rwt_batch_info* h_info);
 rwt_status rwt_batch_plan(const rwt_batch* batch, int32_t m, const rwt_plan** out);
 rwt_status rwt_batch_destroy(rwt_batch* batch);
 
+/* ------------------------------------------------------------------------
+ * Measurement of the hand-off that bounds sync-free schedules from below:
+ * one workgroup publishes a value with a relaxed device-scope store, a
+ * second finds it with relaxed device-scope loads (the readiness mechanism
+ * of the solves).  Two workgroups exchange `rounds` values back and forth;
+ * *h_ns_one_way = elapsed / (2 rounds).  A latency floor of a solve with D
+ * dependent levels crossing workgroups is about D times this.  Every wait
+ * is bounded (100 ms in all: RWT_ERR_DEADLOCK).  Workspace:
+ * rwt_probe_handoff_ws(rounds) bytes.  Synchronizes.
+ * ---------------------------------------------------------------------- */
+size_t rwt_probe_handoff_ws(int32_t rounds);
+rwt_status rwt_probe_handoff(int32_t rounds, void* d_ws, size_t ws_bytes, double* h_ns_one_way,
+                             rwt_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

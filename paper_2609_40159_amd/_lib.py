@@ -156,6 +156,8 @@ SIGNATURES = {
     "rwt_solve_pair": (C.c_int, [P, P, P, I32, I64, P, I64, P]),
     "rwt_upper_check": (C.c_int, [P, P]),
     "rwt_upper_destroy": (C.c_int, [P]),
+    "rwt_probe_handoff_ws": (SZ, [I32]),
+    "rwt_probe_handoff": (C.c_int, [I32, P, SZ, C.POINTER(C.c_double), P]),
     "rwt_generate_ws": (C.c_int, [I32, I32, I32, C.POINTER(SZ)]),
     "rwt_generate": (C.c_int, [C.POINTER(Csr), P, P, P, P, I32, I32, C.POINTER(GenParams), I32,
                                P, P, P, P, P, P, P, P, SZ, P]),

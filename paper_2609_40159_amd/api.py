@@ -647,3 +647,12 @@ class Batch:
                 "block_rows": inf.block_rows, "lanes_per_row": inf.lanes_per_row,
                 "rhs_chunk": inf.rhs_chunk, "num_blocks": inf.num_blocks,
                 "tuned_ms": inf.tuned_ms_syncfree}
+
+
+def probe_handoff(rounds: int = 2000) -> float:
+    """One-way cross-workgroup hand-off latency on the current device, in ns."""
+    lib = _lib.load()
+    ws = _workspace(lib.rwt_probe_handoff_ws(rounds), "cuda")
+    out = C.c_double(0.0)
+    check(lib.rwt_probe_handoff(rounds, _ptr(ws), ws.numel(), C.byref(out), _stream()))
+    return float(out.value)
