@@ -280,11 +280,11 @@ def run_generator(args, L, Lh, info, dev):
     """Rewrite-list generation for a grid of parameter sets on the workload's
     matrix (one launch, one wave per environment), the lists turned into
     candidate row sets and scored in one batched launch (levels and CV of
-    each rewritten matrix); a sample checked against the oracle."""
+    each rewritten matrix).  Returns the figures and a sample of lists for
+    the CPU-baseline leg."""
     import numpy as np
     import torch
 
-    import oracle
     from paper_2609_40159_amd import _lib
     from paper_2609_40159_amd.api import Batch, gen_rowsets, generate
 
@@ -355,25 +355,16 @@ def run_generator(args, L, Lh, info, dev):
                    "levels_original": info.num_levels, "cv_original": info.stats["cv"],
                    "env_levels": g.results[best]["levels"], "env_cv": g.results[best]["cv"]}
     log("generated lists scored")
-    # oracle on a sample of environments (parity and single-core rate)
-    lv = info.level.cpu().numpy()
+    # a sample of environments for the CPU-baseline leg (oracle rate and
+    # equality of the lists), taken to the host here
     sample = list(range(0, ne, ne // 16))[:16]
-    t_or, steps_or, same = 0.0, 0, True
-    rows_h, src_h, tgt_h = g.rows.cpu().numpy(), g.src.cpu().numpy(), g.tgt.cpu().numpy()
-    for e in sample:
-        t1 = time.perf_counter()
-        o = oracle.generate(Lh.n, Lh.rowptr, lv, info.num_levels, info.stats["alc"],
-                            info.stats["cv"], cap=cap, **params[e])
-        t_or += time.perf_counter() - t1
-        steps_or += o.steps
-        m = o.moves
-        same = same and m == g.results[e]["moves"] and o.steps == g.results[e]["steps"] \
-            and np.array_equal(rows_h[e, :m], o.rows) and np.array_equal(src_h[e, :m], o.src) \
-            and np.array_equal(tgt_h[e, :m], o.tgt) and o.cv == g.results[e]["cv"]
-    res["oracle"] = {"envs_sampled": len(sample), "steps_per_s": steps_or / t_or, "cores": 1,
-                     "sample_equal": bool(same)}
+    cmp = {"params": [params[e] for e in sample], "cap": cap,
+           "results": [g.results[e] for e in sample],
+           "rows": g.rows[sample].cpu().numpy(), "src": g.src[sample].cpu().numpy(),
+           "tgt": g.tgt[sample].cpu().numpy(), "level": info.level.cpu().numpy(),
+           "D": info.num_levels, "alc": info.stats["alc"], "cv": info.stats["cv"]}
     del bt
-    return res
+    return res, cmp
 
 
 def run_pair(args, L, Lh, dev, k, plan_rw=None, rwres=None):
@@ -383,7 +374,6 @@ def run_pair(args, L, Lh, dev, k, plan_rw=None, rwres=None):
     import numpy as np
     import torch
 
-    import oracle
     import synth
     from paper_2609_40159_amd.api import CSRMatrix, Plan, UpperPlan, apply_M, solve_pair
 
@@ -416,28 +406,24 @@ def run_pair(args, L, Lh, dev, k, plan_rw=None, rwres=None):
 
     pair_ms = timed(lambda: solve_pair(Lp, Up, B, out=X))
     up_ms = timed(lambda: Up.solve(B, out=X))
-    rw_pair_ms = rw_err = None
+    rw_pair_ms = None
     if plan_rw is not None:
         # with the rewritten factor: X = U^-1 L'^-1 (M B) = U^-1 L^-1 B
         rw_pair_ms = timed(lambda: solve_pair(plan_rw, Up, apply_M(rwres, B), out=X))
     Up.check()
     s = 8 if L.dtype == torch.float64 else 4
     b_pair = bytes_solve(Lh.n, Lh.nnz, k, s) * 2
-    t1 = time.perf_counter()
-    ref = oracle.solve_pair(Lh.n, Lh.rowptr, Lh.colidx, Lh.vals, Uh.rowptr, Uh.colidx, Uh.vals, Bh)
-    t_or = time.perf_counter() - t1
     Xh = solve_pair(Lp, Up, B, out=X).double().cpu().numpy()
-    err = float(np.max(np.abs(Xh - ref)) / np.max(np.abs(ref)))
+    Xr = None
     if plan_rw is not None:
         Xr = solve_pair(plan_rw, Up, apply_M(rwres, B)).double().cpu().numpy()
-        rw_err = float(np.max(np.abs(Xr - ref)) / np.max(np.abs(ref)))
-    return {"what": "X = U^-1 L^-1 B with U = L^T (upper CSR), main workload's original factor",
-            "rhs": k, "upper_plan_ms": plan_ms, "upper_algo": Up.info["algo_fwd"],
-            "upper_block_rows": Up.info["block_rows"], "pair_ms": pair_ms, "upper_ms": up_ms,
-            "pair_gbs": b_pair / pair_ms / 1e6, "applications_per_s": 1e3 / pair_ms,
-            "relerr_vs_oracle": err, "oracle_pair_ms": t_or * 1e3, "oracle_cores": 1,
-            "rewritten_pair_ms": rw_pair_ms, "rewritten_relerr_vs_oracle": rw_err,
-            "speedup_rewritten_pair": None if rw_pair_ms is None else pair_ms / rw_pair_ms}
+    res = {"what": "X = U^-1 L^-1 B with U = L^T (upper CSR), main workload's original factor",
+           "rhs": k, "upper_plan_ms": plan_ms, "upper_algo": Up.info["algo_fwd"],
+           "upper_block_rows": Up.info["block_rows"], "pair_ms": pair_ms, "upper_ms": up_ms,
+           "pair_gbs": b_pair / pair_ms / 1e6, "applications_per_s": 1e3 / pair_ms,
+           "rewritten_pair_ms": rw_pair_ms,
+           "speedup_rewritten_pair": None if rw_pair_ms is None else pair_ms / rw_pair_ms}
+    return res, {"Uh": Uh, "Bh": Bh, "X": Xh, "X_rewritten": Xr}
 
 
 def main():
@@ -618,7 +604,16 @@ def main():
     del a, b2
 
     log("main workload timed")
+    generator = gen_cmp = None
+    if not args.no_generator:
+        generator, gen_cmp = run_generator(args, L, Lh, info, dev)
+    pair = pair_cmp = None
+    if not args.no_pair:
+        pair, pair_cmp = run_pair(args, L, Lh, dev, k, plan, rwres)
     # ---------------- CPU oracle baseline ----------------
+    # The oracle runs here only: the main step on a bounded sample, and
+    # beside it the generator sample and the pair (their lists and results
+    # compared with the GPU's)
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -641,6 +636,34 @@ def main():
                "kind": "oracle", "ms_per_step": t_cpu / reps * 1e3,
                "sample": f"{reps} full steps (rewrite, forward solve, adjoint) of the same "
                          f"workload, single-threaded FP64 oracle"}
+        if gen_cmp is not None:
+            t_or, steps_or, same = 0.0, 0, True
+            for q, prm in enumerate(gen_cmp["params"]):
+                t1 = time.perf_counter()
+                o = oracle.generate(n, Lh.rowptr, gen_cmp["level"], gen_cmp["D"], gen_cmp["alc"],
+                                    gen_cmp["cv"], cap=gen_cmp["cap"], **prm)
+                t_or += time.perf_counter() - t1
+                steps_or += o.steps
+                r = gen_cmp["results"][q]
+                m = o.moves
+                same = same and m == r["moves"] and o.steps == r["steps"] and o.cv == r["cv"] \
+                    and np.array_equal(gen_cmp["rows"][q, :m], o.rows) \
+                    and np.array_equal(gen_cmp["src"][q, :m], o.src) \
+                    and np.array_equal(gen_cmp["tgt"][q, :m], o.tgt)
+            cpu["generator"] = {"value": steps_or / t_or, "unit": "steps/s", "cores": 1,
+                                "sample": f"{len(gen_cmp['params'])} environments of the grid",
+                                "lists_equal_gpu": bool(same)}
+        if pair_cmp is not None:
+            Uh = pair_cmp["Uh"]
+            t1 = time.perf_counter()
+            ref = oracle.solve_pair(n, Lh.rowptr, Lh.colidx, Lh.vals, Uh.rowptr, Uh.colidx,
+                                    Uh.vals, pair_cmp["Bh"])
+            t_or = time.perf_counter() - t1
+            rel = lambda x: float(np.max(np.abs(x - ref)) / np.max(np.abs(ref)))
+            cpu["pair"] = {"value": 1.0 / t_or, "unit": "applications/s", "cores": 1,
+                           "sample": "one application", "relerr_gpu": rel(pair_cmp["X"]),
+                           "relerr_gpu_rewritten": (None if pair_cmp["X_rewritten"] is None
+                                                    else rel(pair_cmp["X_rewritten"]))}
 
     # ---------------- roofline of the dominant kernel ----------------
     # the forward and the transposed solve take most of a step; the longer
@@ -669,8 +692,6 @@ def main():
         rf["bandwidth_floor_ms"] = rf["algorithmic_bytes_per_launch"] / (PEAK_HBM_GBS * 1e9) * 1e3
         rf["handoff_ns"] = hop_ns
         rf["latency_floor_ms"] = Dp * hop_ns * 1e-6
-    generator = None if args.no_generator else run_generator(args, L, Lh, info, dev)
-    pair = None if args.no_pair else run_pair(args, L, Lh, dev, k, plan, rwres)
     batched = run_batched(args, man, gen, dev) if man is not None else None
     if batched is not None:
         batched["host_generation_s"] = gen_s
