@@ -60,6 +60,28 @@ class _GenResult(C.Structure):
 GEN_NO_SOURCE, GEN_THIN, GEN_MOVES, GEN_STEPS = 0, 1, 2, 3
 
 
+class _EnvParams(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("thin_stop", C.c_double), ("reward_alpha", C.c_double),
+                ("eps", C.c_double), ("decay", C.c_double), ("max_dist", C.c_int32),
+                ("search_window", C.c_int32), ("dist_threshold", C.c_int32),
+                ("max_steps", C.c_int32), ("stall_steps", C.c_int32), ("keep_top", C.c_int32)]
+
+
+class _EnvResult(C.Structure):
+    _fields_ = [("outcome", C.c_int32), ("node", C.c_int32), ("src", C.c_int32),
+                ("tgt", C.c_int32), ("collapsed", C.c_int32), ("done", C.c_int32),
+                ("steps", C.c_int32), ("moves", C.c_int32), ("levels", C.c_int32),
+                ("thin", C.c_int32), ("thin0", C.c_int32), ("pad_", C.c_int32),
+                ("reward", C.c_double), ("r_cv", C.c_double), ("r_cp", C.c_double),
+                ("r_rwdist", C.c_double), ("r_abandon", C.c_double), ("cv", C.c_double),
+                ("cv_rows", C.c_double)]
+
+
+ENV_MOVED, ENV_INVALID, ENV_REJECTED, ENV_IGNORED = 0, 1, 2, 3
+ENV_DEFAULTS = dict(alpha=1.0, thin_stop=0.02, reward_alpha=1.0, eps=1e-6, decay=0.9, max_dist=8,
+                    search_window=5, dist_threshold=2, max_steps=0, stall_steps=0, keep_top=8)
+
+
 _lib = None
 
 
@@ -89,6 +111,19 @@ def _L():
                                       C.POINTER(_GenParams), C.c_int32, P, P, P,
                                       C.POINTER(_GenResult), P, P, P]
         _lib.orc_generate.restype = C.c_int
+        _lib.orc_env_create.argtypes = [C.c_int32, P, P, C.c_int32, C.c_double, C.c_double,
+                                        C.POINTER(_EnvParams), C.c_int32]
+        _lib.orc_env_create.restype = C.c_void_p
+        _lib.orc_env_destroy.argtypes = [P]
+        _lib.orc_env_destroy.restype = None
+        _lib.orc_env_reset.argtypes = [P]
+        _lib.orc_env_reset.restype = None
+        _lib.orc_env_step.argtypes = [P, C.c_int32, C.POINTER(_EnvResult)]
+        _lib.orc_env_step.restype = None
+        _lib.orc_env_observe.argtypes = [P, P, P, P]
+        _lib.orc_env_observe.restype = None
+        _lib.orc_env_state.argtypes = [P, P, P, P, P, P, P, P]
+        _lib.orc_env_state.restype = None
     return _lib
 
 
@@ -286,3 +321,62 @@ def generate(n, rowptr, level, num_levels, alc, cv, *, alpha=1.0, thin_stop=0.02
                      int(res.rejected), float(res.threshold), int(res.S1),
                      int(res.S2_lo) | (int(res.S2_hi) << 64), float(res.cv), oc[:D].copy(),
                      orr[:D].copy(), od[:D].copy())
+
+
+class Env:
+    """One environment of Sections 4.1-4.5 driven from outside, with the
+    reward of Algorithm 2 (see orc_env_step for every reading taken).
+    ``level`` is the analysis' level of every row; ``alc`` and ``cv`` its
+    average level cost and CV of level costs."""
+
+    def __init__(self, n, rowptr, level, num_levels, alc, cv, cap=None, **params):
+        unknown = set(params) - set(ENV_DEFAULTS)
+        if unknown:
+            raise TypeError("unknown environment parameters: %s" % sorted(unknown))
+        prm = dict(ENV_DEFAULTS, **params)
+        self.params = prm
+        self.n, self.D = int(n), int(num_levels)
+        self.cap = self.n if cap is None else int(cap)
+        self._rowptr, self._level = _i32(rowptr), _i32(level)
+        cp = _EnvParams(float(prm["alpha"]), float(prm["thin_stop"]), float(prm["reward_alpha"]),
+                        float(prm["eps"]), float(prm["decay"]), int(prm["max_dist"]),
+                        int(prm["search_window"]), int(prm["dist_threshold"]),
+                        int(prm["max_steps"]), int(prm["stall_steps"]), int(prm["keep_top"]))
+        self._h = _L().orc_env_create(self.n, _p(self._rowptr), _p(self._level), self.D,
+                                      float(alc), float(cv), C.byref(cp), self.cap)
+        if not self._h:
+            raise ValueError("oracle environment: invalid arguments")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _L().orc_env_destroy(h)
+            self._h = None
+
+    def reset(self):
+        _L().orc_env_reset(self._h)
+
+    def step(self, action) -> dict:
+        r = _EnvResult()
+        _L().orc_env_step(self._h, int(action), C.byref(r))
+        return {f: getattr(r, f) for f, _ in _EnvResult._fields_ if f != "pad_"}
+
+    def observe(self):
+        """(level features [6, D], global features [9], mask [D] bool)."""
+        lv = np.zeros((6, max(self.D, 1)), dtype=np.float64)
+        gl = np.zeros(9, dtype=np.float64)
+        mk = np.zeros(max(self.D, 1), dtype=np.uint8)
+        _L().orc_env_observe(self._h, _p(lv), _p(gl), _p(mk))
+        return lv[:, :self.D], gl, mk[:self.D].astype(bool)
+
+    def state(self):
+        """(level of every row, per-level cost, rows, dependency sums, and
+        the move list (rows, sources, targets))."""
+        lev = np.zeros(self.n, dtype=np.int32)
+        cost = np.zeros(self.D, dtype=np.int64)
+        rows = np.zeros(self.D, dtype=np.int32)
+        deps = np.zeros(self.D, dtype=np.int64)
+        c = max(self.cap, 1)
+        mr, ms, mt = (np.zeros(c, dtype=np.int32) for _ in range(3))
+        _L().orc_env_state(self._h, _p(lev), _p(cost), _p(rows), _p(deps), _p(mr), _p(ms), _p(mt))
+        return lev, cost, rows, deps, (mr, ms, mt)

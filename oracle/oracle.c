@@ -19,7 +19,10 @@
  * Parity pins (what checks this file against something other than itself)
  * live in the test suite: brute-force longest paths on every small pattern,
  * lattice closed forms for grid Laplacians, dense linear algebra for the
- * rewrite, SciPy for the solve, finite differences for the adjoint.  The
+ * rewrite, SciPy for the solve, finite differences for the adjoint,
+ * hand-worked cases for the generator and the environment step (whose
+ * reward constants and abandonment penalty are readings, stated there), a
+ * plain-Python second implementation of the environment.  The
  * choice of the population standard deviation in the CV (see below) is a
  * definition the paper does not fix: parity unpinned on that one point.
  */
@@ -638,4 +641,480 @@ int orc_generate(int32_t n, const int32_t *rowptr, const int32_t *level, int32_t
     free(is_target);
     free(rejected);
     return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * Environment step with the reward of Algorithm 2 (Sections 4.1-4.5).
+ *
+ * One environment over the level table of L, driven from outside: each step
+ * takes an action (a source level) and returns the reward.  State
+ * (Section 4.1, the DAG is never modified): the level of every row, and
+ * per level its cost, row count and dependency sum (a moved row keeps its
+ * original cost 2*nnz_i - 1 and dependency count nnz_i - 1); per level also
+ * whether it ever received a row, its initial size and first-touch step
+ * (abandonment, Section 4.5), and the steps at which it was last chosen as
+ * source and last received a row (the affinities of Section 4.2).
+ *
+ * Readings (the paper leaves these open; stated here and pinned by
+ * hand-worked cases):
+ *  - thr = ALC * (1 + alpha * max(0, 1 - CV)) of the input, fixed; thin =
+ *    non-empty and cost < thr; levels, CV = over the non-empty levels.
+ *  - action a is valid when 1 <= a < D and level a is non-empty; the mask
+ *    heuristics of Section 4.4 shape the mask given to the policy
+ *    (env_observe) and do not change validity.  An invalid action, or one
+ *    Algorithm 1 rejects, changes nothing but the step count and earns
+ *    -reward_alpha.
+ *  - node: the row of level a with the fewest dependencies, ties to the
+ *    lower row index (Section 4.4); rows that moved in may move again.
+ *  - Algorithm 1: p = nearest non-empty level above a.  p == 0: target 0
+ *    when level 0 is thin, else reject.  p > 0: among the search_window
+ *    nearest thin levels at or above p, the one with the highest target
+ *    affinity (the one that most recently received a row; never = lowest;
+ *    ties to the nearest); with no thin level at or above p the fallback is
+ *    p when the source is thin, else reject.  Reject when a - t > max_dist.
+ *  - affinity of a level (observation): decay^(steps - stamp) with the step
+ *    stamp of the last choice as source / last received row, 0 if never,
+ *    -1 when the level is empty or, for the source affinity, ever received
+ *    a row, or, for the target affinity, is not thin.  Comparisons of
+ *    affinities are comparisons of stamps, exact.
+ *  - reward of a move (Algorithm 2), dCV = CV before - CV after:
+ *      r_cv = -reward_alpha if dCV < -eps; D0 * dCV if dCV > eps; else 0
+ *      s = log(1 + size + 1), size = source rows before the move
+ *      r_cp = reward_alpha * (D0 / levels after) * (1 + 1/s) if the source
+ *             emptied; reward_alpha / s if the source was thin; else
+ *             -reward_alpha * (1 + s)
+ *      r_rwdist = log1p(thd - d) / D0 if d < thd, else -log1p(d - thd) / D0,
+ *             d = a - t, thd = dist_threshold
+ *      r_abandon (A = the previous move's source, when A != a): if A ever
+ *             received a row, its initial size becomes its current size and
+ *             its first touch 0, no penalty; no penalty when A is empty, or
+ *             when a level >= 1 with exactly one row exists and A is thin;
+ *             else -(1 - c) * log1p(step - first touch of A), with the
+ *             completion ratio c = 1 - rows/(initial size + 1)
+ *      reward = 0.80 r_cv + 0.80 r_cp + 0.05 r_rwdist + 0.50 r_abandon.
+ *  - the episode ends (checked after reset and after each step, in this
+ *    order): THIN when T0 > 0 and thin / T0 < thin_stop; MOVES when cap
+ *    moves were made; STEPS when max_steps steps were taken (0 = max(2 D,
+ *    6144)); NO_SOURCE when no level >= 1 is non-empty.  Later actions are
+ *    ignored (reward 0) until reset.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    double alpha;
+    double thin_stop;
+    double reward_alpha;
+    double eps;
+    double decay;
+    int32_t max_dist;
+    int32_t search_window;
+    int32_t dist_threshold;
+    int32_t max_steps;
+    int32_t stall_steps;
+    int32_t keep_top;
+} orc_env_params;
+
+enum { ORC_ENV_MOVED = 0, ORC_ENV_INVALID = 1, ORC_ENV_REJECTED = 2, ORC_ENV_IGNORED = 3 };
+
+typedef struct {
+    int32_t outcome, node, src, tgt, collapsed, done;
+    int32_t steps, moves, levels, thin, thin0, pad_;
+    double reward, r_cv, r_cp, r_rwdist, r_abandon, cv, cv_rows;
+} orc_env_result;
+
+typedef struct {
+    int32_t n, D, cap;
+    orc_env_params prm;
+    double thr, alc, arl;
+    int32_t *deps_row;   /* nnz_i - 1 */
+    const int32_t *level0;
+    int32_t *lev;
+    int64_t *cost, *deps;
+    int32_t *rows, *init_size, *first, *sstamp, *tstamp;
+    unsigned char *is_target;
+    int32_t steps, moves, last_src, last_collapse, T0, D0, done, max_steps;
+    int32_t *mv_row, *mv_src, *mv_tgt;
+} orc_env;
+
+static int env_thin(const orc_env *v, int32_t l)
+{
+    return v->rows[l] > 0 && (double)v->cost[l] < v->thr;
+}
+
+static int32_t env_count_thin(const orc_env *v)
+{
+    int32_t t = 0;
+    for (int32_t l = 0; l < v->D; ++l) t += env_thin(v, l);
+    return t;
+}
+
+static int32_t env_levels(const orc_env *v)
+{
+    int32_t t = 0;
+    for (int32_t l = 0; l < v->D; ++l) t += v->rows[l] > 0;
+    return t;
+}
+
+/* CV of the non-empty levels' costs and of their row counts */
+static void env_cvs(const orc_env *v, double *cv_cost, double *cv_rows)
+{
+    int64_t *a = (int64_t *)malloc(sizeof(int64_t) * (size_t)v->D);
+    int64_t *b = (int64_t *)malloc(sizeof(int64_t) * (size_t)v->D);
+    int32_t m = 0;
+    for (int32_t l = 0; l < v->D; ++l)
+        if (v->rows[l] > 0) {
+            a[m] = v->cost[l];
+            b[m] = v->rows[l];
+            ++m;
+        }
+    *cv_cost = cv_of(a, m, NULL, NULL);
+    *cv_rows = cv_of(b, m, NULL, NULL);
+    free(a);
+    free(b);
+}
+
+static int32_t env_stop(const orc_env *v)
+{
+    int32_t thin = env_count_thin(v);
+    if (v->T0 > 0 && (double)thin / (double)v->T0 < v->prm.thin_stop) return ORC_GEN_THIN;
+    if (v->moves >= v->cap) return ORC_GEN_MOVES;
+    if (v->steps >= v->max_steps) return ORC_GEN_STEPS;
+    int32_t any = 0;
+    for (int32_t l = 1; l < v->D; ++l) any |= v->rows[l] > 0;
+    if (!any) return ORC_GEN_NO_SOURCE;
+    return -1;
+}
+
+void orc_env_reset(orc_env *v)
+{
+    memset(v->cost, 0, sizeof(int64_t) * (size_t)v->D);
+    memset(v->deps, 0, sizeof(int64_t) * (size_t)v->D);
+    memset(v->rows, 0, sizeof(int32_t) * (size_t)v->D);
+    for (int32_t i = 0; i < v->n; ++i) {
+        int32_t l = v->level0[i];
+        v->lev[i] = l;
+        v->cost[l] += 2 * (int64_t)v->deps_row[i] + 1;
+        v->deps[l] += v->deps_row[i];
+        v->rows[l] += 1;
+    }
+    for (int32_t l = 0; l < v->D; ++l) {
+        v->init_size[l] = v->rows[l];
+        v->first[l] = 0;
+        v->sstamp[l] = 0;
+        v->tstamp[l] = 0;
+        v->is_target[l] = 0;
+    }
+    v->steps = 0;
+    v->moves = 0;
+    v->last_src = -1;
+    v->last_collapse = 0;
+    v->T0 = env_count_thin(v);
+    v->D0 = env_levels(v);
+    v->done = env_stop(v);
+}
+
+void orc_env_destroy(orc_env *v)
+{
+    if (!v) return;
+    free(v->deps_row);
+    free(v->lev);
+    free(v->cost);
+    free(v->deps);
+    free(v->rows);
+    free(v->init_size);
+    free(v->first);
+    free(v->sstamp);
+    free(v->tstamp);
+    free(v->is_target);
+    free(v->mv_row);
+    free(v->mv_src);
+    free(v->mv_tgt);
+    free(v);
+}
+
+/* level: the analysis' level of every row (kept by pointer: the caller
+ * keeps it alive while the environment exists).  Returns NULL on bad
+ * arguments. */
+orc_env *orc_env_create(int32_t n, const int32_t *rowptr, const int32_t *level, int32_t D,
+                        double alc, double cv, const orc_env_params *prm, int32_t cap)
+{
+    if (n < 1 || D < 1 || D > n || cap < 0 || !(prm->alpha >= 0.0) || !(prm->thin_stop >= 0.0) ||
+        !(prm->decay > 0.0 && prm->decay < 1.0) || !(prm->eps >= 0.0) || prm->max_dist < 0 ||
+        prm->search_window < 1 || prm->max_steps < 0 || prm->stall_steps < 0 ||
+        prm->keep_top < 1)
+        return NULL;
+    for (int32_t i = 0; i < n; ++i)
+        if (level[i] < 0 || level[i] >= D) return NULL;
+    orc_env *v = (orc_env *)calloc(1, sizeof(orc_env));
+    v->n = n;
+    v->D = D;
+    v->cap = cap;
+    v->prm = *prm;
+    double relax = 1.0 - cv;
+    if (relax < 0.0) relax = 0.0;
+    double scaled = prm->alpha * relax;
+    double factor = 1.0 + scaled;
+    v->thr = alc * factor;
+    v->alc = alc;
+    v->arl = (double)n / (double)D;
+    v->level0 = level;
+    v->deps_row = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    for (int32_t i = 0; i < n; ++i) v->deps_row[i] = rowptr[i + 1] - rowptr[i] - 1;
+    v->lev = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    v->cost = (int64_t *)malloc(sizeof(int64_t) * (size_t)D);
+    v->deps = (int64_t *)malloc(sizeof(int64_t) * (size_t)D);
+    v->rows = (int32_t *)malloc(sizeof(int32_t) * (size_t)D);
+    v->init_size = (int32_t *)malloc(sizeof(int32_t) * (size_t)D);
+    v->first = (int32_t *)malloc(sizeof(int32_t) * (size_t)D);
+    v->sstamp = (int32_t *)malloc(sizeof(int32_t) * (size_t)D);
+    v->tstamp = (int32_t *)malloc(sizeof(int32_t) * (size_t)D);
+    v->is_target = (unsigned char *)malloc((size_t)D);
+    size_t cc = cap > 0 ? (size_t)cap : 1;
+    v->mv_row = (int32_t *)malloc(sizeof(int32_t) * cc);
+    v->mv_src = (int32_t *)malloc(sizeof(int32_t) * cc);
+    v->mv_tgt = (int32_t *)malloc(sizeof(int32_t) * cc);
+    int64_t ms = 2 * (int64_t)D < 6144 ? 6144 : 2 * (int64_t)D;
+    if (ms > INT32_MAX) ms = INT32_MAX;
+    v->max_steps = prm->max_steps > 0 ? prm->max_steps : (int32_t)ms;
+    orc_env_reset(v);
+    return v;
+}
+
+static void env_fill(const orc_env *v, orc_env_result *r)
+{
+    r->done = v->done;
+    r->steps = v->steps;
+    r->moves = v->moves;
+    r->levels = env_levels(v);
+    r->thin = env_count_thin(v);
+    r->thin0 = v->T0;
+    env_cvs(v, &r->cv, &r->cv_rows);
+}
+
+void orc_env_step(orc_env *v, int32_t a, orc_env_result *r)
+{
+    memset(r, 0, sizeof *r);
+    r->node = r->src = r->tgt = -1;
+    if (v->done >= 0) {
+        r->outcome = ORC_ENV_IGNORED;
+        env_fill(v, r);
+        return;
+    }
+    const int32_t step = v->steps + 1;
+    const double ra = v->prm.reward_alpha;
+    int32_t t = -1, node = -1;
+    int outcome = ORC_ENV_MOVED;
+    if (a < 1 || a >= v->D || v->rows[a] == 0) {
+        outcome = ORC_ENV_INVALID;
+    } else {
+        /* node: fewest dependencies, ties to the lower row */
+        for (int32_t i = 0; i < v->n; ++i)
+            if (v->lev[i] == a && (node < 0 || v->deps_row[i] < v->deps_row[node])) node = i;
+        /* Algorithm 1 */
+        int32_t p = a - 1;
+        while (p > 0 && v->rows[p] == 0) --p;
+        if (p == 0) {
+            t = env_thin(v, 0) ? 0 : -1;
+        } else {
+            int32_t found = 0, best = -1;
+            for (int32_t l = p; l >= 0 && found < v->prm.search_window; --l) {
+                if (!env_thin(v, l)) continue;
+                ++found;
+                if (best < 0 || v->tstamp[l] > v->tstamp[best]) best = l;
+            }
+            if (best >= 0) t = best;
+            else t = env_thin(v, a) ? p : -1;
+        }
+        if (t >= 0 && a - t > v->prm.max_dist) t = -1;
+        if (t < 0) outcome = ORC_ENV_REJECTED;
+    }
+    v->steps = step;
+    if (outcome != ORC_ENV_MOVED) {
+        r->outcome = outcome;
+        r->src = outcome == ORC_ENV_REJECTED ? a : -1;
+        r->node = outcome == ORC_ENV_REJECTED ? node : -1;
+        r->reward = -ra;
+        v->done = env_stop(v);
+        env_fill(v, r);
+        return;
+    }
+
+    double cv_before, cvr_unused;
+    env_cvs(v, &cv_before, &cvr_unused);
+    const int32_t size = v->rows[a];
+    const int src_thin = env_thin(v, a);
+
+    /* abandonment of the previous source, on the state before the move */
+    double r_ab = 0.0;
+    const int32_t A = v->last_src;
+    if (A >= 1 && A != a) {
+        if (v->is_target[A]) {
+            v->init_size[A] = v->rows[A];
+            v->first[A] = 0;
+        } else if (v->rows[A] > 0) {
+            int32_t ones = 0;
+            for (int32_t l = 1; l < v->D; ++l) ones += v->rows[l] == 1;
+            if (!(ones > 0 && env_thin(v, A))) {
+                double q = (double)v->rows[A] / ((double)v->init_size[A] + 1.0);
+                double c = 1.0 - q;
+                double pen = (1.0 - c) * log1p((double)(step - v->first[A]));
+                r_ab = -pen;
+            }
+        }
+    }
+
+    /* the move */
+    const int64_t d = v->deps_row[node];
+    v->lev[node] = t;
+    v->cost[a] -= 2 * d + 1;
+    v->deps[a] -= d;
+    v->rows[a] -= 1;
+    v->cost[t] += 2 * d + 1;
+    v->deps[t] += d;
+    v->rows[t] += 1;
+    v->is_target[t] = 1;
+    v->tstamp[t] = step;
+    v->sstamp[a] = step;
+    if (v->first[a] == 0) v->first[a] = step;
+    v->last_src = a;
+    if (v->moves < v->cap) {
+        v->mv_row[v->moves] = node;
+        v->mv_src[v->moves] = a;
+        v->mv_tgt[v->moves] = t;
+    }
+    v->moves += 1;
+    const int collapsed = v->rows[a] == 0;
+    if (collapsed) v->last_collapse = step;
+
+    double cv_after, cvr_after;
+    env_cvs(v, &cv_after, &cvr_after);
+    const int32_t levels = env_levels(v);
+    const double D0 = (double)v->D0;
+
+    double dcv = cv_before - cv_after;
+    double r_cv = 0.0;
+    if (dcv < -v->prm.eps) r_cv = -ra;
+    else if (dcv > v->prm.eps) r_cv = D0 * dcv;
+
+    double s = log(1.0 + (double)size + 1.0);
+    double r_cp;
+    if (collapsed) r_cp = ra * (D0 / (double)levels) * (1.0 + 1.0 / s);
+    else if (src_thin) r_cp = ra / s;
+    else r_cp = -1.0 * ra * (1.0 + s);
+
+    int32_t dist = a - t, thd = v->prm.dist_threshold;
+    double r_rw;
+    if (dist < thd) r_rw = log1p((double)(thd - dist)) / D0;
+    else r_rw = -log1p((double)(dist - thd)) / D0;
+
+    r->outcome = ORC_ENV_MOVED;
+    r->node = node;
+    r->src = a;
+    r->tgt = t;
+    r->collapsed = collapsed;
+    r->r_cv = r_cv;
+    r->r_cp = r_cp;
+    r->r_rwdist = r_rw;
+    r->r_abandon = r_ab;
+    double w1 = 0.80 * r_cv;
+    double w2 = 0.80 * r_cp;
+    double w3 = 0.05 * r_rw;
+    double w4 = 0.50 * r_ab;
+    double sum = w1 + w2;
+    sum = sum + w3;
+    r->reward = sum + w4;
+    v->done = env_stop(v);
+    env_fill(v, r);
+}
+
+/* Observation of Section 4.2 (Table 3) and the action mask of Section 4.4.
+ *   level[f * D + l], f = 0..5: cost / ALC, rows / ARL, source affinity,
+ *     target affinity, completion ratio 1 - rows/(initial size + 1), thin
+ *     (1 or 0); ALC and ARL of the input.
+ *   global[9]: CV of level costs, 1 (its reference), CV of rows per level,
+ *     1, levels / n, moves / n (rewrite ratio), thin / T0 (0 when T0 = 0),
+ *     levels / D0 (critical-path ratio), thin / levels.
+ *   mask[D]: 1 for a valid action (1 <= l, non-empty), all 0 once the
+ *     episode ended; when the previous move's source has exactly one row
+ *     left, only that level; otherwise, after stall_steps > 0 steps without
+ *     a collapse, only the keep_top valid levels of highest source affinity
+ *     (ties to the lower level; levels that received rows rank below
+ *     untouched ones).
+ * Each output is nullable. */
+void orc_env_observe(const orc_env *v, double *level, double *global, unsigned char *mask)
+{
+    const int32_t D = v->D;
+    const int32_t thin = env_count_thin(v), levels = env_levels(v);
+    if (level) {
+        for (int32_t l = 0; l < D; ++l) {
+            int empty = v->rows[l] == 0;
+            level[0 * D + l] = (double)v->cost[l] / v->alc;
+            level[1 * D + l] = (double)v->rows[l] / v->arl;
+            double sa, ta;
+            if (empty || v->is_target[l]) sa = -1.0;
+            else if (v->sstamp[l] == 0) sa = 0.0;
+            else sa = pow(v->prm.decay, (double)(v->steps - v->sstamp[l]));
+            if (!env_thin(v, l)) ta = -1.0;
+            else if (v->tstamp[l] == 0) ta = 0.0;
+            else ta = pow(v->prm.decay, (double)(v->steps - v->tstamp[l]));
+            level[2 * D + l] = sa;
+            level[3 * D + l] = ta;
+            double q = (double)v->rows[l] / ((double)v->init_size[l] + 1.0);
+            level[4 * D + l] = 1.0 - q;
+            level[5 * D + l] = env_thin(v, l) ? 1.0 : 0.0;
+        }
+    }
+    if (global) {
+        double cvc, cvr;
+        env_cvs(v, &cvc, &cvr);
+        global[0] = cvc;
+        global[1] = 1.0;
+        global[2] = cvr;
+        global[3] = 1.0;
+        global[4] = (double)levels / (double)v->n;
+        global[5] = (double)v->moves / (double)v->n;
+        global[6] = v->T0 > 0 ? (double)thin / (double)v->T0 : 0.0;
+        global[7] = (double)levels / (double)v->D0;
+        global[8] = levels > 0 ? (double)thin / (double)levels : 0.0;
+    }
+    if (mask) {
+        for (int32_t l = 0; l < D; ++l) mask[l] = v->done < 0 && l >= 1 && v->rows[l] > 0;
+        if (v->done >= 0) return;
+        if (v->last_src >= 1 && v->rows[v->last_src] == 1) {
+            for (int32_t l = 0; l < D; ++l) mask[l] = l == v->last_src;
+        } else if (v->prm.stall_steps > 0 && v->steps - v->last_collapse >= v->prm.stall_steps) {
+            /* keep the keep_top best valid levels by (key desc, level asc) */
+            unsigned char *keep = (unsigned char *)calloc((size_t)D, 1);
+            for (int32_t k = 0; k < v->prm.keep_top; ++k) {
+                int32_t best = -1;
+                int64_t bkey = 0;
+                for (int32_t l = 1; l < D; ++l) {
+                    if (!mask[l] || keep[l]) continue;
+                    int64_t key = v->is_target[l] ? -1 : v->sstamp[l];
+                    if (best < 0 || key > bkey) { best = l; bkey = key; }
+                }
+                if (best < 0) break;
+                keep[best] = 1;
+            }
+            for (int32_t l = 0; l < D; ++l) mask[l] = keep[l];
+            free(keep);
+        }
+    }
+}
+
+/* State readout: current level of every row (nullable), per-level cost,
+ * rows, dependency sums (each nullable), and the move list so far. */
+void orc_env_state(const orc_env *v, int32_t *lev, int64_t *cost, int32_t *rows, int64_t *deps,
+                   int32_t *mv_row, int32_t *mv_src, int32_t *mv_tgt)
+{
+    for (int32_t i = 0; lev && i < v->n; ++i) lev[i] = v->lev[i];
+    for (int32_t l = 0; l < v->D; ++l) {
+        if (cost) cost[l] = v->cost[l];
+        if (rows) rows[l] = v->rows[l];
+        if (deps) deps[l] = v->deps[l];
+    }
+    int32_t m = v->moves < v->cap ? v->moves : v->cap;
+    for (int32_t q = 0; q < m; ++q) {
+        if (mv_row) mv_row[q] = v->mv_row[q];
+        if (mv_src) mv_src[q] = v->mv_src[q];
+        if (mv_tgt) mv_tgt[q] = v->mv_tgt[q];
+    }
 }
