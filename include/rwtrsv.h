@@ -424,6 +424,142 @@ rwt_status rwt_gen_rowsets(int32_t n, int32_t num_env, int32_t cap, const rwt_ge
                            void* d_ws, size_t ws_bytes, rwt_stream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Environment step (Sections 4.1-4.5, Algorithms 1 and 2) for many
+ * environments over one matrix, driven by the caller's policy: every call
+ * of rwt_env_step applies one action (a source level) per environment and
+ * returns its reward; rwt_env_observe writes the observation of Table 3
+ * and the action mask of Section 4.4.  The rewriting list of each
+ * environment grows in the caller's move arrays.
+ *
+ * State (Section 4.1; the DAG is never modified): the level of every row
+ * and, per level, its cost (sum of 2*nnz_i - 1; a moved row keeps its
+ * original cost), row count and dependency sum; per level also whether it
+ * ever received a row, its initial size and first-touch step (abandonment)
+ * and the steps of its last choice as source and of its last received row
+ * (affinities, Section 4.2).  thr = ALC * (1 + alpha * max(0, 1 - CV)) of
+ * the input, fixed; thin = non-empty and cost < thr; levels and CV count
+ * the non-empty levels.
+ *
+ * One step with action a (readings of what the paper leaves open):
+ *   validity  1 <= a < D and level a non-empty (the mask heuristics shape
+ *             the policy's mask only).  An invalid action, or one that
+ *             Algorithm 1 rejects, changes only the step count; reward
+ *             -reward_alpha;
+ *   node      the row of level a with the fewest dependencies (ties: lower
+ *             row), rows that moved in included (Section 4.4);
+ *   target    Algorithm 1: p = nearest non-empty level above a; p == 0:
+ *             level 0 if thin, else reject; p > 0: among the search_window
+ *             nearest thin levels at or above p, the one that most recently
+ *             received a row (never: lowest; ties: the nearest); with none,
+ *             p when the source is thin, else reject; reject when a - t >
+ *             max_dist;
+ *   reward    Algorithm 2 with dCV = CV before - CV after:
+ *             r_cv = -reward_alpha if dCV < -eps, D0*dCV if dCV > eps, else 0;
+ *             s = ln(size + 2) with the source's rows before the move;
+ *             r_cp = reward_alpha (D0/levels after)(1 + 1/s) when the source
+ *             emptied, reward_alpha/s when it was thin, else
+ *             -reward_alpha (1 + s);
+ *             r_rwdist = log1p(thd - d)/D0 if d < thd else -log1p(d - thd)/D0,
+ *             d = a - t, thd = dist_threshold;
+ *             r_abandon for the previous move's source A != a: if A ever
+ *             received a row, its initial size becomes its current size and
+ *             its first touch 0, no penalty; none if A is empty, or if a
+ *             level >= 1 with one row exists and A is thin; else
+ *             -(rows_A/(init_A + 1)) * log1p(step - first touch of A);
+ *             reward = 0.80 r_cv + 0.80 r_cp + 0.05 r_rwdist + 0.50 r_abandon
+ *             (the weights of Section 4.5); D0 = initial level count.
+ *   end       checked after reset and after every step, in this order:
+ *             RWT_GEN_THIN when T0 > 0 and thin/T0 < thin_stop;
+ *             RWT_GEN_MOVES after cap moves; RWT_GEN_STEPS after max_steps
+ *             steps (0 = max(2 D, 6144)); RWT_GEN_NO_SOURCE when only level
+ *             0 is non-empty.  Later actions are ignored (reward 0).
+ *
+ * Workspace: rwt_env_ws bytes, owned by the caller and kept between calls;
+ * rwt_env_init builds the tables from the analysis of L (d_level[n],
+ * d_level_ptr[D+1], d_cost[D], d_stats, D = num_levels; device) and resets
+ * every environment; it synchronizes the stream before returning.  Every
+ * later call must pass the same n, num_levels, num_env, cap and workspace:
+ * the kernels check them against the workspace and do nothing (step:
+ * outcome RWT_ENV_ERROR) on a mismatch.  Calls on one workspace must not
+ * overlap.  Sizes: n >= 1, 1 <= num_levels <= n, num_env >= 1, cap >= 1.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    double alpha;            /* threshold relaxation, >= 0 (the paper: 1.0) */
+    double thin_stop;        /* episode end below this thin ratio (0.02) */
+    double reward_alpha;     /* alpha of Algorithm 2, >= 0 */
+    double eps;              /* dead band of dCV, >= 0 */
+    double decay;            /* affinity decay per step, in (0, 1) */
+    int32_t max_dist;        /* MAX_REWRITE_DISTANCE, >= 0 */
+    int32_t search_window;   /* SEARCH_WINDOW (the paper: 5), >= 1 */
+    int32_t dist_threshold;  /* threshold of r_rwdist, >= 0 */
+    int32_t max_steps;       /* truncation; 0 = max(2 D, 6144) */
+    int32_t stall_steps;     /* mask to keep_top after this many steps
+                                without a collapse; 0 = off */
+    int32_t keep_top;        /* X of Section 4.4, >= 1 */
+} rwt_env_params;
+
+typedef enum {
+    RWT_ENV_MOVED = 0,
+    RWT_ENV_INVALID = 1,
+    RWT_ENV_REJECTED = 2,   /* Algorithm 1 found no target */
+    RWT_ENV_IGNORED = 3,    /* the episode had ended */
+    RWT_ENV_ERROR = 4       /* workspace mismatch or corrupt state */
+} rwt_env_outcome;
+
+typedef struct {
+    int32_t outcome;     /* rwt_env_outcome */
+    int32_t node;        /* the row chosen (moved or rejected), else -1 */
+    int32_t src;         /* the action when it was valid, else -1 */
+    int32_t tgt;         /* target level of a move, else -1 */
+    int32_t collapsed;   /* the source emptied */
+    int32_t done;        /* -1 running, else an rwt_gen_stop */
+    int32_t steps, moves, levels, thin, thin0, pad_;
+    double reward;
+    double r_cv, r_cp, r_rwdist, r_abandon;   /* 0 unless moved */
+    double cv;           /* CV of the non-empty levels' costs after the step */
+    double cv_rows;      /* CV of their row counts */
+} rwt_env_result;
+
+rwt_status rwt_env_ws(int32_t n, int32_t num_levels, int32_t num_env, int32_t cap,
+                      size_t* h_bytes);
+rwt_status rwt_env_init(const rwt_csr* L, const int32_t* d_level, const int32_t* d_level_ptr,
+                        const int64_t* d_cost, const rwt_level_stats* d_stats,
+                        int32_t num_levels, int32_t num_env, int32_t cap,
+                        const rwt_env_params* h_params, void* d_ws, size_t ws_bytes,
+                        rwt_stream_t stream);
+/* Reset the environments e with d_which[e] != 0 (device, nullable: all). */
+rwt_status rwt_env_reset(int32_t n, int32_t num_levels, int32_t num_env, int32_t cap,
+                         const uint8_t* d_which, void* d_ws, size_t ws_bytes,
+                         rwt_stream_t stream);
+/* d_action[num_env] (device); d_res[num_env]; move q of environment e is
+ * written to d_mv_row/src/tgt[e*cap + q] (the same arrays at every step
+ * since the environment's reset).  Asynchronous. */
+rwt_status rwt_env_step(int32_t n, int32_t num_levels, int32_t num_env, int32_t cap,
+                        const int32_t* d_action, rwt_env_result* d_res, int32_t* d_mv_row,
+                        int32_t* d_mv_src, int32_t* d_mv_tgt, void* d_ws, size_t ws_bytes,
+                        rwt_stream_t stream);
+/* Observation (each output nullable, device, float32 / uint8):
+ *   d_obs_level[(e*6 + f)*D + l], f = 0..5: cost/ALC, rows/ARL, source
+ *     affinity, target affinity, completion ratio 1 - rows/(init + 1),
+ *     thin (1/0); affinity = decay^(steps - stamp), 0 if never, -1 when the
+ *     level is empty or (source) ever received a row or (target) not thin;
+ *   d_obs_global[e*9 + g]: CV of level costs, 1 (its reference), CV of rows
+ *     per level, 1, levels/n, moves/n (rewrite ratio), thin/T0 (0 if T0 =
+ *     0), levels/D0 (critical-path ratio), thin/levels;
+ *   d_mask[e*D + l]: 1 for levels >= 1 that are non-empty while the episode
+ *     runs; only the previous source when it has one row left; otherwise,
+ *     after stall_steps steps without a collapse, only the keep_top of
+ *     highest source affinity (levels that received rows rank lowest, ties
+ *     to the lower level).  Asynchronous. */
+rwt_status rwt_env_observe(int32_t n, int32_t num_levels, int32_t num_env, int32_t cap,
+                           float* d_obs_level, float* d_obs_global, uint8_t* d_mask,
+                           const void* d_ws, size_t ws_bytes, rwt_stream_t stream);
+/* Per-level state d_cost/d_rows/d_deps[e*D + l] (device, each nullable). */
+rwt_status rwt_env_levels(int32_t n, int32_t num_levels, int32_t num_env, int32_t cap,
+                          int64_t* d_cost, int32_t* d_rows, int64_t* d_deps, const void* d_ws,
+                          size_t ws_bytes, rwt_stream_t stream);
+
+/* ------------------------------------------------------------------------
  * Batched launch: many matrices of uneven size, each with its own block of
  * right-hand sides, plus many candidate rewrite sets (rewriting lists in
  * the sense of Algorithm 1, one per environment step of the paper's agent)

@@ -104,6 +104,26 @@ class GenResult(C.Structure):
         return d
 
 
+class EnvParams(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("thin_stop", C.c_double), ("reward_alpha", C.c_double),
+                ("eps", C.c_double), ("decay", C.c_double), ("max_dist", C.c_int32),
+                ("search_window", C.c_int32), ("dist_threshold", C.c_int32),
+                ("max_steps", C.c_int32), ("stall_steps", C.c_int32), ("keep_top", C.c_int32)]
+
+
+class EnvResult(C.Structure):
+    _fields_ = [("outcome", C.c_int32), ("node", C.c_int32), ("src", C.c_int32),
+                ("tgt", C.c_int32), ("collapsed", C.c_int32), ("done", C.c_int32),
+                ("steps", C.c_int32), ("moves", C.c_int32), ("levels", C.c_int32),
+                ("thin", C.c_int32), ("thin0", C.c_int32), ("pad_", C.c_int32),
+                ("reward", C.c_double), ("r_cv", C.c_double), ("r_cp", C.c_double),
+                ("r_rwdist", C.c_double), ("r_abandon", C.c_double), ("cv", C.c_double),
+                ("cv_rows", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
+
+
 P = C.c_void_p
 I32 = C.c_int32
 I64 = C.c_int64
@@ -163,6 +183,13 @@ SIGNATURES = {
                                P, P, P, P, P, P, P, P, SZ, P]),
     "rwt_gen_rowsets_ws": (C.c_int, [I32, I32, C.POINTER(SZ)]),
     "rwt_gen_rowsets": (C.c_int, [I32, I32, I32, P, P, P, P, P, P, P, SZ, P]),
+    "rwt_env_ws": (C.c_int, [I32, I32, I32, I32, C.POINTER(SZ)]),
+    "rwt_env_init": (C.c_int, [C.POINTER(Csr), P, P, P, P, I32, I32, I32, C.POINTER(EnvParams),
+                               P, SZ, P]),
+    "rwt_env_reset": (C.c_int, [I32, I32, I32, I32, P, P, SZ, P]),
+    "rwt_env_step": (C.c_int, [I32, I32, I32, I32, P, P, P, P, P, P, SZ, P]),
+    "rwt_env_observe": (C.c_int, [I32, I32, I32, I32, P, P, P, P, SZ, P]),
+    "rwt_env_levels": (C.c_int, [I32, I32, I32, I32, P, P, P, P, SZ, P]),
 }
 
 _lib = None

@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import RwtError, check
 
 __all__ = ["CSRMatrix", "LevelInfo", "validate", "analyze", "rewrite", "Rewrite", "Rewriter", "Plan",
-           "apply_MT", "grad_vals", "Batch", "RwtError"]
+           "apply_MT", "grad_vals", "Batch", "RwtError", "Env"]
 
 
 def _stream() -> int:
@@ -480,6 +480,107 @@ def generate(L: CSRMatrix, info: LevelInfo, params, cap: int, level_sums: bool =
     return Generated(mr[:, :cap], ms[:, :cap], mt[:, :cap], results,
                      None if lc is None else lc[:, :D], None if lr is None else lr[:, :D],
                      None if ld is None else ld[:, :D], d_res, n, cap)
+
+
+ENV_DEFAULTS = dict(alpha=1.0, thin_stop=0.02, reward_alpha=1.0, eps=1e-6, decay=0.9, max_dist=8,
+                    search_window=5, dist_threshold=2, max_steps=0, stall_steps=0, keep_top=8)
+ENV_OUTCOMES = {0: "moved", 1: "invalid", 2: "rejected", 3: "ignored", 4: "error"}
+
+
+class EnvStep:
+    """Results of one rwt_env_step call, as views of its device buffer."""
+
+    def __init__(self, raw: torch.Tensor, num_env: int):
+        self.raw = raw
+        self.num_env = num_env
+        ints = raw.view(torch.int32).view(num_env, -1)
+        dbl = raw.view(torch.float64).view(num_env, -1)
+        self.outcome, self.node, self.src, self.tgt = ints[:, 0], ints[:, 1], ints[:, 2], ints[:, 3]
+        self.collapsed, self.done = ints[:, 4], ints[:, 5]
+        self.reward = dbl[:, 6]
+        self.terms = dbl[:, 7:11]          # r_cv, r_cp, r_rwdist, r_abandon
+        self.cv = dbl[:, 11]
+
+    def results(self) -> list[dict]:
+        buf = self.raw.cpu().numpy().tobytes()
+        sz = C.sizeof(_lib.EnvResult)
+        return [_lib.EnvResult.from_buffer_copy(buf, e * sz).as_dict()
+                for e in range(self.num_env)]
+
+
+class Env:
+    """num_env environments of Sections 4.1-4.5 over one analysed matrix,
+    stepped together by the caller's policy (rwt_env_*): step(actions)
+    returns the Algorithm 2 rewards, observe() the Table 3 features and the
+    action mask.  Move lists grow in mv_row / mv_src / mv_tgt (num_env, cap)."""
+
+    def __init__(self, L: CSRMatrix, info: LevelInfo, num_env: int, cap: int | None = None,
+                 **params):
+        unknown = set(params) - set(ENV_DEFAULTS)
+        if unknown:
+            raise TypeError("unknown environment parameters: %s" % sorted(unknown))
+        self.lib = _lib.load()
+        p = dict(ENV_DEFAULTS, **params)
+        self.params = p
+        self.n, self.D, self.E = L.n, info.num_levels, int(num_env)
+        self.cap = self.n if cap is None else int(cap)
+        self.device = L.device
+        sz = C.c_size_t(0)
+        check(self.lib.rwt_env_ws(self.n, self.D, self.E, self.cap, C.byref(sz)))
+        self.ws = _workspace(sz.value, self.device)
+        hp = _lib.EnvParams(float(p["alpha"]), float(p["thin_stop"]), float(p["reward_alpha"]),
+                            float(p["eps"]), float(p["decay"]), int(p["max_dist"]),
+                            int(p["search_window"]), int(p["dist_threshold"]),
+                            int(p["max_steps"]), int(p["stall_steps"]), int(p["keep_top"]))
+        dev = self.device
+        self.mv_row = torch.full((self.E, self.cap), -1, dtype=torch.int32, device=dev)
+        self.mv_src = torch.full_like(self.mv_row, -1)
+        self.mv_tgt = torch.full_like(self.mv_row, -1)
+        self._res = torch.zeros(self.E * C.sizeof(_lib.EnvResult), dtype=torch.uint8, device=dev)
+        self.obs_level = torch.empty((self.E, 6, self.D), dtype=torch.float32, device=dev)
+        self.obs_global = torch.empty((self.E, 9), dtype=torch.float32, device=dev)
+        self.mask = torch.empty((self.E, self.D), dtype=torch.uint8, device=dev)
+        check(self.lib.rwt_env_init(C.byref(L.view()), _ptr(info.level), _ptr(info.level_ptr),
+                                    _ptr(info.cost), _ptr(info.device_stats), self.D, self.E,
+                                    self.cap, C.byref(hp), _ptr(self.ws), self.ws.numel(),
+                                    _stream()))
+
+    def _dims(self):
+        return self.n, self.D, self.E, self.cap
+
+    def reset(self, which: torch.Tensor | None = None):
+        """Reset every environment, or those with which[e] != 0 (bool/uint8)."""
+        w = None if which is None else which.to(device=self.device, dtype=torch.uint8).contiguous()
+        check(self.lib.rwt_env_reset(*self._dims(), _ptr(w), _ptr(self.ws), self.ws.numel(),
+                                     _stream()))
+
+    def step(self, actions) -> EnvStep:
+        a = torch.as_tensor(actions, dtype=torch.int32).to(self.device).contiguous()
+        if a.numel() != self.E:
+            raise ValueError("one action per environment")
+        check(self.lib.rwt_env_step(*self._dims(), _ptr(a), _ptr(self._res), _ptr(self.mv_row),
+                                    _ptr(self.mv_src), _ptr(self.mv_tgt), _ptr(self.ws),
+                                    self.ws.numel(), _stream()))
+        self._last_actions = a            # keep alive until the launch ran
+        return EnvStep(self._res, self.E)
+
+    def observe(self, level: bool = True, glob: bool = True, mask: bool = True):
+        """(level features (E, 6, D) f32, global features (E, 9) f32, mask
+        (E, D) uint8); the buffers are reused by the next call."""
+        check(self.lib.rwt_env_observe(*self._dims(), _ptr(self.obs_level if level else None),
+                                       _ptr(self.obs_global if glob else None),
+                                       _ptr(self.mask if mask else None), _ptr(self.ws),
+                                       self.ws.numel(), _stream()))
+        return self.obs_level, self.obs_global, self.mask
+
+    def levels(self):
+        """Per-level (cost, rows, dependency sums), each (E, D)."""
+        c = torch.empty((self.E, self.D), dtype=torch.int64, device=self.device)
+        r = torch.empty((self.E, self.D), dtype=torch.int32, device=self.device)
+        d = torch.empty_like(c)
+        check(self.lib.rwt_env_levels(*self._dims(), _ptr(c), _ptr(r), _ptr(d), _ptr(self.ws),
+                                      self.ws.numel(), _stream()))
+        return c, r, d
 
 
 def gen_rowsets(g: Generated) -> tuple[torch.Tensor, torch.Tensor, torch.Tensor]:

@@ -76,6 +76,20 @@ def test_host_only_calls(lib):
     assert lib.rwt_generate_ws(10, 3, 4, C.byref(sz)) == 0 and sz.value > 0
     assert lib.rwt_gen_rowsets_ws(1 << 16, 1 << 16, C.byref(sz)) == -8
     assert lib.rwt_gen_rowsets_ws(4, 100, C.byref(sz)) == 0 and sz.value > 0
+    # environment: sizes, a workspace too small, invalid parameters
+    assert lib.rwt_env_ws(10, 11, 1, 5, C.byref(sz)) == -1        # more levels than rows
+    assert lib.rwt_env_ws(10, 3, 0, 5, C.byref(sz)) == -1         # no environment
+    assert lib.rwt_env_ws(10, 3, 4, 0, C.byref(sz)) == -1         # no move capacity
+    assert lib.rwt_env_ws(10, 3, 4, 6, C.byref(sz)) == 0 and sz.value > 0
+    need = sz.value
+    assert lib.rwt_env_reset(10, 3, 4, 6, None, C.c_void_p(1), need - 1, None) == -7
+    assert lib.rwt_env_step(10, 3, 4, 6, None, None, None, None, None, C.c_void_p(1), need,
+                            None) == -1
+    ep = _lib.EnvParams(1.0, 0.02, 1.0, 1e-6, 1.0, 8, 5, 2, 0, 0, 8)   # decay must be < 1
+    c.n = 10
+    assert lib.rwt_env_init(C.byref(c), C.c_void_p(1), C.c_void_p(1), C.c_void_p(1),
+                            C.c_void_p(1), 3, 4, 6, C.byref(ep), C.c_void_p(1), need, None) == -1
+    assert b"parameters" in lib.rwt_last_error_string()
     for field, bad in (("block_rows", (1 << 20) + 1), ("rhs_chunk", 5), ("tune_cols", -1)):
         setattr(o, field, bad)
         assert lib.rwt_plan_ws(C.byref(c), C.byref(o), C.byref(sz)) == -1, field
