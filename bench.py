@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--no-pair", action="store_true", help="skip the L-then-U pair section")
     ap.add_argument("--no-generator", action="store_true",
                     help="skip the rewrite-list generator section")
+    ap.add_argument("--no-env", action="store_true", help="skip the environment-step section")
+    ap.add_argument("--env-count", type=int, default=1024, help="environments stepped together")
+    ap.add_argument("--env-steps", type=int, default=200, help="timed environment steps")
     ap.add_argument("--batch-count", type=int, default=256, help="matrices in the batch")
     ap.add_argument("--batch-steps", type=int, default=5, help="timed batched launches")
     ap.add_argument("--gen-workers", type=int, default=min(16, os.cpu_count() or 1),
@@ -367,6 +370,93 @@ def run_generator(args, L, Lh, info, dev):
     return res, cmp
 
 
+def run_env(args, L, info, dev):
+    """Environment steps (Algorithms 1 and 2) for env_count environments on
+    the workload's matrix under a uniform random policy over each mask.  One
+    rollout step -- the observation with the mask, the policy's draw (torch)
+    and the step -- is captured in a HIP graph and replayed; the kernels
+    alone are timed as well."""
+    import numpy as np
+    import torch
+
+    from paper_2609_40159_amd.api import Env
+
+    E, K = args.env_count, args.env_steps
+    t0 = time.perf_counter()
+    env = Env(L, info, E, cap=max(8, 4 * K))
+    torch.cuda.synchronize()
+    init_ms = (time.perf_counter() - t0) * 1e3
+
+    def one():
+        _, _, mask = env.observe()
+        score = torch.rand(mask.shape, device=dev) * mask
+        return env.step(score.argmax(dim=1).to(torch.int32))
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(3):
+            one()
+    torch.cuda.current_stream().wait_stream(s)
+    # CH rollout steps per graph, the returns summed inside it: one replay
+    # per CH steps keeps the host's launch cost off the step
+    CH = 20
+    K = (K + CH - 1) // CH * CH
+    rewards = torch.zeros(E, dtype=torch.float64, device=dev)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(CH):
+            st = one()
+            rewards += st.reward
+    env.reset()
+    rewards.zero_()
+    torch.cuda.synchronize()
+    a0 = torch.cuda.Event(enable_timing=True)
+    a1 = torch.cuda.Event(enable_timing=True)
+    a0.record()
+    for _ in range(K // CH):
+        g.replay()
+    a1.record()
+    torch.cuda.synchronize()
+    total = a0.elapsed_time(a1)
+    res = st.results()
+    moves = sum(r["moves"] for r in res)
+    done = sum(1 for r in res if r["done"] >= 0)
+    # the observation and the policy alone, back to back in a graph (they
+    # do not change the state); the step is the rest of the rollout step
+    mask_fixed = env.mask.clone()
+
+    def timed(fn, reps=50):
+        fn()
+        torch.cuda.synchronize()
+        b0 = torch.cuda.Event(enable_timing=True)
+        b1 = torch.cuda.Event(enable_timing=True)
+        gg = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gg):
+            for _ in range(reps):
+                fn()
+        b0.record()
+        gg.replay()
+        b1.record()
+        torch.cuda.synchronize()
+        return b0.elapsed_time(b1) / reps
+
+    obs_ms = timed(lambda: env.observe())
+    pol_ms = timed(lambda: (torch.rand(mask_fixed.shape, device=dev) * mask_fixed)
+                   .argmax(dim=1).to(torch.int32))
+    out = {"workload": "matrix of the main workload", "envs": E, "steps": K,
+           "policy": "uniform over each environment's mask (torch), in the graph",
+           "steps_per_graph": CH,
+           "init_ms": init_ms, "rollout_ms_per_step": total / K,
+           "env_steps_per_s": E * K / total * 1e3,
+           "observe_ms": obs_ms, "policy_ms": pol_ms,
+           "step_ms_by_difference": total / K - obs_ms - pol_ms,
+           "moves": moves, "episodes_ended": done,
+           "mean_return": float(rewards.mean().item())}
+    del env, g
+    return out
+
+
 def run_pair(args, L, Lh, dev, k, plan_rw=None, rwres=None):
     """The L-then-U pair of an incomplete factorization M = L L^T (U = L^T, an
     upper CSR with the diagonal first): one preconditioner application per
@@ -610,6 +700,10 @@ def main():
     pair = pair_cmp = None
     if not args.no_pair:
         pair, pair_cmp = run_pair(args, L, Lh, dev, k, plan, rwres)
+    envres = None
+    if not args.no_env:
+        envres = run_env(args, L, info, dev)
+        log("environment steps timed")
     # ---------------- CPU oracle baseline ----------------
     # The oracle runs here only: the main step on a bounded sample, and
     # beside it the generator sample and the pair (their lists and results
@@ -653,6 +747,22 @@ def main():
             cpu["generator"] = {"value": steps_or / t_or, "unit": "steps/s", "cores": 1,
                                 "sample": f"{len(gen_cmp['params'])} environments of the grid",
                                 "lists_equal_gpu": bool(same)}
+        if envres is not None:
+            # one oracle environment under the same kind of policy, about 3 s
+            rng = np.random.default_rng(7)
+            oe = oracle.Env(n, Lh.rowptr, a.level, a.num_levels, a.alc, a.cv, cap=4 * args.env_steps)
+            t1 = time.perf_counter()
+            ks = 0
+            while time.perf_counter() - t1 < 3.0 and ks < args.env_steps:
+                _, _, m = oe.observe()
+                v = np.flatnonzero(m)
+                r = oe.step(int(rng.choice(v)) if v.size else 0)
+                ks += 1
+                if r["done"] >= 0:
+                    oe.reset()
+            cpu["env"] = {"value": ks / (time.perf_counter() - t1), "unit": "env steps/s",
+                          "cores": 1, "sample": f"{ks} steps of one environment with its "
+                                                 "observation and mask"}
         if pair_cmp is not None:
             Uh = pair_cmp["Uh"]
             t1 = time.perf_counter()
@@ -728,6 +838,7 @@ def main():
         "roofline_other": roofs["bwd" if dom == "fwd" else "fwd"],
         "generator": generator,
         "pair": pair,
+        "env": envres,
         "batched": batched,
         "cpu_baseline": cpu,
     }

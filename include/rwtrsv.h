@@ -348,7 +348,7 @@ rwt_status rwt_grad_vals(const rwt_csr* L, const void* d_gB, int64_t ldg, const 
  *   source  the thin level >= 1 that never received a row and was never
  *           rejected, with the fewest rows (ties: lower level);
  *   node    its row with the fewest dependencies (ties: lower row),
- *           Section 4.4;
+ *           Section 4.3;
  *   target  Algorithm 1 with equal affinities: p = nearest non-empty level
  *           above the source; p == 0: level 0 if thin, else reject; p > 0:
  *           the nearest thin level at or above p, else p itself; reject when
@@ -427,8 +427,8 @@ rwt_status rwt_gen_rowsets(int32_t n, int32_t num_env, int32_t cap, const rwt_ge
  * Environment step (Sections 4.1-4.5, Algorithms 1 and 2) for many
  * environments over one matrix, driven by the caller's policy: every call
  * of rwt_env_step applies one action (a source level) per environment and
- * returns its reward; rwt_env_observe writes the observation of Table 3
- * and the action mask of Section 4.4.  The rewriting list of each
+ * returns its reward; rwt_env_observe writes the observation of Table 1
+ * and the action mask of Section 4.3.  The rewriting list of each
  * environment grows in the caller's move arrays.
  *
  * State (Section 4.1; the DAG is never modified): the level of every row
@@ -446,7 +446,7 @@ rwt_status rwt_gen_rowsets(int32_t n, int32_t num_env, int32_t cap, const rwt_ge
  *             Algorithm 1 rejects, changes only the step count; reward
  *             -reward_alpha;
  *   node      the row of level a with the fewest dependencies (ties: lower
- *             row), rows that moved in included (Section 4.4);
+ *             row), rows that moved in included (Section 4.3);
  *   target    Algorithm 1: p = nearest non-empty level above a; p == 0:
  *             level 0 if thin, else reject; p > 0: among the search_window
  *             nearest thin levels at or above p, the one that most recently
@@ -467,7 +467,7 @@ rwt_status rwt_gen_rowsets(int32_t n, int32_t num_env, int32_t cap, const rwt_ge
  *             level >= 1 with one row exists and A is thin; else
  *             -(rows_A/(init_A + 1)) * log1p(step - first touch of A);
  *             reward = 0.80 r_cv + 0.80 r_cp + 0.05 r_rwdist + 0.50 r_abandon
- *             (the weights of Section 4.5); D0 = initial level count.
+ *             (the weights of Section 4.4); D0 = initial level count.
  *   end       checked after reset and after every step, in this order:
  *             RWT_GEN_THIN when T0 > 0 and thin/T0 < thin_stop;
  *             RWT_GEN_MOVES after cap moves; RWT_GEN_STEPS after max_steps
@@ -495,7 +495,7 @@ typedef struct {
     int32_t max_steps;       /* truncation; 0 = max(2 D, 6144) */
     int32_t stall_steps;     /* mask to keep_top after this many steps
                                 without a collapse; 0 = off */
-    int32_t keep_top;        /* X of Section 4.4, >= 1 */
+    int32_t keep_top;        /* X of Section 4.3, >= 1 */
 } rwt_env_params;
 
 typedef enum {

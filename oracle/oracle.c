@@ -440,7 +440,7 @@ void orc_grad_vals(int32_t n, const int32_t *rowptr, const int32_t *colidx,
 
 /* ------------------------------------------------------------------------
  * Rewrite-list generator: the environment of Section 4.1 driven by a fixed
- * policy instead of the learned one, with the node choice of Section 4.4
+ * policy instead of the learned one, with the node choice of Section 4.3
  * and the target selection of Algorithm 1.  Written as plain scans over
  * the level table at every step.
  *
@@ -460,7 +460,7 @@ void orc_grad_vals(int32_t n, const int32_t *rowptr, const int32_t *colidx,
  *     rejected, the one with the fewest rows, ties to the lower level (a
  *     level keeps being chosen until it empties: its row count only falls);
  *   node: among the source's rows, the one with the fewest dependencies,
- *     ties to the lower row index (Section 4.4);
+ *     ties to the lower row index (Section 4.3);
  *   target (Algorithm 1): p = nearest non-empty level above the source.
  *     p == 0: the target is level 0 when level 0 is thin, else the step
  *     is rejected.  p > 0: the target is the nearest thin level at or above
@@ -652,7 +652,7 @@ int orc_generate(int32_t n, const int32_t *rowptr, const int32_t *level, int32_t
  * per level its cost, row count and dependency sum (a moved row keeps its
  * original cost 2*nnz_i - 1 and dependency count nnz_i - 1); per level also
  * whether it ever received a row, its initial size and first-touch step
- * (abandonment, Section 4.5), and the steps at which it was last chosen as
+ * (abandonment, Section 4.4), and the steps at which it was last chosen as
  * source and last received a row (the affinities of Section 4.2).
  *
  * Readings (the paper leaves these open; stated here and pinned by
@@ -660,12 +660,12 @@ int orc_generate(int32_t n, const int32_t *rowptr, const int32_t *level, int32_t
  *  - thr = ALC * (1 + alpha * max(0, 1 - CV)) of the input, fixed; thin =
  *    non-empty and cost < thr; levels, CV = over the non-empty levels.
  *  - action a is valid when 1 <= a < D and level a is non-empty; the mask
- *    heuristics of Section 4.4 shape the mask given to the policy
+ *    heuristics of Section 4.3 shape the mask given to the policy
  *    (env_observe) and do not change validity.  An invalid action, or one
  *    Algorithm 1 rejects, changes nothing but the step count and earns
  *    -reward_alpha.
  *  - node: the row of level a with the fewest dependencies, ties to the
- *    lower row index (Section 4.4); rows that moved in may move again.
+ *    lower row index (Section 4.3); rows that moved in may move again.
  *  - Algorithm 1: p = nearest non-empty level above a.  p == 0: target 0
  *    when level 0 is thin, else reject.  p > 0: among the search_window
  *    nearest thin levels at or above p, the one with the highest target
@@ -1025,7 +1025,7 @@ void orc_env_step(orc_env *v, int32_t a, orc_env_result *r)
     env_fill(v, r);
 }
 
-/* Observation of Section 4.2 (Table 3) and the action mask of Section 4.4.
+/* Observation of Section 4.2 (Table 1) and the action mask of Section 4.3.
  *   level[f * D + l], f = 0..5: cost / ALC, rows / ARL, source affinity,
  *     target affinity, completion ratio 1 - rows/(initial size + 1), thin
  *     (1 or 0); ALC and ARL of the input.

@@ -511,7 +511,7 @@ class EnvStep:
 class Env:
     """num_env environments of Sections 4.1-4.5 over one analysed matrix,
     stepped together by the caller's policy (rwt_env_*): step(actions)
-    returns the Algorithm 2 rewards, observe() the Table 3 features and the
+    returns the Algorithm 2 rewards, observe() the Table 1 features and the
     action mask.  Move lists grow in mv_row / mv_src / mv_tgt (num_env, cap)."""
 
     def __init__(self, L: CSRMatrix, info: LevelInfo, num_env: int, cap: int | None = None,

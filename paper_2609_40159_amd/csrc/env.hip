@@ -1,9 +1,9 @@
 // Environment step of Sections 4.1-4.5 for many environments over one
 // matrix: the caller's policy picks a source level per environment, one
-// launch applies every action (node choice of Section 4.4, target of
+// launch applies every action (node choice of Section 4.3, target of
 // Algorithm 1 with the target affinities and the search window), updates
 // the level table incrementally and returns the reward of Algorithm 2; a
-// second launch writes the observation of Table 3 and the action mask.
+// second launch writes the observation of Table 1 and the action mask.
 //
 // One wave serves one environment in the step: the move itself is a
 // handful of scalar updates; the 64 lanes are used for the searches (the

@@ -1,6 +1,6 @@
 // Rewrite-list generator: the environment of Section 4.1 (level table
 // updated per move without touching the DAG, relaxed thin-level threshold)
-// driven by a fixed policy, with the node choice of Section 4.4 and the
+// driven by a fixed policy, with the node choice of Section 4.3 and the
 // target selection of Algorithm 1, for many environments (parameter sets)
 // over one matrix in one launch.
 //

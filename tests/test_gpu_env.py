@@ -139,3 +139,48 @@ def test_env_workspace_mismatch_is_refused():
     out = [_lib.EnvResult.from_buffer_copy(res.cpu().numpy().tobytes(), e * C.sizeof(_lib.EnvResult))
            for e in range(4)]
     assert all(r.outcome == 4 for r in out)
+
+
+def test_env_graph_replay_matches_eager():
+    """One rollout step (observe, a deterministic masked policy, step)
+    captured in a graph and replayed, with eager work and synchronizations
+    between replays, equals the same steps run eagerly on a twin."""
+    from paper_2609_40159_amd.api import Env, analyze
+    L = synth.power_law(30000, 23)
+    G = to_gpu(L)
+    info = analyze(G)
+    E = 64
+    A = Env(G, info, E, cap=400, max_dist=30, stall_steps=5, keep_top=3)
+    B = Env(G, info, E, cap=400, max_dist=30, stall_steps=5, keep_top=3)
+    w = torch.rand((E, info.num_levels), generator=torch.Generator().manual_seed(3)).to(DEV)
+
+    def one(env):
+        _, _, mask = env.observe()
+        act = (w * mask).argmax(dim=1).to(torch.int32)
+        return env.step(act)
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        one(B)
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        outB = one(B)
+    A.reset()
+    B.reset()
+    torch.cuda.synchronize()
+    print("env graph replay: 150 replays", flush=True)
+    for k in range(150):
+        outA = one(A)
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(outA.raw, outB.raw), k
+        if k % 10 == 0:
+            ca, ra, da = A.levels()
+            cb, rb, db = B.levels()
+            assert torch.equal(ca, cb) and torch.equal(ra, rb) and torch.equal(da, db), k
+            assert torch.equal(A.obs_level, B.obs_level) and torch.equal(A.mask, B.mask), k
+            torch.cuda.synchronize()
+    assert torch.equal(A.mv_row, B.mv_row) and torch.equal(A.mv_tgt, B.mv_tgt)
+    assert int(outA.raw.view(torch.int32).view(E, -1)[:, 7].sum()) > 0   # moves were made

@@ -1,5 +1,5 @@
 """Pins for the oracle's rewrite-list generator (Section 4.1 thin levels and
-state, Section 4.4 node choice, Algorithm 1 target selection).  CPU only.
+state, Section 4.3 node choice, Algorithm 1 target selection).  CPU only.
 
 The hand-worked cases in golden/generator_cases.txt fix every branch of the
 target selection, the node order and each stop rule; the invariants below
