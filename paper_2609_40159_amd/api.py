@@ -16,6 +16,7 @@ from . import _lib
 from ._lib import RwtError, check
 
 __all__ = ["CSRMatrix", "LevelInfo", "validate", "analyze", "rewrite", "Rewrite", "Rewriter", "Plan",
+           "solve",
            "apply_MT", "grad_vals", "Batch", "RwtError", "Env"]
 
 
@@ -295,6 +296,19 @@ class Plan:
     def check(self) -> None:
         """Raise if a device wait expired in the last solve (synchronizes)."""
         check(self._lib.rwt_plan_check(self._h, _stream()))
+
+
+def solve(L: CSRMatrix, B: torch.Tensor, plan: Plan | None = None,
+          out: torch.Tensor | None = None) -> torch.Tensor:
+    """X = L^{-1} B (B: (n,) or (k, n), one right-hand side per row of the
+    block, column-major at the boundary).  Without a plan one is built for L
+    (analysis, schedule and autotuning); keep a Plan to reuse them."""
+    if plan is None:
+        k = 1 if B.dim() == 1 else B.shape[0]
+        plan = Plan(L, kmax=k)
+    elif plan.L is not L:
+        raise ValueError("the plan was built for another matrix")
+    return plan.solve(B, out=out)
 
 
 class UpperPlan(Plan):

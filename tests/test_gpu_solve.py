@@ -129,3 +129,19 @@ def test_solve_full_size_powerlaw_1m_64rhs(orc):
     plan.check()
     assert relerr(host(X), ref) <= 1e-12
     assert relerr(host(X), xs) <= 1e-10      # the rewritten system, against x*
+
+
+def test_solve_function_builds_or_reuses_a_plan(orc):
+    from paper_2609_40159_amd.api import Plan, solve
+    L = synth.power_law(8000, 31)
+    xs, B = synth.rhs(L, 3, 7)
+    ref = orc.solve(L.n, L.rowptr, L.colidx, L.vals, B)
+    G = to_gpu(L)
+    X = solve(G, block(B))
+    assert relerr(host(X), ref) <= 1e-12
+    p = Plan(G, kmax=3)
+    assert relerr(host(solve(G, block(B), plan=p)), ref) <= 1e-12
+    x1 = solve(G, block(B[0]))                    # one right-hand side as a vector
+    assert x1.shape == (L.n,) and relerr(host(x1), ref[0]) <= 1e-12
+    with pytest.raises(ValueError):
+        solve(to_gpu(L), block(B), plan=p)        # a plan of another matrix object
