@@ -502,7 +502,8 @@ ENV_OUTCOMES = {0: "moved", 1: "invalid", 2: "rejected", 3: "ignored", 4: "error
 
 
 class EnvStep:
-    """Results of one rwt_env_step call, as views of its device buffer."""
+    """Results of one rwt_env_step call, as views of the environment's
+    result buffer (the next step overwrites them; clone to keep)."""
 
     def __init__(self, raw: torch.Tensor, num_env: int):
         self.raw = raw
@@ -526,7 +527,10 @@ class Env:
     """num_env environments of Sections 4.1-4.5 over one analysed matrix,
     stepped together by the caller's policy (rwt_env_*): step(actions)
     returns the Algorithm 2 rewards, observe() the Table 1 features and the
-    action mask.  Move lists grow in mv_row / mv_src / mv_tgt (num_env, cap)."""
+    action mask.  Move lists grow in mv_row / mv_src / mv_tgt (num_env, cap);
+    cap defaults to the step limit (no episode makes more moves), which
+    keeps the per-environment memory at 45 bytes per level plus 24 per move
+    of capacity."""
 
     def __init__(self, L: CSRMatrix, info: LevelInfo, num_env: int, cap: int | None = None,
                  **params):
@@ -537,7 +541,11 @@ class Env:
         p = dict(ENV_DEFAULTS, **params)
         self.params = p
         self.n, self.D, self.E = L.n, info.num_levels, int(num_env)
-        self.cap = self.n if cap is None else int(cap)
+        if cap is None:
+            # moves never outnumber steps: the step limit bounds the list
+            steps = int(p["max_steps"]) or max(2 * self.D, 6144)
+            cap = min(self.n, steps)
+        self.cap = int(cap)
         self.device = L.device
         sz = C.c_size_t(0)
         check(self.lib.rwt_env_ws(self.n, self.D, self.E, self.cap, C.byref(sz)))
