@@ -1,0 +1,42 @@
+"""Host-side checks of the benchmark's contract (no GPU): more than one GPU
+is refused with a JSON message, and the algorithmic byte counts reproduce
+the figures the workload definitions give for the 128^3 factor and the
+power-law matrix (4(n+1) + nnz(4+s) + 2nks for a forward solve)."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU" in line["error"]
+
+
+def test_solve_bytes_match_the_workload_figures():
+    # 128^3 7-point lower factor: n = 2,097,152, nnz = 8,339,456 (FP64, k = 1)
+    n = 128 ** 3
+    nnz = n + 3 * n - 3 * 128 * 128
+    assert nnz == 8_339_456
+    assert bench.bytes_solve(n, nnz, 1, 8) == 142_016_516        # 142.0 MB
+    assert round(bench.bytes_solve(n, nnz, 1, 4) / 1e6, 1) == 91.9
+    assert round(bench.bytes_solve(n, nnz, 64, 8) / 1e9, 3) == 2.256
+    # power-law 1M with about 8.97M stored entries, 64 right-hand sides
+    assert round(bench.bytes_solve(1_000_000, 8_970_000, 64, 8) / 1e9, 3) == 1.136
+
+
+def test_transposed_and_adjoint_bytes_are_consistent():
+    n, nnz, k, s = 1000, 4000, 3, 8
+    # the transposed solve reads what the forward solve reads plus the
+    # successor-list indirection; both read the block once and write it once
+    assert bench.bytes_solve_t(n, nnz, k, s) > bench.bytes_solve(n, nnz, k, s)
+    assert bench.bytes_grad_vals(n, nnz, k, s) == 4 * (n + 1) + nnz * (4 + s) + 2 * n * k * s
+    assert bench.bytes_apply_mt(n, k, s, 0) == 2 * n * k * s + 4 * (n + 1)
