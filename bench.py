@@ -225,6 +225,7 @@ def run_batched(args, man, gen, dev):
     b_solve = sum(bytes_solve(L.n, L.nnz, spec["k"], 8) for (L, _, _), spec in zip(mats, man))
     b_cand = sum(bytes_levels(mats[m][0].n, mats[m][0].nnz) for m in cand_mat)
     res["full_gbs"] = (b_solve + b_cand) / res["full_ms"] / 1e6
+    res["solve_bytes"] = b_solve
     del full
     # (2) solves only: one launch vs one launch per matrix (same schedules)
     solves = Batch(mats, [], None, None, block_rows=R)
@@ -803,6 +804,12 @@ def main():
         rf["handoff_ns"] = hop_ns
         rf["latency_floor_ms"] = Dp * hop_ns * 1e-6
     batched = run_batched(args, man, gen, dev) if man is not None else None
+    if batched is not None:
+        # floors of the batched solves: all their bytes at 8 TB/s, and the
+        # deepest matrix's levels times the measured hand-off
+        batched["solve_bandwidth_floor_ms"] = batched["solve_bytes"] / (PEAK_HBM_GBS * 1e9) * 1e3
+        batched["solve_latency_floor_ms"] = batched["max_levels"] * hop_ns * 1e-6
+        batched["handoff_ns"] = hop_ns
     if batched is not None:
         batched["host_generation_s"] = gen_s
 
