@@ -195,3 +195,15 @@ def test_env_graph_replay_matches_eager():
             torch.cuda.synchronize()
     assert torch.equal(A.mv_row, B.mv_row) and torch.equal(A.mv_tgt, B.mv_tgt)
     assert int(outA.raw.view(torch.int32).view(E, -1)[:, 7].sum()) > 0   # moves were made
+
+
+def test_env_capacity_one_and_single_environment():
+    """A move capacity of one ends every episode after its first move (the
+    MOVES end); a single environment; both against the oracle."""
+    L = synth.laplacian_2d(30, 20)
+    print("env parity: cap 1, 8 environments", flush=True)
+    res = run(L, 8, 12, dict(), seed=21, cap=1)
+    assert all(r["done"] in (-1, 2) for r in res)
+    assert any(r["done"] == 2 for r in res)
+    print("env parity: one environment", flush=True)
+    run(synth.power_law(3000, 5), 1, 80, dict(search_window=3), seed=22)
