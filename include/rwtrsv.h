@@ -17,7 +17,10 @@
  *    Inside a row the columns strictly ascend and the diagonal is the last
  *    entry (rwt_validate checks this).  nnz < 2^31.
  *  - Dense blocks of k right-hand sides: column-major n x k, leading
- *    dimension ld >= n, same value type as the matrix.
+ *    dimension ld >= n, same value type as the matrix.  An empty system
+ *    (n = 0, or k = 0) is accepted by the solves, the adjoint calls and
+ *    the upper-plan calls with NULL blocks, and does nothing; the empty
+ *    matrix (rowptr = {0}, nnz = 0) may pass NULL colidx and values.
  *  - Every pointer argument named d_* (and every pointer inside rwt_csr) is
  *    device memory; h_* is host memory.  The library never allocates device
  *    memory: the caller passes a workspace of at least the size returned by

@@ -171,9 +171,9 @@ extern "C" rwt_status rwt_apply_MT_apply(int32_t n, int64_t nC, const int32_t* d
     RWT_REQUIRE(k >= 0, RWT_ERR_INVALID_ARG, "negative k");
     RWT_REQUIRE(dt == RWT_F64 || dt == RWT_F32, RWT_ERR_INVALID_ARG, "bad dtype");
     RWT_REQUIRE(nC == 0 || (d_crow && d_cval), RWT_ERR_INVALID_ARG, "null multipliers");
-    RWT_REQUIRE(k == 0 || (d_Y && d_out && ldy >= n && ldo >= n), RWT_ERR_INVALID_ARG,
+    RWT_REQUIRE(k == 0 || n == 0 || (d_Y && d_out && ldy >= n && ldo >= n), RWT_ERR_INVALID_ARG,
                 "bad dense blocks");
-    RWT_REQUIRE(k == 0 || d_Y != d_out, RWT_ERR_INVALID_ARG, "output may not alias Y");
+    RWT_REQUIRE(k == 0 || n == 0 || d_Y != d_out, RWT_ERR_INVALID_ARG, "output may not alias Y");
     if (n == 0 || k == 0) return RWT_OK;
     MtWs w;
     carve_mt(const_cast<void*>(d_ws), n, nC, &w);
@@ -199,9 +199,9 @@ extern "C" rwt_status rwt_apply_MT(int32_t n, int64_t nC, const int32_t* d_crow,
     RWT_REQUIRE(k >= 0, RWT_ERR_INVALID_ARG, "negative k");
     RWT_REQUIRE(dt == RWT_F64 || dt == RWT_F32, RWT_ERR_INVALID_ARG, "bad dtype");
     RWT_REQUIRE(nC == 0 || (d_crow && d_ccol && d_cval), RWT_ERR_INVALID_ARG, "null multipliers");
-    RWT_REQUIRE(k == 0 || (d_Y && d_out && ldy >= n && ldo >= n), RWT_ERR_INVALID_ARG,
+    RWT_REQUIRE(k == 0 || n == 0 || (d_Y && d_out && ldy >= n && ldo >= n), RWT_ERR_INVALID_ARG,
                 "bad dense blocks");
-    RWT_REQUIRE(k == 0 || d_Y != d_out, RWT_ERR_INVALID_ARG, "output may not alias Y");
+    RWT_REQUIRE(k == 0 || n == 0 || d_Y != d_out, RWT_ERR_INVALID_ARG, "output may not alias Y");
     if (n == 0 || k == 0) return RWT_OK;
     RWT_TRY(rwt_apply_MT_prepare(n, nC, d_ccol, d_ws, ws_bytes, stream));
     return rwt_apply_MT_apply(n, nC, d_crow, d_cval, dt, d_Y, k, ldy, d_out, ldo, d_ws, ws_bytes,
@@ -222,9 +222,9 @@ extern "C" rwt_status rwt_apply_M(int32_t n, int64_t nC, const int32_t* d_crow,
     RWT_REQUIRE(nC < (int64_t(1) << 31), RWT_ERR_TOO_LARGE, "too many multipliers");
     RWT_REQUIRE(dt == RWT_F64 || dt == RWT_F32, RWT_ERR_INVALID_ARG, "bad dtype");
     RWT_REQUIRE(nC == 0 || (d_crow && d_ccol && d_cval), RWT_ERR_INVALID_ARG, "null multipliers");
-    RWT_REQUIRE(k == 0 || (d_B && d_out && ldb >= n && ldo >= n), RWT_ERR_INVALID_ARG,
+    RWT_REQUIRE(k == 0 || n == 0 || (d_B && d_out && ldb >= n && ldo >= n), RWT_ERR_INVALID_ARG,
                 "bad dense blocks");
-    RWT_REQUIRE(k == 0 || d_B != d_out, RWT_ERR_INVALID_ARG, "output may not alias B");
+    RWT_REQUIRE(k == 0 || n == 0 || d_B != d_out, RWT_ERR_INVALID_ARG, "output may not alias B");
     size_t need = 0;
     RWT_TRY(rwt_apply_M_ws(n, &need));
     RWT_REQUIRE(d_ws && ws_bytes >= need, RWT_ERR_BUFFER_TOO_SMALL,
@@ -256,7 +256,7 @@ extern "C" rwt_status rwt_grad_vals(const rwt_csr* L, const void* d_gB, int64_t 
     RWT_REQUIRE(L->dt == RWT_F64 || L->dt == RWT_F32, RWT_ERR_INVALID_ARG, "bad dtype");
     RWT_REQUIRE(L->n == 0 || (L->rowptr && L->colidx && d_gvals), RWT_ERR_INVALID_ARG,
                 "null pointer");
-    RWT_REQUIRE(k == 0 || (d_gB && d_X && ldg >= L->n && ldx >= L->n), RWT_ERR_INVALID_ARG,
+    RWT_REQUIRE(k == 0 || L->n == 0 || (d_gB && d_X && ldg >= L->n && ldx >= L->n), RWT_ERR_INVALID_ARG,
                 "bad dense blocks");
     if (L->n == 0) return RWT_OK;
     hipStream_t s = hs(stream);

@@ -216,7 +216,7 @@ rwt_status check_opts(const rwt_csr* L, const rwt_plan_opts* o) {
     RWT_REQUIRE(L != nullptr && o != nullptr, RWT_ERR_INVALID_ARG, "null argument");
     RWT_REQUIRE(L->n >= 0 && L->nnz >= L->n, RWT_ERR_INVALID_ARG, "bad sizes");
     RWT_REQUIRE(L->nnz < (int64_t(1) << 31), RWT_ERR_TOO_LARGE, "nnz must be < 2^31");
-    RWT_REQUIRE(L->rowptr && L->colidx && L->vals, RWT_ERR_INVALID_ARG,
+    RWT_REQUIRE(L->rowptr && (L->nnz == 0 || (L->colidx && L->vals)), RWT_ERR_INVALID_ARG,
                 "a plan needs pattern and values");
     RWT_REQUIRE(L->dt == RWT_F64 || L->dt == RWT_F32, RWT_ERR_INVALID_ARG, "bad dtype");
     RWT_REQUIRE(o->algo >= RWT_ALGO_AUTO && o->algo <= RWT_ALGO_SYNCFREE, RWT_ERR_INVALID_ARG,
@@ -600,7 +600,8 @@ static rwt_status solve_common(const rwt_plan* p, bool transposed, const void* B
     RWT_REQUIRE(p != nullptr, RWT_ERR_INVALID_ARG, "null plan");
     RWT_REQUIRE(k >= 0 && k <= p->opts.kmax, RWT_ERR_INVALID_ARG, "k=%d outside [0, kmax=%d]", k,
                 p->opts.kmax);
-    RWT_REQUIRE(B != nullptr && X != nullptr, RWT_ERR_INVALID_ARG, "null right-hand side");
+    RWT_REQUIRE(k == 0 || p->L.n == 0 || (B != nullptr && X != nullptr), RWT_ERR_INVALID_ARG,
+                "null right-hand side");
     RWT_REQUIRE(ldb >= p->L.n && ldx >= p->L.n, RWT_ERR_INVALID_ARG, "leading dimension < n");
     if (k == 0 || p->L.n == 0) return RWT_OK;
     Algo algo = transposed ? p->bwd : p->fwd;

@@ -822,7 +822,7 @@ extern "C" rwt_status rwt_rewrite_numeric(const rwt_csr* L, const int32_t* d_lev
     RWT_REQUIRE(Lp != nullptr && Lp->rowptr && (Lp->nnz == 0 || (Lp->colidx && Lp->vals)),
                 RWT_ERR_INVALID_ARG, "null output matrix");
     RWT_REQUIRE(Lp->n == L->n && Lp->dt == L->dt, RWT_ERR_INVALID_ARG, "output matrix mismatch");
-    RWT_REQUIRE(k >= 0 && (k == 0 || (d_B && d_Bp && ldb >= L->n && ldbp >= L->n)),
+    RWT_REQUIRE(k >= 0 && (k == 0 || L->n == 0 || (d_B && d_Bp && ldb >= L->n && ldbp >= L->n)),
                 RWT_ERR_INVALID_ARG, "bad right-hand side block");
     RWT_REQUIRE(k == 0 || d_B != d_Bp, RWT_ERR_INVALID_ARG, "B' may not alias B");
     hipStream_t s = hs(stream);

@@ -164,7 +164,7 @@ rwt_status up_args(const rwt_csr* U, const rwt_plan_opts* opts, rwt_csr* LU, siz
     RWT_REQUIRE(U != nullptr && opts != nullptr, RWT_ERR_INVALID_ARG, "null argument");
     RWT_REQUIRE(U->n >= 0 && U->nnz >= U->n, RWT_ERR_INVALID_ARG, "bad sizes");
     RWT_REQUIRE(U->nnz < (int64_t(1) << 31), RWT_ERR_TOO_LARGE, "nnz must be < 2^31");
-    RWT_REQUIRE(U->rowptr && U->colidx && U->vals, RWT_ERR_INVALID_ARG,
+    RWT_REQUIRE(U->rowptr && (U->nnz == 0 || (U->colidx && U->vals)), RWT_ERR_INVALID_ARG,
                 "an upper plan needs pattern and values");
     *LU = *U;   // sizes and type; pointers are replaced by the workspace's
     return rwt_plan_ws(LU, opts, plan_bytes);
@@ -275,7 +275,7 @@ static rwt_status upper_run(const rwt_upper* up, bool transposed, const void* d_
     RWT_REQUIRE(up != nullptr, RWT_ERR_INVALID_ARG, "NULL upper plan");
     const int32_t n = up->U.n;
     RWT_REQUIRE(k >= 0 && k <= up->kmax, RWT_ERR_INVALID_ARG, "k must be 0..kmax");
-    RWT_REQUIRE(k == 0 || (d_B && d_X && ldb >= n && ldx >= n), RWT_ERR_INVALID_ARG,
+    RWT_REQUIRE(k == 0 || n == 0 || (d_B && d_X && ldb >= n && ldx >= n), RWT_ERR_INVALID_ARG,
                 "bad dense blocks");
     if (n == 0 || k == 0) return RWT_OK;
     hipStream_t s = hs(stream);
