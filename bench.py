@@ -48,8 +48,6 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="approximate CPU budget of the oracle baseline")
-    ap.add_argument("--copy-probe", action="store_true",   # kept for scripts; the copy always runs
-                    help="also run a plain 1 GiB device copy (counter scaling for profiles)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the comparison solves (original DAG, forced schedules)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload")
