@@ -18,6 +18,7 @@
 // abandonment penalty, affinities, the invalid-action reward) follow the
 // documentation of rwt_env_step in rwtrsv.h.
 #include "common.hpp"
+#include "levtab.hpp"
 #include "prim.hpp"
 #include "u128.hpp"
 
@@ -156,26 +157,6 @@ __device__ __forceinline__ int32_t stop_of(const EnvMeta& m, int32_t thin, int32
 }
 
 // ---------------------------------------------------------------- init ----
-
-__global__ void k_env_keys_deps(const int32_t* rowptr, int32_t n, uint32_t* keys, int32_t* vals) {
-    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        keys[i] = (uint32_t)(rowptr[i + 1] - rowptr[i] - 1);
-        vals[i] = i;
-    }
-}
-
-__global__ void k_env_keys_level(const int32_t* level, const int32_t* vals, int32_t n,
-                                 uint32_t* keys) {
-    for (int32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x)
-        keys[q] = (uint32_t)level[vals[q]];
-}
-
-__global__ void k_env_ent(const int32_t* rowptr, const int32_t* vals, int32_t n, int2* ent) {
-    for (int32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
-        const int32_t i = vals[q];
-        ent[q] = make_int2(i, rowptr[i + 1] - rowptr[i] - 1);
-    }
-}
 
 __global__ void k_env_levels(const int32_t* lptr_in, const int64_t* cost, int32_t D,
                              int32_t* lptr, int32_t* rows0, int64_t* cost0, int64_t* deps0) {
@@ -733,21 +714,14 @@ extern "C" rwt_status rwt_env_init(const rwt_csr* L, const int32_t* d_level,
                 RWT_ERR_INVALID_ARG, "environment parameters are invalid");
     hipStream_t s = hs(stream);
     RWT_HIP(hipMemcpyAsync(w.prm, h_params, sizeof(rwt_env_params), hipMemcpyHostToDevice, s));
-    const unsigned gb = blocks_for(n, 256, 4096);
     hipLaunchKernelGGL(k_env_levels, dim3(blocks_for((size_t)D + 1, 256, 4096)), dim3(256), 0, s,
                        d_level_ptr, d_cost, D, w.lptr, w.rows0, w.cost0, w.deps0);
     RWT_LAUNCHED();
     hipLaunchKernelGGL(k_env_meta, dim3(1), dim3(256), 0, s, w.meta, d_stats, w.prm, w.rows0,
                        w.cost0, n, D, E, cap);
     RWT_LAUNCHED();
-    hipLaunchKernelGGL(k_env_keys_deps, dim3(gb), dim3(256), 0, s, L->rowptr, n, w.keys, w.vals);
-    RWT_LAUNCHED();
-    RWT_TRY(radix_sort(w.keys, w.vals, w.tkeys, w.tvals, n, bits_for((uint64_t)n), w.rws, s));
-    hipLaunchKernelGGL(k_env_keys_level, dim3(gb), dim3(256), 0, s, d_level, w.vals, n, w.keys);
-    RWT_LAUNCHED();
-    RWT_TRY(radix_sort(w.keys, w.vals, w.tkeys, w.tvals, n, bits_for((uint64_t)D), w.rws, s));
-    hipLaunchKernelGGL(k_env_ent, dim3(gb), dim3(256), 0, s, L->rowptr, w.vals, n, w.ent);
-    RWT_LAUNCHED();
+    RWT_TRY(rows_by_level_and_deps(L->rowptr, d_level, n, D, w.keys, w.vals, w.tkeys, w.tvals,
+                                   w.rws, w.ent, s));
     hipLaunchKernelGGL(k_env_reset, dim3(E), dim3(256), 0, s, w, (const uint8_t*)nullptr, n, D, E,
                        cap);
     RWT_LAUNCHED();

@@ -23,6 +23,7 @@
 // The result equals taking the fewest-rows source and the nearest thin
 // target afresh at every step.
 #include "common.hpp"
+#include "levtab.hpp"
 #include "prim.hpp"
 #include "u128.hpp"
 
@@ -68,26 +69,6 @@ size_t carve_gen(void* base, int32_t n, int32_t D, int32_t ne, GenWs* g) {
     g->st_rows = cv.take<int32_t>(ee * dd);
     g->st_flags = cv.take<uint8_t>(ee * dd);
     return cv.used();
-}
-
-__global__ void k_gen_keys_deps(const int32_t* rowptr, int32_t n, uint32_t* keys, int32_t* vals) {
-    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        keys[i] = (uint32_t)(rowptr[i + 1] - rowptr[i] - 1);
-        vals[i] = i;
-    }
-}
-
-__global__ void k_gen_keys_level(const int32_t* level, const int32_t* vals, int32_t n,
-                                 uint32_t* keys) {
-    for (int32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x)
-        keys[q] = (uint32_t)level[vals[q]];
-}
-
-__global__ void k_gen_ent(const int32_t* rowptr, const int32_t* vals, int32_t n, int2* ent) {
-    for (int32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
-        const int32_t i = vals[q];
-        ent[q] = make_int2(i, rowptr[i + 1] - rowptr[i] - 1);
-    }
 }
 
 // per-level rows and dependencies (cost = 2 deps + rows), and the sort keys
@@ -554,15 +535,8 @@ extern "C" rwt_status rwt_generate(const rwt_csr* L, const int32_t* d_level,
         RWT_LAUNCHED();
         return RWT_OK;
     }
-    const unsigned gb = blocks_for(n, 256, 4096);
-    hipLaunchKernelGGL(k_gen_keys_deps, dim3(gb), dim3(256), 0, s, L->rowptr, n, g.keys, g.vals);
-    RWT_LAUNCHED();
-    RWT_TRY(radix_sort(g.keys, g.vals, g.tkeys, g.tvals, n, bits_for((uint64_t)n), g.rws, s));
-    hipLaunchKernelGGL(k_gen_keys_level, dim3(gb), dim3(256), 0, s, d_level, g.vals, n, g.keys);
-    RWT_LAUNCHED();
-    RWT_TRY(radix_sort(g.keys, g.vals, g.tkeys, g.tvals, n, bits_for((uint64_t)D), g.rws, s));
-    hipLaunchKernelGGL(k_gen_ent, dim3(gb), dim3(256), 0, s, L->rowptr, g.vals, n, g.ent);
-    RWT_LAUNCHED();
+    RWT_TRY(rows_by_level_and_deps(L->rowptr, d_level, n, D, g.keys, g.vals, g.tkeys, g.tvals,
+                                   g.rws, g.ent, s));
     hipLaunchKernelGGL(k_gen_levels, dim3(blocks_for(D, 256, 4096)), dim3(256), 0, s, d_level_ptr,
                        d_cost, D, g.rows0, g.deps0, g.keys, g.vals);
     RWT_LAUNCHED();

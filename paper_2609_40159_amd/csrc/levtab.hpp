@@ -1,0 +1,19 @@
+// The rows of a matrix in (level, dependencies, row) order, shared by the
+// rewrite-list generator and the environment step: the node of a source
+// level with the fewest dependencies (ties to the lower row) is then the
+// first of its unmoved rows in this table.
+#pragma once
+
+#include "common.hpp"
+
+namespace rwt {
+
+// ent[q] = (row, dependency count nnz_i - 1) of the q-th row in (level,
+// dependencies, row) order, from the CSR row pointers and the level of every
+// row (levels below D).  keys/vals/tkeys/tvals [n] and rws (radix_ws(n)
+// bytes) are scratch; two stable radix sorts on the stream.
+rwt_status rows_by_level_and_deps(const int32_t* rowptr, const int32_t* level, int32_t n,
+                                  int32_t D, uint32_t* keys, int32_t* vals, uint32_t* tkeys,
+                                  int32_t* tvals, void* rws, int2* ent, hipStream_t s);
+
+}  // namespace rwt
