@@ -83,6 +83,24 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        const T u = __shfl_xor(v, o);
+        v = u > v ? u : v;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        const T u = __shfl_xor(v, o);
+        v = u < v ? u : v;
+    }
+    return v;
+}
+
 // sum over an aligned group of G lanes (G a power of two <= 64)
 template <typename T>
 __device__ __forceinline__ T group_sum(T v, int G) {

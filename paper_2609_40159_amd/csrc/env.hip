@@ -114,38 +114,6 @@ __device__ __forceinline__ bool meta_ok(const EnvMeta& m, int32_t n, int32_t D, 
     return m.magic == ENV_MAGIC && m.n == n && m.D == D && m.E == E && m.cap == cap;
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_max(T v) {
-    for (int o = WAVE / 2; o > 0; o >>= 1) {
-        const T u = __shfl_xor(v, o);
-        v = u > v ? u : v;
-    }
-    return v;
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_min(T v) {
-    for (int o = WAVE / 2; o > 0; o >>= 1) {
-        const T u = __shfl_xor(v, o);
-        v = u < v ? u : v;
-    }
-    return v;
-}
-
-__device__ __forceinline__ U128 wave_sum128(U128 s) {
-    for (int o = WAVE / 2; o > 0; o >>= 1) {
-        U128 u;
-        u.lo = __shfl_xor(s.lo, o);
-        u.hi = __shfl_xor(s.hi, o);
-        s = u128_add(s, u);
-    }
-    return s;
-}
-
-__device__ __forceinline__ bool thin_of(int32_t r, int64_t c, int64_t cb) {
-    return r > 0 && c < cb;
-}
-
 // episode end, checked after reset and after every step, in this order
 __device__ __forceinline__ int32_t stop_of(const EnvMeta& m, int32_t thin, int32_t moves,
                                            int32_t steps, int32_t levels) {
@@ -184,11 +152,7 @@ __global__ void __launch_bounds__(256) k_env_meta(EnvMeta* meta, const rwt_level
     const double scaled = p.alpha * relax;
     const double factor = 1.0 + scaled;
     const double thr = st->alc * factor;
-    int64_t cb = 0;
-    if (thr > 0.0) {
-        const double b = ceil(thr);
-        cb = b >= 9.0e18 ? INT64_MAX : (int64_t)b;
-    }
+    const int64_t cb = cost_bound(thr);
     uint64_t s1 = 0, s2r = 0;
     U128 s2{0, 0};
     int32_t t0 = 0, ones = 0;

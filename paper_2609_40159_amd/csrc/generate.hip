@@ -109,19 +109,6 @@ struct GenArgs {
     int64_t* out_deps;
 };
 
-// A level cost c is an integer below 2^32, exact in double, so
-// (double)c < thr holds exactly when c < ceil(thr): the comparison is done
-// on integers against that bound.
-__device__ __forceinline__ int64_t cost_bound(double thr) {
-    if (!(thr > 0.0)) return 0;
-    const double b = ceil(thr);
-    return b >= 9.0e18 ? INT64_MAX : (int64_t)b;
-}
-
-__device__ __forceinline__ bool thin_of(int32_t r, int64_t c, int64_t cb) {
-    return r > 0 && c < cb;
-}
-
 // The stop test thin / T0 < thin_stop (double division) is monotone in the
 // thin count, which only falls: it holds exactly when thin <= the largest
 // k in [0, T0] that passes it (-1 when none does).
@@ -367,12 +354,7 @@ __global__ void __launch_bounds__(WAVE) k_gen_env(GenArgs a) {
     ne = wave_sum(ne);
     th = wave_sum(th);
     s1 = wave_sum(s1);
-    for (int o = WAVE / 2; o > 0; o >>= 1) {
-        U128 u;
-        u.lo = __shfl_xor(s2.lo, o);
-        u.hi = __shfl_xor(s2.hi, o);
-        s2 = u128_add(s2, u);
-    }
+    s2 = wave_sum128(s2);
     if (lane == 0) {
         rwt_gen_result r;
         r.moves = moves;

@@ -76,6 +76,17 @@ __host__ __device__ inline double u128_to_double(U128 v) {
     return ldexp((double)top, 64 - s);
 }
 
+// sum over the 64 lanes of a wave
+__device__ inline U128 wave_sum128(U128 s) {
+    for (int o = 32; o > 0; o >>= 1) {
+        U128 u;
+        u.lo = __shfl_xor(s.lo, o);
+        u.hi = __shfl_xor(s.hi, o);
+        s = u128_add(s, u);
+    }
+    return s;
+}
+
 __host__ __device__ inline double cv_exact(uint64_t D, uint64_t S1, U128 S2) {
     if (D <= 1 || S1 == 0) return 0.0;
     U128 a = u128_mul_small(S2, D);
