@@ -10,21 +10,6 @@ namespace rwt {
 
 namespace {
 
-template <typename T>
-__device__ __forceinline__ T mul_rn(T a, T b) {
-#pragma clang fp contract(off)
-    return a * b;
-}
-template <typename T>
-__device__ __forceinline__ T sub_rn(T a, T b) {
-#pragma clang fp contract(off)
-    return a - b;
-}
-template <typename T>
-__device__ __forceinline__ T add_rn(T a, T b) {
-#pragma clang fp contract(off)
-    return a + b;
-}
 
 __global__ void k_ct_keys(const int32_t* ccol, int64_t nc, uint32_t* keys, int32_t* vals) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

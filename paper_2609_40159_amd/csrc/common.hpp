@@ -83,6 +83,24 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
+// Value arithmetic rounded one operation at a time (no contraction into
+// fused multiply-adds), so that results follow a fixed rounding order.
+template <typename T>
+__device__ __forceinline__ T mul_rn(T a, T b) {
+#pragma clang fp contract(off)
+    return a * b;
+}
+template <typename T>
+__device__ __forceinline__ T sub_rn(T a, T b) {
+#pragma clang fp contract(off)
+    return a - b;
+}
+template <typename T>
+__device__ __forceinline__ T add_rn(T a, T b) {
+#pragma clang fp contract(off)
+    return a + b;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_max(T v) {
     for (int o = WAVE / 2; o > 0; o >>= 1) {

@@ -117,17 +117,6 @@ __device__ __forceinline__ int lower_bound_lds(const int32_t* a, int len, int32_
     return lo;
 }
 
-// Value arithmetic of the recurrence, each operation rounded on its own.
-template <typename T>
-__device__ __forceinline__ T mul_rn(T a, T b) {
-#pragma clang fp contract(off)
-    return a * b;
-}
-template <typename T>
-__device__ __forceinline__ T sub_rn(T a, T b) {
-#pragma clang fp contract(off)
-    return a - b;
-}
 
 // Rewrite one row with one wave.  Returns false on capacity overflow.
 // QMODE 0: symbolic or numeric rewrite of one matrix; QMODE 1: only the new
@@ -359,6 +348,30 @@ __global__ void __launch_bounds__((TIER == 1 ? RW_WAVES1 : RW_WAVES2) * WAVE) k_
     }
 }
 
+// A wave's buffers at capacity cap (value size S) carved from a workspace
+// slab, 8-byte aligned.
+__device__ inline Bufs slab_bufs(unsigned char* base, int64_t cap, int S) {
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        unsigned char* p = base + off;
+        off += (bytes + 7) & ~int64_t(7);
+        return p;
+    };
+    Bufs bf;
+    for (int i = 0; i < 2; ++i) {
+        bf.acol[i] = reinterpret_cast<int32_t*>(take(cap * 4));
+        bf.aval[i] = reinterpret_cast<double*>(take(cap * S));
+        bf.aelig[i] = take(cap);
+    }
+    bf.bcol = reinterpret_cast<int32_t*>(take(cap * 4));
+    bf.bval = reinterpret_cast<double*>(take(cap * S));
+    bf.nd = reinterpret_cast<int32_t*>(take((cap + 1) * 4));
+    bf.bdup = take(cap);
+    bf.cap = (int32_t)cap;
+    bf.capb = (int32_t)cap;
+    return bf;
+}
+
 // Rows that overflowed the LDS capacity: same algorithm, buffers in a
 // workspace slab large enough for any row (n + 1 entries).
 template <typename T, bool NUMERIC>
@@ -366,26 +379,7 @@ __global__ void __launch_bounds__(WAVE) k_rewrite_slab(RwArgs a) {
     const int32_t cnt = a.ctrl[5];
     const int S = sizeof(T);
     for (int32_t s = blockIdx.x; s < cnt; s += gridDim.x) {
-        unsigned char* base = a.slab + (int64_t)blockIdx.x * a.slab_stride;
-        const int64_t cap = a.slab_cap;
-        int64_t off = 0;
-        auto take = [&](int64_t bytes) {
-            unsigned char* p = base + off;
-            off += (bytes + 7) & ~int64_t(7);
-            return p;
-        };
-        Bufs bf;
-        for (int i = 0; i < 2; ++i) {
-            bf.acol[i] = reinterpret_cast<int32_t*>(take(cap * 4));
-            bf.aval[i] = reinterpret_cast<double*>(take(cap * S));
-            bf.aelig[i] = take(cap);
-        }
-        bf.bcol = reinterpret_cast<int32_t*>(take(cap * 4));
-        bf.bval = reinterpret_cast<double*>(take(cap * S));
-        bf.nd = reinterpret_cast<int32_t*>(take((cap + 1) * 4));
-        bf.bdup = take(cap);
-        bf.cap = (int32_t)cap;
-        bf.capb = (int32_t)cap;
+        const Bufs bf = slab_bufs(a.slab + (int64_t)blockIdx.x * a.slab_stride, a.slab_cap, S);
         const int32_t q = a.ovf2[s];
         if (!rewrite_row<T, NUMERIC>(a, q, bf) && lane_id() == 0) atomicExch(&a.ctrl[3], 1);
     }
@@ -664,26 +658,7 @@ __global__ void __launch_bounds__(WAVE) k_batch_rw_slab(BatchRwArgsDev ba) {
     const int32_t cnt = ba.ctrl[7];
     const int S = 8;
     for (int32_t s = blockIdx.x; s < cnt; s += gridDim.x) {
-        unsigned char* base = ba.slab + (int64_t)blockIdx.x * ba.slab_stride;
-        const int64_t cap = ba.slab_cap;
-        int64_t off = 0;
-        auto take = [&](int64_t bytes) {
-            unsigned char* p = base + off;
-            off += (bytes + 7) & ~int64_t(7);
-            return p;
-        };
-        Bufs bf;
-        for (int i = 0; i < 2; ++i) {
-            bf.acol[i] = reinterpret_cast<int32_t*>(take(cap * 4));
-            bf.aval[i] = reinterpret_cast<double*>(take(cap * S));
-            bf.aelig[i] = take(cap);
-        }
-        bf.bcol = reinterpret_cast<int32_t*>(take(cap * 4));
-        bf.bval = reinterpret_cast<double*>(take(cap * S));
-        bf.nd = reinterpret_cast<int32_t*>(take((cap + 1) * 4));
-        bf.bdup = take(cap);
-        bf.cap = (int32_t)cap;
-        bf.capb = (int32_t)cap;
+        const Bufs bf = slab_bufs(ba.slab + (int64_t)blockIdx.x * ba.slab_stride, ba.slab_cap, S);
         const int32_t q = ba.ovf2[s];
         const RwArgs a = batch_row_args(ba, q);
         if (!rewrite_row<double, false, QMODE>(a, q, bf) && lane_id() == 0) atomicExch(&ba.ctrl[3], 1);
