@@ -557,6 +557,14 @@ rwt_status rwt_env_step(int32_t n, int32_t num_levels, int32_t num_env, int32_t 
 rwt_status rwt_env_observe(int32_t n, int32_t num_levels, int32_t num_env, int32_t cap,
                            float* d_obs_level, float* d_obs_global, uint8_t* d_mask,
                            const void* d_ws, size_t ws_bytes, rwt_stream_t stream);
+/* rwt_env_step followed by rwt_env_observe, in one launch: the same
+ * results, moves, observation and mask as the two calls (observation
+ * outputs nullable). */
+rwt_status rwt_env_step_observe(int32_t n, int32_t num_levels, int32_t num_env, int32_t cap,
+                                const int32_t* d_action, rwt_env_result* d_res,
+                                int32_t* d_mv_row, int32_t* d_mv_src, int32_t* d_mv_tgt,
+                                float* d_obs_level, float* d_obs_global, uint8_t* d_mask,
+                                void* d_ws, size_t ws_bytes, rwt_stream_t stream);
 /* Per-level state d_cost/d_rows/d_deps[e*D + l] (device, each nullable). */
 rwt_status rwt_env_levels(int32_t n, int32_t num_levels, int32_t num_env, int32_t cap,
                           int64_t* d_cost, int32_t* d_rows, int64_t* d_deps, const void* d_ws,

@@ -188,6 +188,7 @@ SIGNATURES = {
                                P, SZ, P]),
     "rwt_env_reset": (C.c_int, [I32, I32, I32, I32, P, P, SZ, P]),
     "rwt_env_step": (C.c_int, [I32, I32, I32, I32, P, P, P, P, P, P, SZ, P]),
+    "rwt_env_step_observe": (C.c_int, [I32, I32, I32, I32, P, P, P, P, P, P, P, P, P, SZ, P]),
     "rwt_env_observe": (C.c_int, [I32, I32, I32, I32, P, P, P, P, SZ, P]),
     "rwt_env_levels": (C.c_int, [I32, I32, I32, I32, P, P, P, P, SZ, P]),
 }

@@ -576,13 +576,22 @@ class Env:
         check(self.lib.rwt_env_reset(*self._dims(), _ptr(w), _ptr(self.ws), self.ws.numel(),
                                      _stream()))
 
-    def step(self, actions) -> EnvStep:
+    def step(self, actions, observe: bool = False) -> EnvStep:
+        """Apply one action per environment; with observe=True the
+        observation and mask of the new state are written in the same
+        launch (obs_level / obs_global / mask)."""
         a = torch.as_tensor(actions, dtype=torch.int32).to(self.device).contiguous()
         if a.numel() != self.E:
             raise ValueError("one action per environment")
-        check(self.lib.rwt_env_step(*self._dims(), _ptr(a), _ptr(self._res), _ptr(self.mv_row),
-                                    _ptr(self.mv_src), _ptr(self.mv_tgt), _ptr(self.ws),
-                                    self.ws.numel(), _stream()))
+        if observe:
+            check(self.lib.rwt_env_step_observe(
+                *self._dims(), _ptr(a), _ptr(self._res), _ptr(self.mv_row), _ptr(self.mv_src),
+                _ptr(self.mv_tgt), _ptr(self.obs_level), _ptr(self.obs_global), _ptr(self.mask),
+                _ptr(self.ws), self.ws.numel(), _stream()))
+        else:
+            check(self.lib.rwt_env_step(*self._dims(), _ptr(a), _ptr(self._res),
+                                        _ptr(self.mv_row), _ptr(self.mv_src), _ptr(self.mv_tgt),
+                                        _ptr(self.ws), self.ws.numel(), _stream()))
         self._last_actions = a            # keep alive until the launch ran
         return EnvStep(self._res, self.E)
 

@@ -269,11 +269,10 @@ __device__ __forceinline__ void fill_result(rwt_env_result& r, const EnvHdr& h, 
     r.cv_rows = h.cv_rows;
 }
 
-__global__ void __launch_bounds__(WAVE) k_env_step(EnvWs w, const int32_t* action, int32_t n,
-                                                   int32_t D, int32_t E, int32_t cap,
-                                                   rwt_env_result* res, int32_t* mv_row,
-                                                   int32_t* mv_src, int32_t* mv_tgt) {
-    const int32_t e = blockIdx.x;
+// One environment's step, run by one wave (no workgroup barrier inside).
+__device__ void env_step_body(const EnvWs& w, const int32_t* action, int32_t n, int32_t D,
+                              int32_t E, int32_t cap, rwt_env_result* res, int32_t* mv_row,
+                              int32_t* mv_src, int32_t* mv_tgt, int32_t e) {
     const int lane = lane_id();
     const EnvMeta m = *w.meta;
     rwt_env_result r{};
@@ -534,11 +533,11 @@ __device__ __forceinline__ T block_max256(T v, T* sm) {
     return r;
 }
 
-__global__ void __launch_bounds__(256) k_env_observe(EnvWs w, int32_t n, int32_t D, int32_t E,
-                                                     int32_t cap, float* obs_level,
-                                                     float* obs_global, uint8_t* mask) {
-    __shared__ int64_t s_red[4];
-    const int32_t e = blockIdx.x;
+// One environment's observation and mask, run by a whole workgroup of 256
+// (its early returns depend only on values uniform over the workgroup).
+__device__ void env_observe_body(const EnvWs& w, int32_t n, int32_t D, int32_t E, int32_t cap,
+                                 float* obs_level, float* obs_global, uint8_t* mask, int32_t e,
+                                 int64_t* s_red) {
     const EnvMeta m = *w.meta;
     if (!meta_ok(m, n, D, E, cap)) return;
     const rwt_env_params& p = m.prm;
@@ -611,6 +610,35 @@ __global__ void __launch_bounds__(256) k_env_observe(EnvWs w, int32_t n, int32_t
         if (threadIdx.x == 0) mk[D - 1 - (int32_t)(bestk & 0xffffffff)] = 1;
         last = bestk;
     }
+}
+
+__global__ void __launch_bounds__(WAVE) k_env_step(EnvWs w, const int32_t* action, int32_t n,
+                                                   int32_t D, int32_t E, int32_t cap,
+                                                   rwt_env_result* res, int32_t* mv_row,
+                                                   int32_t* mv_src, int32_t* mv_tgt) {
+    env_step_body(w, action, n, D, E, cap, res, mv_row, mv_src, mv_tgt, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_env_observe(EnvWs w, int32_t n, int32_t D, int32_t E,
+                                                     int32_t cap, float* obs_level,
+                                                     float* obs_global, uint8_t* mask) {
+    __shared__ int64_t s_red[4];
+    env_observe_body(w, n, D, E, cap, obs_level, obs_global, mask, blockIdx.x, s_red);
+}
+
+// The step by the first wave, then the observation of the new state by the
+// whole workgroup: the barrier makes the step's writes visible to it.
+__global__ void __launch_bounds__(256) k_env_step_observe(EnvWs w, const int32_t* action,
+                                                          int32_t n, int32_t D, int32_t E,
+                                                          int32_t cap, rwt_env_result* res,
+                                                          int32_t* mv_row, int32_t* mv_src,
+                                                          int32_t* mv_tgt, float* obs_level,
+                                                          float* obs_global, uint8_t* mask) {
+    __shared__ int64_t s_red[4];
+    if (threadIdx.x < WAVE)
+        env_step_body(w, action, n, D, E, cap, res, mv_row, mv_src, mv_tgt, blockIdx.x);
+    __syncthreads();
+    env_observe_body(w, n, D, E, cap, obs_level, obs_global, mask, blockIdx.x, s_red);
 }
 
 __global__ void k_env_read(EnvWs w, int32_t n, int32_t D, int32_t E, int32_t cap, int64_t* cost,
@@ -715,6 +743,24 @@ extern "C" rwt_status rwt_env_step(int32_t n, int32_t num_levels, int32_t num_en
                 "NULL action, result or move arrays");
     hipLaunchKernelGGL(k_env_step, dim3(num_env), dim3(WAVE), 0, hs(stream), w, d_action, n,
                        num_levels, num_env, cap, d_res, d_mv_row, d_mv_src, d_mv_tgt);
+    RWT_LAUNCHED();
+    return RWT_OK;
+}
+
+extern "C" rwt_status rwt_env_step_observe(int32_t n, int32_t num_levels, int32_t num_env,
+                                           int32_t cap, const int32_t* d_action,
+                                           rwt_env_result* d_res, int32_t* d_mv_row,
+                                           int32_t* d_mv_src, int32_t* d_mv_tgt,
+                                           float* d_obs_level, float* d_obs_global,
+                                           uint8_t* d_mask, void* d_ws, size_t ws_bytes,
+                                           rwt_stream_t stream) {
+    EnvWs w;
+    RWT_TRY(check_ws(n, num_levels, num_env, cap, d_ws, ws_bytes, &w));
+    RWT_REQUIRE(d_action && d_res && d_mv_row && d_mv_src && d_mv_tgt, RWT_ERR_INVALID_ARG,
+                "NULL action, result or move arrays");
+    hipLaunchKernelGGL(k_env_step_observe, dim3(num_env), dim3(256), 0, hs(stream), w, d_action, n,
+                       num_levels, num_env, cap, d_res, d_mv_row, d_mv_src, d_mv_tgt, d_obs_level,
+                       d_obs_global, d_mask);
     RWT_LAUNCHED();
     return RWT_OK;
 }

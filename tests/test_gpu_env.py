@@ -207,3 +207,35 @@ def test_env_capacity_one_and_single_environment():
     assert any(r["done"] == 2 for r in res)
     print("env parity: one environment", flush=True)
     run(synth.power_law(3000, 5), 1, 80, dict(search_window=3), seed=22)
+
+
+def test_env_step_observe_equals_separate_calls():
+    """The fused step-and-observe launch gives bit for bit the results, moves,
+    level table, observation and mask of a step followed by an observe."""
+    from paper_2609_40159_amd.api import Env, analyze
+    L = synth.power_law(20000, 27)
+    G = to_gpu(L)
+    info = analyze(G)
+    E = 48
+    kw = dict(max_dist=25, stall_steps=3, keep_top=4, search_window=4)
+    A = Env(G, info, E, cap=300, **kw)
+    B = Env(G, info, E, cap=300, **kw)
+    w = torch.rand((E, info.num_levels), generator=torch.Generator().manual_seed(5)).to(DEV)
+    _, _, mask = A.observe()
+    B.observe()
+    print("env fused step+observe: 120 steps", flush=True)
+    for k in range(120):
+        act = (w * A.mask).argmax(dim=1).to(torch.int32)
+        if k % 7 == 3:
+            act[::5] = -1                      # some invalid actions
+        ra = A.step(act)
+        A.observe()
+        rb = B.step(act, observe=True)
+        torch.cuda.synchronize()
+        assert torch.equal(ra.raw, rb.raw), k
+        assert torch.equal(A.obs_level, B.obs_level) and torch.equal(A.obs_global, B.obs_global), k
+        assert torch.equal(A.mask, B.mask), k
+    ca, rwa, da = A.levels()
+    cb, rwb, db = B.levels()
+    assert torch.equal(ca, cb) and torch.equal(rwa, rwb) and torch.equal(da, db)
+    assert torch.equal(A.mv_row, B.mv_row) and torch.equal(A.mv_tgt, B.mv_tgt)
