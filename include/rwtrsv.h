@@ -612,7 +612,9 @@ typedef struct {
     const void* B;        /* device, k columns (ldb) */
     void* X;              /* device, k columns (ldx) */
     int32_t k;
-    int32_t block_rows;   /* solve row-block size; 0: autotuned at creation */
+    int32_t block_rows;   /* solve row-block size; 0: the largest that fits the LDS
+                             budget (fewer level steps for the solve and the
+                             candidate chains that share its blocks) */
     int64_t ldb;
     int64_t ldx;
 } rwt_batch_matrix;

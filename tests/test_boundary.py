@@ -121,3 +121,37 @@ def test_oracle_and_gpu_path_are_independent():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
                 assert "oracle.c" not in txt and "orc_" not in txt, f
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every structure the Python binding declares has the size and field
+    offsets of its C definition in include/rwtrsv.h (compiled as C99)."""
+    import ctypes as C
+    import shutil
+    import subprocess
+    from paper_2609_40159_amd import _lib
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    pairs = {"Csr": "rwt_csr", "LevelStats": "rwt_level_stats", "PlanOpts": "rwt_plan_opts",
+             "PlanInfo": "rwt_plan_info", "GenParams": "rwt_gen_params",
+             "GenResult": "rwt_gen_result", "EnvParams": "rwt_env_params",
+             "EnvResult": "rwt_env_result", "BatchMatrix": "rwt_batch_matrix",
+             "BatchDesc": "rwt_batch_desc", "CandStats": "rwt_cand_stats",
+             "BatchInfo": "rwt_batch_info"}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rwtrsv.h"', 'int main(void) {']
+    want = []
+    for py, c in pairs.items():
+        st = getattr(_lib, py)
+        lines.append(f'    printf("%zu\\n", sizeof({c}));')
+        want.append(C.sizeof(st))
+        for f, _ in st._fields_:
+            lines.append(f'    printf("%zu\\n", offsetof({c}, {f}));')
+            want.append(getattr(st, f).offset)
+    lines += ['    return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Werror", "-I", inc, str(src), "-o", str(exe)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert got == want
