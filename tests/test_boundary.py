@@ -155,3 +155,30 @@ def test_struct_layouts_match_header(tmp_path):
     subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Werror", "-I", inc, str(src), "-o", str(exe)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     assert got == want
+
+
+def test_python_signatures_match_header_prototypes():
+    """Each ctypes declaration has the argument count of the C prototype,
+    pointer arguments where the prototype has pointers, and the right
+    return kind (status int, size_t, double pointer...)."""
+    import ctypes as C
+    from paper_2609_40159_amd import _lib
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    protos = dict()
+    for m in re.finditer(r"\b([A-Za-z_][\w ]*?\**)\s*\b(rwt_\w+)\s*\(([^;{]*?)\)\s*;", text):
+        ret, name, args = m.group(1).strip(), m.group(2), m.group(3).strip()
+        params = [] if args in ("", "void") else [a.strip() for a in args.split(",")]
+        protos[name] = (ret, params)
+    assert sorted(protos) == sorted(_lib.SIGNATURES)
+    for name, (restype, argtypes) in _lib.SIGNATURES.items():
+        ret, params = protos[name]
+        assert len(params) == len(argtypes), (name, params, argtypes)
+        for p, t in zip(params, argtypes):
+            is_ptr = "*" in p or p.split()[0] in ("rwt_stream_t",)
+            ctypes_ptr = t is C.c_void_p or t is C.c_char_p or isinstance(t, type(C.POINTER(C.c_int)))
+            assert is_ptr == bool(ctypes_ptr), (name, p, t)
+        if ret == "rwt_status":
+            assert restype is C.c_int, name
+        elif ret == "size_t":
+            assert restype is C.c_size_t, name
