@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--no-generator", action="store_true",
                     help="skip the rewrite-list generator section")
     ap.add_argument("--no-env", action="store_true", help="skip the environment-step section")
+    ap.add_argument("--stage-outside", default="auto", choices=["auto", "on", "off"],
+                    help="main solve plan: helper waves prefetch outside x values (auto: timed "
+                         "at plan creation; fix it for counter runs, whose timings are distorted)")
     ap.add_argument("--env-count", type=int, default=1024, help="environments stepped together")
     ap.add_argument("--env-steps", type=int, default=200, help="timed environment steps")
     ap.add_argument("--batch-count", type=int, default=256, help="matrices in the batch")
@@ -103,8 +106,9 @@ def src_hash(files):
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel_key: str, srchash: str):
-    """HBM bytes per launch from committed counter runs, if they are current."""
+def load_traffic(kernel_key: str, srchash: str, stage: str):
+    """HBM bytes per launch from committed counter runs, if they are current
+    (same solve sources, same staging of outside values)."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
@@ -113,7 +117,7 @@ def load_traffic(kernel_key: str, srchash: str):
     except (OSError, ValueError):
         return None
     e = d.get(kernel_key)
-    if not e or e.get("src_hash") != srchash:
+    if not e or e.get("src_hash") != srchash or e.get("stage_outside") != stage:
         return None
     return e.get("hbm_bytes_per_launch")
 
@@ -596,7 +600,7 @@ def main():
     Bp = rw.numeric(vals, B)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plan = Plan(rw.Lp, algo="auto", kmax=k)
+    plan = Plan(rw.Lp, algo="auto", kmax=k, stage_outside=args.stage_outside)
     torch.cuda.synchronize()
     pre["plan_ms"] = (time.perf_counter() - t0) * 1e3
     pinfo = plan.info
@@ -791,7 +795,8 @@ def main():
         roofs[ph_name] = {
             "bound": "hbm", "kernel": kname, "achieved": achieved, "peak": PEAK_HBM_GBS,
             "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-            "traffic": load_traffic(f"{args.workload}:{args.dtype}:{kname}", srch),
+            "traffic": load_traffic(f"{args.workload}:{args.dtype}:{kname}", srch,
+                                    pinfo["stage_outside"]),
             "algorithmic_bytes_per_launch": nbytes, "avg_launch_ms": ms[ph_name],
             "latency_floor_note": f"{Dp} dependent levels on the critical path"}
     dom = "fwd" if ms["fwd"] >= ms["bwd"] else "bwd"
@@ -836,7 +841,8 @@ def main():
                       "grad_vals": b_gv / ms["grad_vals"] / 1e6},
         "plan": {"rewritten": {kk: pinfo[kk] for kk in ("algo_fwd", "algo_bwd", "block_rows",
                                                           "lanes_per_row", "narrow_rows", "grid",
-                                                          "tuned_ms_level", "tuned_ms_syncfree")},
+                                                          "stage_outside", "tuned_ms_level",
+                                                          "tuned_ms_syncfree")},
                  "original": {kk: oinfo[kk] for kk in ("algo_fwd", "tuned_ms_level",
                                                          "tuned_ms_syncfree")}},
         "compare": cmp,

@@ -185,8 +185,9 @@ rwt_status rwt_rewrite_numeric(const rwt_csr* L, const int32_t* d_level,
  *                     concurrently (each chain is a full sync-free solve);
  *   RWT_ALGO_AUTO     autotuned: both candidates are timed on the plan's
  *                     matrix and the faster kept.
- * Unless fixed by the options, the sync-free block size and RHS chunk are
- * chosen by timing solves on the plan's own matrix (min(kmax, 64) columns).
+ * Unless fixed by the options, the sync-free block size, RHS chunk and
+ * staging of outside values are chosen by timing solves on the plan's own
+ * matrix (min(kmax, 64) columns).
  * The plan keeps pointers to L (pattern and values): the caller keeps them
  * alive and may change the values between solves.  The plan's device
  * state lives in the caller's workspace (rwt_plan_ws bytes).
@@ -202,6 +203,9 @@ typedef struct {
     int32_t watchdog_ms;      /* bound on any device wait (0: 5000 ms) */
     int32_t rhs_chunk;        /* sync-free columns per chain: 0 choose, else 1..4 */
     int32_t tune_cols;        /* columns the autotuner solves with: 0 min(kmax, 64), else 1..kmax */
+    int32_t stage_outside;    /* sync-free, whether the helper waves prefetch the x values a block
+                                 reads from earlier blocks: 0 choose by timing both, 1 yes, 2 no
+                                 (the solving lanes then load them when they need them) */
 } rwt_plan_opts;
 
 typedef struct rwt_plan rwt_plan;
@@ -216,6 +220,7 @@ typedef struct {
     int32_t num_blocks;
     int32_t grid;             /* workgroups of the persistent launches */
     int32_t rhs_chunk;        /* sync-free right-hand-side columns per chain */
+    int32_t stage_outside;    /* 1 or 2, as in rwt_plan_opts: what the plan uses */
     double tuned_ms_level;    /* autotuner measurements (0 when not tuned) */
     double tuned_ms_syncfree;
 } rwt_plan_info;

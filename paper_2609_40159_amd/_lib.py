@@ -51,14 +51,16 @@ class LevelStats(C.Structure):
 class PlanOpts(C.Structure):
     _fields_ = [("algo", C.c_int32), ("block_rows", C.c_int32), ("lanes_per_row", C.c_int32),
                 ("narrow_rows", C.c_int32), ("kmax", C.c_int32), ("watchdog_ms", C.c_int32),
-                ("rhs_chunk", C.c_int32), ("tune_cols", C.c_int32)]
+                ("rhs_chunk", C.c_int32), ("tune_cols", C.c_int32),
+                ("stage_outside", C.c_int32)]
 
 
 class PlanInfo(C.Structure):
     _fields_ = [("stats", LevelStats), ("algo_fwd", C.c_int32), ("algo_bwd", C.c_int32),
                 ("block_rows", C.c_int32), ("lanes_per_row", C.c_int32),
                 ("narrow_rows", C.c_int32), ("num_blocks", C.c_int32), ("grid", C.c_int32),
-                ("rhs_chunk", C.c_int32), ("tuned_ms_level", C.c_double),
+                ("rhs_chunk", C.c_int32), ("stage_outside", C.c_int32),
+                ("tuned_ms_level", C.c_double),
                 ("tuned_ms_syncfree", C.c_double)]
 
 

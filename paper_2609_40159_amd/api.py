@@ -223,12 +223,18 @@ def rewrite(L: CSRMatrix, level: torch.Tensor, rows, targets=None,
     return rw.result(Bp)
 
 
+# sync-free solves: whether helper waves prefetch the x values a row block
+# reads from earlier blocks ("auto": the plan times both)
+STAGE = {"auto": 0, "on": 1, "off": 2}
+STAGE_NAME = {1: "on", 2: "off"}
+
+
 class Plan:
     """Analysis + schedule of one matrix; solves L X = B and L^T Y = G."""
 
     def __init__(self, L: CSRMatrix, algo: str = "auto", kmax: int = 1, block_rows: int = 0,
                  lanes_per_row: int = 0, narrow_rows: int = -1, watchdog_ms: int = 0,
-                 rhs_chunk: int = 0):
+                 rhs_chunk: int = 0, stage_outside: str = "auto"):
         lib = _lib.load()
         self.L = L
         self._lib = lib
@@ -240,6 +246,7 @@ class Plan:
         o.kmax = kmax
         o.watchdog_ms = watchdog_ms
         o.rhs_chunk = rhs_chunk
+        o.stage_outside = STAGE[stage_outside]
         self.opts = o
         sz = C.c_size_t(0)
         check(lib.rwt_plan_ws(C.byref(L.view()), C.byref(o), C.byref(sz)))
@@ -263,6 +270,7 @@ class Plan:
         d = {f: getattr(inf, f) for f, _ in inf._fields_ if f not in ("stats", "pad_")}
         d["algo_fwd"] = _lib.ALGO_NAME[d["algo_fwd"]]
         d["algo_bwd"] = _lib.ALGO_NAME[d["algo_bwd"]]
+        d["stage_outside"] = STAGE_NAME[d["stage_outside"]]
         d["stats"] = inf.stats.as_dict()
         return d
 
@@ -317,7 +325,7 @@ class UpperPlan(Plan):
 
     def __init__(self, U: CSRMatrix, algo: str = "auto", kmax: int = 1, block_rows: int = 0,
                  lanes_per_row: int = 0, narrow_rows: int = -1, watchdog_ms: int = 0,
-                 rhs_chunk: int = 0):
+                 rhs_chunk: int = 0, stage_outside: str = "auto"):
         lib = _lib.load()
         self.L = U
         self._lib = lib
@@ -329,6 +337,7 @@ class UpperPlan(Plan):
         o.kmax = kmax
         o.watchdog_ms = watchdog_ms
         o.rhs_chunk = rhs_chunk
+        o.stage_outside = STAGE[stage_outside]
         self.opts = o
         sz = C.c_size_t(0)
         check(lib.rwt_upper_ws(C.byref(U.view()), C.byref(o), C.byref(sz)))
@@ -352,6 +361,7 @@ class UpperPlan(Plan):
         d = {f: getattr(inf, f) for f, _ in inf._fields_ if f not in ("stats", "pad_")}
         d["algo_fwd"] = _lib.ALGO_NAME[d["algo_fwd"]]
         d["algo_bwd"] = _lib.ALGO_NAME[d["algo_bwd"]]
+        d["stage_outside"] = STAGE_NAME[d["stage_outside"]]
         d["stats"] = inf.stats.as_dict()
         return d
 

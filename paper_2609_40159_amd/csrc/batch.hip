@@ -582,6 +582,7 @@ __global__ void __launch_bounds__(BT_THREADS) k_batch_main(BatchKArgs a) {
             b.ns = M.blk_step[tk.z + 1] - b.sb;
             b.k = min(M.kc, M.k - q0);
             b.lanes = M.lanes;
+            b.stage_x = 0;   // read by the staged body only
             b.ldb = M.ldb;
             b.ldx = M.ldx;
             b.colidx = M.colidx;
@@ -788,6 +789,7 @@ rwt_plan_opts batch_plan_opts(const rwt_batch_desc* d, const rwt_batch_matrix& m
     o.kmax = m.k > 0 ? m.k : 1;
     o.rhs_chunk = 1;   // one column per solve chain: parallel chains to spare
     o.tune_cols = 1;
+    o.stage_outside = 1;   // no timing solves at creation
     o.narrow_rows = -1;
     o.watchdog_ms = d->watchdog_ms;
     return o;

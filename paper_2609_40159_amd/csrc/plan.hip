@@ -231,6 +231,8 @@ rwt_status check_opts(const rwt_csr* L, const rwt_plan_opts* o) {
     RWT_REQUIRE(o->rhs_chunk >= 0 && o->rhs_chunk <= 4, RWT_ERR_INVALID_ARG,
                 "rhs_chunk must be 0..4");
     RWT_REQUIRE(o->tune_cols >= 0, RWT_ERR_INVALID_ARG, "negative tune_cols");
+    RWT_REQUIRE(o->stage_outside >= 0 && o->stage_outside <= 2, RWT_ERR_INVALID_ARG,
+                "stage_outside must be 0..2");
     return RWT_OK;
 }
 
@@ -255,6 +257,7 @@ SolveArgs make_args(const rwt_plan* p) {
     a.blk_step = p->blk_step;
     a.lanes = p->lanes;
     a.kc = p->kc;
+    a.stage_x = p->stage_x == 1;
     a.ctrl = p->ctrl;
     a.ticks = watchdog_ticks(p->opts.watchdog_ms);
     return a;
@@ -506,7 +509,9 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
     const bool tune_sf = opts->algo != RWT_ALGO_LEVEL &&
                          (kcs.size() > 1 ||
                           block_candidates(*opts, L->dt, n, kcs.front(), lanes).size() > 1);
-    if (tune_algo || tune_sf) {
+    const bool tune_stage = opts->algo != RWT_ALGO_LEVEL && opts->stage_outside == 0 && n > 0;
+    p->stage_x = opts->stage_outside == 2 ? 2 : 1;
+    if (tune_algo || tune_sf || tune_stage) {
         const int64_t nf = (int64_t)n * kt;
         const unsigned g = blocks_for(nf, 256, 8192);
         if (L->dt == RWT_F64)
@@ -515,6 +520,8 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
         else
             hipLaunchKernelGGL(k_fill_val<float>, dim3(g), dim3(256), 0, s,
                                static_cast<float*>(p->xtmp), nf, 1.0f);
+    }
+    if (tune_algo || tune_sf) {
         // per chunk, candidates run from large blocks to small; stop after
         // two in a row that are more than 10% slower than the best so far
         double best_sf = 1e30;
@@ -552,6 +559,18 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
         }
     }
     if ((st = build_blocks(R)) != RWT_OK) return fail(st);
+    // staging of outside x values in the helper waves (on or off): both
+    // timed on the chosen schedule, alternately, best of three each
+    if (tune_stage && p->nblocks > 1 && (p->fwd == Algo::SyncFree || p->bwd == Algo::SyncFree)) {
+        double t[2] = {1e30, 1e30};
+        (void)time_solve(p, Algo::SyncFree, kt, s, 1);   // warm-up
+        for (int r = 0; r < 3; ++r)
+            for (int m = 0; m < 2; ++m) {
+                p->stage_x = m + 1;
+                t[m] = std::min(t[m], time_solve(p, Algo::SyncFree, kt, s, 1));
+            }
+        p->stage_x = t[1] < t[0] ? 2 : 1;
+    }
     if (hipStreamSynchronize(s) != hipSuccess) {
         set_hip_error(hipGetLastError(), "plan creation");
         return fail(RWT_ERR_HIP);
@@ -571,6 +590,7 @@ extern "C" rwt_status rwt_plan_get_info(const rwt_plan* p, rwt_plan_info* h) {
     h->narrow_rows = p->opts.narrow_rows;
     h->num_blocks = p->nblocks;
     h->rhs_chunk = p->kc;
+    h->stage_outside = p->stage_x;
     h->grid = (int32_t)solve_grid(p->fwd, p->L.dt, false, p->fwd == Algo::SyncFree ? p->kc : 1,
                                   p->fwd == Algo::SyncFree
                                       ? syncfree_lds_bytes(p->R, p->kc, p->L.dt, p->lanes)

@@ -29,6 +29,7 @@ struct rwt_plan {
     rwt::Algo fwd = rwt::Algo::SyncFree;
     rwt::Algo bwd = rwt::Algo::SyncFree;
     int32_t lanes = 4;
+    int32_t stage_x = 1;      // sync-free: helper waves stage outside x values (1) or not (2)
     int cus = 256;
     double tuned_level = 0, tuned_sf = 0;
 };

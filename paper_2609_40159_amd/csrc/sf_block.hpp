@@ -33,6 +33,7 @@ struct SfBlockArgs {
     int32_t sb, ns;          // first step (in step_pos) and number of steps
     int32_t k;               // right-hand sides
     int32_t lanes;           // lanes per row
+    int32_t stage_x;         // staged body: helper waves prefetch x values of earlier blocks
     int64_t ldb, ldx;
     const int32_t* colidx;   // forward pattern
     const int32_t* crow;     // successor pattern (transposed solve)

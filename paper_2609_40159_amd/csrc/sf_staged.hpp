@@ -16,7 +16,11 @@
 //     previous step's x values to HBM.
 // A staged outside value can still be the not-ready sentinel (its producer
 // had not published it when the helper loaded it); the compute lane then
-// waits for it in HBM.  Rows of a step beyond the staged ones, and each
+// waits for it in HBM.  Where that is the rule -- a block whose producers
+// run only just ahead of it, as along the planes of a 3D grid -- the
+// helper's load only lengthens its own step, which the compute waves wait
+// for; with stage_x off the helper stages the sentinel instead and the
+// compute lane always loads the value itself.  The plan times both.  Rows of a step beyond the staged ones, and each
 // row's entries beyond its lanes' first, use direct loads as in sf_block.
 #pragma once
 
@@ -139,17 +143,23 @@ __device__ __forceinline__ void sf_block_staged(const SfBlockArgs& b, unsigned c
             T v;
             T x[KT];
         };
-        auto x_load = [&](const SfEnt2& e) {   // value and outside x of that entry
+        const bool stage_x = b.stage_x != 0;
+        auto x_load = [&](const SfEnt2& e) {   // value and (staged) outside x of that entry
             XL o;
             const bool ok = e.j >= 0;
-            const bool far = ok && !is_local(e.j);
             o.v = vals[ok ? e.m : 0];
-            const int32_t jc = far ? e.j : 0;
+            if (stage_x) {
+                const bool far = ok && !is_local(e.j);
+                const int32_t jc = far ? e.j : 0;
 #pragma unroll
-            for (int q = 0; q < KT; ++q) {
-                const int qc = (KT == 1 || q < k) ? q : 0;
-                const T xv = ld_relaxed(&X[jc + (int64_t)qc * b.ldx]);
-                o.x[q] = far ? xv : T(0);
+                for (int q = 0; q < KT; ++q) {
+                    const int qc = (KT == 1 || q < k) ? q : 0;
+                    const T xv = ld_relaxed(&X[jc + (int64_t)qc * b.ldx]);
+                    o.x[q] = far ? xv : T(0);
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < KT; ++q) o.x[q] = sentinel_value<T>();   // loaded when used
             }
             return o;
         };

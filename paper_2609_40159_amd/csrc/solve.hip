@@ -197,6 +197,7 @@ __global__ void __launch_bounds__(SV_THREADS) k_solve_sf(SolveArgs a) {
     SfBlockArgs b;
     b.k = a.k;
     b.lanes = a.lanes;
+    b.stage_x = a.stage_x;
     b.ldb = a.ldb;
     b.ldx = a.ldx;
     b.colidx = a.colidx;

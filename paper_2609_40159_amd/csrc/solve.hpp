@@ -33,6 +33,7 @@ struct SolveArgs {
     int32_t k;
     int32_t kc;                // sync-free: right-hand sides per chain (1..4)
     int32_t lanes;             // lanes per row (power of two, 1..64)
+    int32_t stage_x;           // sync-free: helper waves prefetch x values of earlier blocks
     const int4* desc;          // sync-free: per row in bperm order {row, first, end, diagonal}
     int32_t lds_bytes;         // sync-free: dynamic LDS per workgroup
     Ctrl* ctrl;

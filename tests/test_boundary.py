@@ -90,7 +90,8 @@ def test_host_only_calls(lib):
     assert lib.rwt_env_init(C.byref(c), C.c_void_p(1), C.c_void_p(1), C.c_void_p(1),
                             C.c_void_p(1), 3, 4, 6, C.byref(ep), C.c_void_p(1), need, None) == -1
     assert b"parameters" in lib.rwt_last_error_string()
-    for field, bad in (("block_rows", (1 << 20) + 1), ("rhs_chunk", 5), ("tune_cols", -1)):
+    for field, bad in (("block_rows", (1 << 20) + 1), ("rhs_chunk", 5), ("tune_cols", -1),
+                       ("stage_outside", 3)):
         setattr(o, field, bad)
         assert lib.rwt_plan_ws(C.byref(c), C.byref(o), C.byref(sz)) == -1, field
         setattr(o, field, 0)

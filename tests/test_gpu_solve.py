@@ -109,6 +109,40 @@ def test_solve_rhs_chunks_agree(orc, block_rows):
     assert relerr(host(X2), ref[:2]) <= 1e-12
 
 
+@pytest.mark.parametrize("name", ["lap3d_24", "powerlaw_20k", "lap2d_120"])
+def test_solve_outside_staging_agrees(orc, name):
+    """Helper waves prefetching the x values of earlier blocks, or the
+    solving lanes loading them: bit-identical results that match the
+    oracle, forward and transposed, one- and four-column chains, both
+    precisions; the tuned plan picks one of the two."""
+    from paper_2609_40159_amd.api import Plan
+    L = {"lap3d_24": lambda: synth.laplacian_3d(24, 24, 24),
+         "powerlaw_20k": lambda: synth.power_law(20000, 23),
+         "lap2d_120": lambda: synth.laplacian_2d(120, 120)}[name]()
+    xs, B = synth.rhs(L, 5, 9)
+    ref = orc.solve(L.n, L.rowptr, L.colidx, L.vals, B)
+    refT = orc.solve_transpose(L.n, L.rowptr, L.colidx, L.vals, B)
+    for dt in (torch.float64, torch.float32):
+        G = to_gpu(L, dt)
+        for kc in (1, 4):
+            out = {}
+            for st in ("on", "off"):
+                plan = Plan(G, algo="syncfree", kmax=5, block_rows=256, rhs_chunk=kc,
+                            stage_outside=st)
+                assert plan.info["stage_outside"] == st and plan.info["num_blocks"] > 1
+                X = plan.solve(block(B, dt))
+                Y = plan.solve_transpose(block(B, dt))
+                plan.check()
+                assert relerr(host(X).astype(np.float64), ref) <= TOL[dt], (dt, kc, st)
+                assert relerr(host(Y).astype(np.float64), refT) <= TOL[dt], (dt, kc, st)
+                out[st] = (X, Y)
+            assert torch.equal(out["on"][0], out["off"][0]), (dt, kc)
+            assert torch.equal(out["on"][1], out["off"][1]), (dt, kc)
+        plan = Plan(G, algo="syncfree", kmax=5, block_rows=256)
+        assert plan.info["stage_outside"] in ("on", "off")
+        assert relerr(host(plan.solve(block(B, dt))).astype(np.float64), ref) <= TOL[dt]
+
+
 def test_solve_full_size_powerlaw_1m_64rhs(orc):
     """Power-law n = 1M, 64 right-hand sides, 0.8% of rows rewritten
     (thin-first): the rewritten system solved with the tuned plan, checked
