@@ -406,15 +406,16 @@ __global__ void k_rw_counts(const int32_t* rowptr, int32_t n, int32_t* counts,
     }
 }
 
-// Copy the rows that are not rewritten: a workgroup takes 256 rows and
-// their contiguous entries; each thread finds its row by binary search in
-// the workgroup's slice of row pointers.
+// Copy the rows that are not rewritten, and their right-hand sides: a
+// workgroup takes 256 rows and their contiguous entries; each thread finds
+// its row by binary search in the workgroup's slice of row pointers.
 template <typename T>
 __global__ void __launch_bounds__(256) k_rw_copy(const int32_t* rowptr, const int32_t* colidx,
                                                  const T* vals, int32_t n,
                                                  const unsigned char* rewritten,
                                                  const int32_t* rowptr_out, int32_t* colidx_out,
-                                                 T* vals_out) {
+                                                 T* vals_out, const T* B, int64_t ldb, T* Bp,
+                                                 int64_t ldbp, int32_t k) {
     __shared__ int32_t s_ptr[257];
     const int32_t r0 = blockIdx.x * 256;
     const int32_t r1 = min(n, r0 + 256);
@@ -435,18 +436,9 @@ __global__ void __launch_bounds__(256) k_rw_copy(const int32_t* rowptr, const in
         colidx_out[o] = colidx[p];
         vals_out[o] = vals[p];
     }
-}
-
-template <typename T>
-__global__ void k_rw_copy_b(const T* B, int64_t ldb, T* Bp, int64_t ldbp, int32_t n, int32_t k,
-                            const unsigned char* rewritten) {
-    int64_t total = (int64_t)n * k;
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t st = (int64_t)gridDim.x * blockDim.x;
-    for (; t < total; t += st) {
-        int64_t q = t / n, i = t - q * n;
-        if (!rewritten[i]) Bp[i + q * ldbp] = B[i + q * ldb];
-    }
+    const int32_t i = r0 + (int32_t)threadIdx.x;
+    if (i < r1 && !rewritten[i])
+        for (int32_t q = 0; q < k; ++q) Bp[i + q * ldbp] = B[i + q * ldb];
 }
 
 struct RwWs {
@@ -772,7 +764,11 @@ extern "C" rwt_status rwt_rewrite_symbolic(const rwt_csr* L, const int32_t* d_le
     if (L->dt == RWT_F64) RWT_TRY(launch_rows<double>(a, false, s));
     else RWT_TRY(launch_rows<float>(a, false, s));
     RWT_TRY(scan_exclusive(w.counts, d_rowptr_out, L->n, w.scan, s));
-    RWT_TRY(scan_exclusive(w.csub, d_cptr_out, m, w.scan, s));
+    // the substitution offsets stay in the workspace too: the numeric call
+    // (same workspace, untouched in between) reads them from there
+    RWT_TRY(scan_exclusive(w.csub, w.cptr, m, w.scan, s));
+    RWT_HIP(hipMemcpyAsync(d_cptr_out, w.cptr, sizeof(int32_t) * ((size_t)m + 1),
+                           hipMemcpyDeviceToDevice, s));
     int32_t tail[2] = {0, 0};
     int32_t hc[8];
     RWT_HIP(hipMemcpyAsync(&tail[0], d_rowptr_out + L->n, 4, hipMemcpyDeviceToHost, s));
@@ -812,40 +808,29 @@ extern "C" rwt_status rwt_rewrite_numeric(const rwt_csr* L, const int32_t* d_lev
     a.Bp = d_Bp;
     a.ldbp = ldbp;
     a.k = k;
-    // scratch multiplier arrays when the caller does not want them
-    a.cptr = nullptr;
     a.crow = d_crow;
     a.ccol = d_ccol;
     a.cval = d_cval;
     RWT_REQUIRE((d_crow && d_ccol && d_cval) || (!d_crow && !d_ccol && !d_cval),
                 RWT_ERR_INVALID_ARG, "multiplier arrays must be all given or all NULL");
-    // offsets of each row's substitutions, from the counts the symbolic call
-    // left in the workspace
-    RWT_TRY(scan_exclusive(w.csub, w.cptr, m, w.scan, s));
+    // offsets of each row's substitutions: the symbolic call left them in
+    // the workspace
     a.cptr = w.cptr;
     if (L->n > 0) {
         const unsigned g = (unsigned)((L->n + 255) / 256);
         if (L->dt == RWT_F64)
             hipLaunchKernelGGL(k_rw_copy<double>, dim3(g), dim3(256), 0, s, L->rowptr, L->colidx,
                                static_cast<const double*>(L->vals), L->n, w.rewritten, Lp->rowptr,
-                               a.colidx_out, static_cast<double*>(a.vals_out));
+                               a.colidx_out, static_cast<double*>(a.vals_out),
+                               static_cast<const double*>(d_B), ldb, static_cast<double*>(d_Bp),
+                               ldbp, k);
         else
             hipLaunchKernelGGL(k_rw_copy<float>, dim3(g), dim3(256), 0, s, L->rowptr, L->colidx,
                                static_cast<const float*>(L->vals), L->n, w.rewritten, Lp->rowptr,
-                               a.colidx_out, static_cast<float*>(a.vals_out));
+                               a.colidx_out, static_cast<float*>(a.vals_out),
+                               static_cast<const float*>(d_B), ldb, static_cast<float*>(d_Bp),
+                               ldbp, k);
         RWT_LAUNCHED();
-        if (k > 0) {
-            const unsigned gb = blocks_for((size_t)L->n * k, 256, 8192);
-            if (L->dt == RWT_F64)
-                hipLaunchKernelGGL(k_rw_copy_b<double>, dim3(gb), dim3(256), 0, s,
-                                   static_cast<const double*>(d_B), ldb, static_cast<double*>(d_Bp),
-                                   ldbp, L->n, k, w.rewritten);
-            else
-                hipLaunchKernelGGL(k_rw_copy_b<float>, dim3(gb), dim3(256), 0, s,
-                                   static_cast<const float*>(d_B), ldb, static_cast<float*>(d_Bp),
-                                   ldbp, L->n, k, w.rewritten);
-            RWT_LAUNCHED();
-        }
     }
     if (L->dt == RWT_F64) RWT_TRY(launch_rows<double>(a, true, s));
     else RWT_TRY(launch_rows<float>(a, true, s));
