@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--no-generator", action="store_true",
                     help="skip the rewrite-list generator section")
     ap.add_argument("--no-env", action="store_true", help="skip the environment-step section")
+    ap.add_argument("--block-rows", type=int, default=0,
+                    help="main solve plan: rows per sync-free block (0: timed at plan creation; "
+                         "fix it for counter runs)")
     ap.add_argument("--stage-outside", default="auto", choices=["auto", "on", "off"],
                     help="main solve plan: helper waves prefetch outside x values (auto: timed "
                          "at plan creation; fix it for counter runs, whose timings are distorted)")
@@ -106,9 +109,9 @@ def src_hash(files):
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel_key: str, srchash: str, stage: str):
+def load_traffic(kernel_key: str, srchash: str, stage: str, block_rows: int):
     """HBM bytes per launch from committed counter runs, if they are current
-    (same solve sources, same staging of outside values)."""
+    (same solve sources, same block size and staging of outside values)."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
@@ -117,7 +120,8 @@ def load_traffic(kernel_key: str, srchash: str, stage: str):
     except (OSError, ValueError):
         return None
     e = d.get(kernel_key)
-    if not e or e.get("src_hash") != srchash or e.get("stage_outside") != stage:
+    if (not e or e.get("src_hash") != srchash or e.get("stage_outside") != stage
+            or e.get("block_rows") != block_rows):
         return None
     return e.get("hbm_bytes_per_launch")
 
@@ -600,7 +604,8 @@ def main():
     Bp = rw.numeric(vals, B)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plan = Plan(rw.Lp, algo="auto", kmax=k, stage_outside=args.stage_outside)
+    plan = Plan(rw.Lp, algo="auto", kmax=k, block_rows=args.block_rows,
+                stage_outside=args.stage_outside)
     torch.cuda.synchronize()
     pre["plan_ms"] = (time.perf_counter() - t0) * 1e3
     pinfo = plan.info
@@ -796,7 +801,7 @@ def main():
             "bound": "hbm", "kernel": kname, "achieved": achieved, "peak": PEAK_HBM_GBS,
             "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
             "traffic": load_traffic(f"{args.workload}:{args.dtype}:{kname}", srch,
-                                    pinfo["stage_outside"]),
+                                    pinfo["stage_outside"], pinfo["block_rows"]),
             "algorithmic_bytes_per_launch": nbytes, "avg_launch_ms": ms[ph_name],
             "latency_floor_note": f"{Dp} dependent levels on the critical path"}
     dom = "fwd" if ms["fwd"] >= ms["bwd"] else "bwd"

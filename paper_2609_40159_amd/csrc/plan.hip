@@ -521,9 +521,27 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
             hipLaunchKernelGGL(k_fill_val<float>, dim3(g), dim3(256), 0, s,
                                static_cast<float*>(p->xtmp), nf, 1.0f);
     }
+    // staging of outside x values in the helper waves (on or off), decided
+    // first, on the largest block candidate, so that the block size is tuned
+    // with it: both timed alternately after two warm-up solves, best of
+    // three each
+    if (tune_stage) {
+        if ((st = build_blocks(R)) != RWT_OK) return fail(st);
+        if (p->nblocks > 1) {
+            double t[2] = {1e30, 1e30};
+            for (int w = 0; w < 2; ++w) (void)time_solve(p, Algo::SyncFree, kt, s, 1);
+            for (int r = 0; r < 3; ++r)
+                for (int m = 0; m < 2; ++m) {
+                    p->stage_x = m + 1;
+                    t[m] = std::min(t[m], time_solve(p, Algo::SyncFree, kt, s, 1));
+                }
+            p->stage_x = t[1] < t[0] ? 2 : 1;
+        }
+    }
     if (tune_algo || tune_sf) {
-        // per chunk, candidates run from large blocks to small; stop after
-        // two in a row that are more than 10% slower than the best so far
+        // per chunk, candidates run from large blocks to small, each the best
+        // of three timed solves after a warm-up; stop after two in a row that
+        // are more than 10% slower than the best so far
         double best_sf = 1e30;
         int best_R = R, best_kc = kcs.front();
         for (int kc : kcs) {
@@ -532,7 +550,7 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
             int worse = 0;
             for (int Rc : block_candidates(*opts, L->dt, n, kc, lanes)) {
                 if ((st = build_blocks(Rc)) != RWT_OK) return fail(st);
-                double ms = time_solve(p, Algo::SyncFree, kt, s, 2);
+                double ms = time_solve(p, Algo::SyncFree, kt, s, 4);   // best of 3
                 if (ms < best_sf) { best_sf = ms; best_R = Rc; best_kc = kc; }
                 if (ms < best_here) best_here = ms;
                 worse = ms > 1.1 * best_here ? worse + 1 : 0;
@@ -559,18 +577,6 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
         }
     }
     if ((st = build_blocks(R)) != RWT_OK) return fail(st);
-    // staging of outside x values in the helper waves (on or off): both
-    // timed on the chosen schedule, alternately, best of three each
-    if (tune_stage && p->nblocks > 1 && (p->fwd == Algo::SyncFree || p->bwd == Algo::SyncFree)) {
-        double t[2] = {1e30, 1e30};
-        (void)time_solve(p, Algo::SyncFree, kt, s, 1);   // warm-up
-        for (int r = 0; r < 3; ++r)
-            for (int m = 0; m < 2; ++m) {
-                p->stage_x = m + 1;
-                t[m] = std::min(t[m], time_solve(p, Algo::SyncFree, kt, s, 1));
-            }
-        p->stage_x = t[1] < t[0] ? 2 : 1;
-    }
     if (hipStreamSynchronize(s) != hipSuccess) {
         set_hip_error(hipGetLastError(), "plan creation");
         return fail(RWT_ERR_HIP);
