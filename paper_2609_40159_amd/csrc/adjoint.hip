@@ -5,6 +5,7 @@
 // C^T is built with the stable radix sort so every sum runs in a fixed
 // order: the results do not depend on the schedule.
 #include "prim.hpp"
+#include "rowmap.hpp"
 
 namespace rwt {
 
@@ -59,27 +60,23 @@ __global__ void k_apply_m(const int32_t* ptr, const int32_t* ccol, const T* cval
 }
 
 // grad_vals[p] = 0 - sum_q gB[row_p, q] * X[col_p, q]: a workgroup takes 256
-// rows and their contiguous entries; each thread finds its row by binary
-// search in the workgroup's slice of row pointers.
+// rows and their contiguous entries; each thread finds its row in an LDS
+// map of entry -> row (binary search when the rows' entries exceed it).
 template <typename T>
 __global__ void __launch_bounds__(256) k_grad_vals(const int32_t* rowptr, const int32_t* colidx,
                                                    int32_t n, const T* gB, int64_t ldg, const T* X,
                                                    int64_t ldx, int32_t k, T* gv) {
     __shared__ int32_t s_ptr[257];
+    __shared__ unsigned char s_row[ROW_MAP];
     const int32_t r0 = blockIdx.x * 256;
     const int32_t r1 = min(n, r0 + 256);
     for (int32_t i = threadIdx.x; i <= r1 - r0; i += blockDim.x) s_ptr[i] = rowptr[r0 + i];
     __syncthreads();
     const int32_t nr = r1 - r0;
     const int32_t pb = s_ptr[0], pe = s_ptr[nr];
+    const bool mapped = map_rows(s_ptr, nr, s_row);
     for (int32_t p = pb + threadIdx.x; p < pe; p += blockDim.x) {
-        int lo = 0, hi = nr - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (s_ptr[mid] <= p) lo = mid;
-            else hi = mid - 1;
-        }
-        const int32_t i = r0 + lo;
+        const int32_t i = r0 + row_of(s_ptr, nr, s_row, mapped, p);
         const int32_t j = colidx[p];
         T s = T(0);
         for (int32_t q = 0; q < k; ++q) s = add_rn(s, mul_rn(gB[i + (int64_t)q * ldg], X[j + (int64_t)q * ldx]));

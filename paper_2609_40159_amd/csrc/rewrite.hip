@@ -24,6 +24,7 @@
 #include "analyze.hpp"
 #include "batch.hpp"
 #include "prim.hpp"
+#include "rowmap.hpp"
 
 namespace rwt {
 
@@ -408,7 +409,8 @@ __global__ void k_rw_counts(const int32_t* rowptr, int32_t n, int32_t* counts,
 
 // Copy the rows that are not rewritten, and their right-hand sides: a
 // workgroup takes 256 rows and their contiguous entries; each thread finds
-// its row by binary search in the workgroup's slice of row pointers.
+// its row in an LDS map of entry -> row (binary search when the rows'
+// entries exceed it).
 template <typename T>
 __global__ void __launch_bounds__(256) k_rw_copy(const int32_t* rowptr, const int32_t* colidx,
                                                  const T* vals, int32_t n,
@@ -417,19 +419,16 @@ __global__ void __launch_bounds__(256) k_rw_copy(const int32_t* rowptr, const in
                                                  T* vals_out, const T* B, int64_t ldb, T* Bp,
                                                  int64_t ldbp, int32_t k) {
     __shared__ int32_t s_ptr[257];
+    __shared__ unsigned char s_row[ROW_MAP];
     const int32_t r0 = blockIdx.x * 256;
     const int32_t r1 = min(n, r0 + 256);
     for (int32_t i = threadIdx.x; i <= r1 - r0; i += blockDim.x) s_ptr[i] = rowptr[r0 + i];
     __syncthreads();
     const int32_t nr = r1 - r0;
     const int32_t pb = s_ptr[0], pe = s_ptr[nr];
+    const bool mapped = map_rows(s_ptr, nr, s_row);
     for (int32_t p = pb + threadIdx.x; p < pe; p += blockDim.x) {
-        int lo = 0, hi = nr - 1;   // last row whose start <= p
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (s_ptr[mid] <= p) lo = mid;
-            else hi = mid - 1;
-        }
+        const int lo = row_of(s_ptr, nr, s_row, mapped, p);
         const int32_t i = r0 + lo;
         if (rewritten[i]) continue;
         const int32_t o = rowptr_out[i] + (p - s_ptr[lo]);
