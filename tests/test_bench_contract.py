@@ -40,3 +40,23 @@ def test_transposed_and_adjoint_bytes_are_consistent():
     assert bench.bytes_solve_t(n, nnz, k, s) > bench.bytes_solve(n, nnz, k, s)
     assert bench.bytes_grad_vals(n, nnz, k, s) == 4 * (n + 1) + nnz * (4 + s) + 2 * n * k * s
     assert bench.bytes_apply_mt(n, k, s, 0) == 2 * n * k * s + 4 * (n + 1)
+
+
+def test_traffic_is_reported_only_for_the_profiled_configuration(tmp_path, monkeypatch):
+    """HBM traffic from the committed counter runs is attached to the bench
+    line only when the solve sources, block size and staging of outside
+    values are those the counters were taken with."""
+    tj = tmp_path / "profiles" / "traffic.json"
+    tj.parent.mkdir()
+    key = "lap3d_128:f64:k_solve_sf<double, true, 1>"
+    tj.write_text(json.dumps({key: {"src_hash": "abc", "stage_outside": "off", "block_rows": 4096,
+                                    "hbm_bytes_per_launch": 5.0e8}}))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.load_traffic(key, "abc", "off", 4096) == 5.0e8
+    assert bench.load_traffic(key, "abd", "off", 4096) is None      # sources changed
+    assert bench.load_traffic(key, "abc", "on", 4096) is None       # other staging
+    assert bench.load_traffic(key, "abc", "off", 2048) is None      # other block size
+    assert bench.load_traffic("other", "abc", "off", 4096) is None
+    tj.write_text("not json")
+    assert bench.load_traffic(key, "abc", "off", 4096) is None
+
