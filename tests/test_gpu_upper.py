@@ -57,6 +57,27 @@ def test_upper_solve_matches_oracle(orc, name, algo):
     assert relerr(host(Y), refT) <= 1e-12, name
 
 
+@pytest.mark.parametrize("name", ["lap3d_14x12x10", "powerlaw_20k"])
+def test_upper_outside_staging_agrees(orc, name):
+    """Upper solves with the helper waves' staging of outside values on and
+    off: bit-identical, and equal to the oracle's backward substitution."""
+    from paper_2609_40159_amd.api import UpperPlan
+    U = uppers()[name]
+    xs, B = synth.rhs(U, 3, 6)
+    ref = orc.solve_upper(U.n, U.rowptr, U.colidx, U.vals, B)
+    G = to_gpu(U)
+    out = {}
+    for st in ("on", "off"):
+        up = UpperPlan(G, algo="syncfree", kmax=3, block_rows=128, stage_outside=st)
+        assert up.info["stage_outside"] == st and up.info["num_blocks"] > 1
+        X = up.solve(block(B))
+        Y = up.solve_transpose(block(B))
+        up.check()
+        assert relerr(host(X), ref) <= 1e-12, st
+        out[st] = (X, Y)
+    assert torch.equal(out["on"][0], out["off"][0]) and torch.equal(out["on"][1], out["off"][1])
+
+
 def test_upper_solve_fp32_and_in_place(orc):
     from paper_2609_40159_amd.api import UpperPlan
     U = synth.transpose_upper(synth.power_law(30000, 9), seed=4)
