@@ -229,6 +229,12 @@ STAGE = {"auto": 0, "on": 1, "off": 2}
 STAGE_NAME = {1: "on", 2: "off"}
 
 
+def _option(table: dict, value, what: str) -> int:
+    if value not in table:
+        raise ValueError(f"{what} must be one of {sorted(table)}, not {value!r}")
+    return table[value]
+
+
 class Plan:
     """Analysis + schedule of one matrix; solves L X = B and L^T Y = G."""
 
@@ -239,14 +245,14 @@ class Plan:
         self.L = L
         self._lib = lib
         o = _lib.PlanOpts()
-        o.algo = _lib.ALGO[algo]
+        o.algo = _option(_lib.ALGO, algo, "algo")
         o.block_rows = block_rows
         o.lanes_per_row = lanes_per_row
         o.narrow_rows = narrow_rows
         o.kmax = kmax
         o.watchdog_ms = watchdog_ms
         o.rhs_chunk = rhs_chunk
-        o.stage_outside = STAGE[stage_outside]
+        o.stage_outside = _option(STAGE, stage_outside, "stage_outside")
         self.opts = o
         sz = C.c_size_t(0)
         check(lib.rwt_plan_ws(C.byref(L.view()), C.byref(o), C.byref(sz)))
@@ -330,14 +336,14 @@ class UpperPlan(Plan):
         self.L = U
         self._lib = lib
         o = _lib.PlanOpts()
-        o.algo = _lib.ALGO[algo]
+        o.algo = _option(_lib.ALGO, algo, "algo")
         o.block_rows = block_rows
         o.lanes_per_row = lanes_per_row
         o.narrow_rows = narrow_rows
         o.kmax = kmax
         o.watchdog_ms = watchdog_ms
         o.rhs_chunk = rhs_chunk
-        o.stage_outside = STAGE[stage_outside]
+        o.stage_outside = _option(STAGE, stage_outside, "stage_outside")
         self.opts = o
         sz = C.c_size_t(0)
         check(lib.rwt_upper_ws(C.byref(U.view()), C.byref(o), C.byref(sz)))

@@ -183,3 +183,13 @@ def test_python_signatures_match_header_prototypes():
             assert restype is C.c_int, name
         elif ret == "size_t":
             assert restype is C.c_size_t, name
+
+
+def test_plan_options_are_checked_by_name(lib):
+    """Unknown algorithm or staging names are refused before any device call."""
+    from paper_2609_40159_amd.api import Plan, UpperPlan
+    for cls in (Plan, UpperPlan):
+        with pytest.raises(ValueError, match="algo must be one of"):
+            cls(None, algo="fast")
+        with pytest.raises(ValueError, match="stage_outside must be one of"):
+            cls(None, stage_outside="maybe")
