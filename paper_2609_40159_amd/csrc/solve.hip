@@ -96,15 +96,22 @@ __device__ __forceinline__ void solve_row(const SolveArgs& a, bool active, int32
     }
 }
 
+// Sentinel prefill of the n x k solution block (column stride ldx) and reset
+// of the solve's control words, in one launch.
+static_assert(sizeof(Ctrl) % 4 == 0 && sizeof(Ctrl) / 4 <= 256, "control words");
 template <typename T>
-__global__ void k_prefill(T* X, int64_t ldx, int32_t n, int32_t k) {
+__global__ void __launch_bounds__(256) k_prefill(T* X, int64_t ldx, int32_t n, int32_t k,
+                                                 uint32_t* ctrl) {
+    if (blockIdx.x == 0 && threadIdx.x < sizeof(Ctrl) / 4) ctrl[threadIdx.x] = 0u;
     const T s = sentinel_value<T>();
-    int64_t total = (int64_t)n * k;
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t st = (int64_t)gridDim.x * blockDim.x;
-    for (; t < total; t += st) {
-        int64_t q = t / n, i = t - q * n;
-        X[i + q * ldx] = s;
+    const int64_t st = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k == 1 || ldx == n) {   // one contiguous run of n * k values
+        const int64_t total = (int64_t)n * k;
+        for (int64_t t = t0; t < total; t += st) X[t] = s;
+    } else {
+        for (int32_t q = 0; q < k; ++q)
+            for (int64_t i = t0; i < n; i += st) X[i + (int64_t)q * ldx] = s;
     }
 }
 
@@ -287,16 +294,17 @@ int syncfree_lds_bytes(int block_rows, int k, rwt_dtype dt, int lanes) {
 }
 
 rwt_status solve_prepare(const SolveArgs& a, rwt_dtype dt, hipStream_t s) {
-    RWT_TRY(fill_u8(a.ctrl, sizeof(Ctrl), s));
     const int64_t total = (int64_t)a.n * a.k;
-    if (total == 0) return RWT_OK;
-    const unsigned g = blocks_for(total, 256, 8192);
+    if (total == 0) return fill_u8(a.ctrl, sizeof(Ctrl), s);
+    // about four values per thread
+    const unsigned g = blocks_for(total, 1024, 4096);
+    uint32_t* cw = reinterpret_cast<uint32_t*>(a.ctrl);
     if (dt == RWT_F64)
         hipLaunchKernelGGL(k_prefill<double>, dim3(g), dim3(256), 0, s, static_cast<double*>(a.X),
-                           a.ldx, a.n, a.k);
+                           a.ldx, a.n, a.k, cw);
     else
         hipLaunchKernelGGL(k_prefill<float>, dim3(g), dim3(256), 0, s, static_cast<float*>(a.X),
-                           a.ldx, a.n, a.k);
+                           a.ldx, a.n, a.k, cw);
     RWT_LAUNCHED();
     return RWT_OK;
 }
