@@ -98,6 +98,8 @@ typedef struct {
 
 const char* rwt_last_error_string(void);
 int rwt_last_hip_error(void);
+/* "rwtrsv <major>.<minor> gfx950"; 0.2 added rwt_plan_opts.stage_outside
+ * and rwt_plan_info.stage_outside (callers built against 0.1 must rebuild) */
 const char* rwt_version(void);
 
 /* ------------------------------------------------------------------------
