@@ -236,6 +236,34 @@ rwt_status rwt_plan_levels(const rwt_plan* plan, const int32_t** d_level,
                            const int32_t** d_perm, const int32_t** d_level_ptr);
 rwt_status rwt_plan_destroy(rwt_plan* plan);
 
+/* ------------------------------------------------------------------------
+ * Tall-block row order (host code, no device work; not in the paper: a
+ * schedule aid for the sync-free solve of Section 7).  The sync-free solve
+ * walks blocks of consecutive rows, and a dependency chain that leaves its
+ * block at every level pays a cross-workgroup hand-off per level.  This
+ * returns a topological order of L's rows in which consecutive rows form
+ * tiles of whole chains: chains follow each row's dependency one level
+ * below (Section 2.1 levels), chains of chains do the same on the chain
+ * heads, and a tile is a positions along a chain of chains by b chains of
+ * chains.
+ *   h_rowptr[n+1], h_colidx[nnz]: L's pattern in host memory (entries of a
+ *     row below the diagonal, the diagonal last; values are not read);
+ *   a, b: tile shape (0: 4 and 8);
+ *   h_perm[n] (caller's host buffer, out): new -> old row numbers.  The
+ *     matrix P L P^T, entry (i, j) = L[perm[i]][perm[j]], is lower
+ *     triangular: solve it with b'[i] = b[perm[i]] and set x[perm[i]] = x'[i].
+ * For a rewritten factor L' = M L compute the order on L: rewriting only
+ * adds dependencies from the transitive closure of L's DAG, so L's order
+ * stays topological for L' and keeps its tiles (the rewritten rows change
+ * the chains when the order is computed on L' itself).
+ * Errors: RWT_ERR_INVALID_ARG (null pointer, negative n, a or b, rowptr[0]
+ * not 0), RWT_ERR_MISSING_DIAG (a row empty or not ending at its
+ * diagonal), RWT_ERR_NOT_LOWER (a column outside [0, row)); h_perm is then
+ * unspecified.
+ * ---------------------------------------------------------------------- */
+rwt_status rwt_tall_block_order(int32_t n, const int32_t* h_rowptr, const int32_t* h_colidx,
+                                int32_t a, int32_t b, int32_t* h_perm);
+
 /* Forward solve L X = B (Section 2.1).  k <= kmax.  d_X may equal d_B
  * (in place).  A watchdog expiry returns RWT_ERR_DEADLOCK (synchronizing
  * only when it must report). */

@@ -145,6 +145,7 @@ SIGNATURES = {
                                        C.POINTER(I64), P]),
     "rwt_rewrite_numeric": (C.c_int, [C.POINTER(Csr), P, P, P, I32, P, I32, I64,
                                       C.POINTER(Csr), P, I64, P, P, P, P, SZ, P]),
+    "rwt_tall_block_order": (C.c_int, [C.c_int32, P, P, C.c_int32, C.c_int32, P]),
     "rwt_plan_ws": (C.c_int, [C.POINTER(Csr), C.POINTER(PlanOpts), C.POINTER(SZ)]),
     "rwt_plan_create": (C.c_int, [C.POINTER(Csr), C.POINTER(PlanOpts), P, SZ, C.POINTER(P), P]),
     "rwt_plan_get_info": (C.c_int, [P, C.POINTER(PlanInfo)]),

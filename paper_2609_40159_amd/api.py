@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes as C
 from dataclasses import dataclass
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -17,7 +18,7 @@ from ._lib import RwtError, check
 
 __all__ = ["CSRMatrix", "LevelInfo", "validate", "analyze", "rewrite", "Rewrite", "Rewriter", "Plan",
            "solve",
-           "apply_MT", "grad_vals", "Batch", "RwtError", "Env"]
+           "apply_MT", "grad_vals", "Batch", "RwtError", "Env", "tall_block_order"]
 
 
 def _stream() -> int:
@@ -795,6 +796,22 @@ class Batch:
                 "block_rows": inf.block_rows, "lanes_per_row": inf.lanes_per_row,
                 "rhs_chunk": inf.rhs_chunk, "num_blocks": inf.num_blocks,
                 "tuned_ms": inf.tuned_ms_syncfree}
+
+
+def tall_block_order(rowptr, colidx, a: int = 0, b: int = 0) -> np.ndarray:
+    """Topological row order (new -> old) whose consecutive rows form tiles
+    of whole dependency chains, for the sync-free solve (host code; tile of
+    a positions along a chain of chains by b chains of chains, 0: 4 and 8).
+    rowptr and colidx are L's pattern as host arrays."""
+    lib = _lib.load()
+    rp = np.ascontiguousarray(rowptr, dtype=np.int32)
+    ci = np.ascontiguousarray(colidx, dtype=np.int32)
+    n = rp.shape[0] - 1
+    if n < 0:
+        raise ValueError("rowptr needs n + 1 entries")
+    perm = np.empty(n, dtype=np.int32)
+    check(lib.rwt_tall_block_order(n, rp.ctypes.data, ci.ctypes.data, a, b, perm.ctypes.data))
+    return perm
 
 
 def probe_handoff(rounds: int = 2000) -> float:
