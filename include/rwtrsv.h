@@ -99,8 +99,13 @@ typedef struct {
 const char* rwt_last_error_string(void);
 int rwt_last_hip_error(void);
 /* "rwtrsv <major>.<minor> gfx950"; 0.2 added rwt_plan_opts.stage_outside
- * and rwt_plan_info.stage_outside (callers built against 0.1 must rebuild) */
+ * and rwt_plan_info.stage_outside (callers built against 0.1 must rebuild);
+ * 0.3 added rwt_upper_levels, rwt_solve_withhold, rwt_batch_run_setup/_main
+ * and rwt_source_hash */
 const char* rwt_version(void);
+/* 16 hex digits identifying the sources and flags the library was built
+ * from ("unknown" when the build did not say) */
+const char* rwt_source_hash(void);
 
 /* ------------------------------------------------------------------------
  * Validation (CSR interchange format of Section 2.2).  Reports the error of
@@ -275,6 +280,18 @@ rwt_status rwt_solve(const rwt_plan* plan, const void* d_B, int32_t k, int64_t l
 rwt_status rwt_solve_transpose(const rwt_plan* plan, const void* d_G, int32_t k, int64_t ldg,
                                void* d_Y, int64_t ldy, rwt_stream_t stream);
 
+/* Test aid for the watchdog path of the sync-free solves (Section 7: a
+ * reader spins until its dependency is published).  Runs rwt_solve but
+ * never publishes row `row`'s values to d_X (the row is still solved and
+ * its block reads it from LDS), so every reader outside that block waits
+ * until the plan's watchdog (rwt_plan_opts.watchdog_ms) expires; every wait
+ * then ends, the kernel exits, rwt_plan_check reports RWT_ERR_DEADLOCK and
+ * d_X holds unspecified values.  The next rwt_solve on the plan is
+ * unaffected.  Errors: RWT_ERR_INVALID_ARG for a row outside [0, n), and
+ * those of rwt_solve. */
+rwt_status rwt_solve_withhold(const rwt_plan* plan, int32_t row, const void* d_B, int32_t k,
+                              int64_t ldb, void* d_X, int64_t ldx, rwt_stream_t stream);
+
 /* Device error word of the last solve on this plan (RWT_OK or
  * RWT_ERR_DEADLOCK).  Synchronizes the stream. */
 rwt_status rwt_plan_check(const rwt_plan* plan, rwt_stream_t stream);
@@ -312,6 +329,11 @@ rwt_status rwt_upper_create(const rwt_csr* U, const rwt_plan_opts* opts, void* d
                             size_t ws_bytes, rwt_upper** out, rwt_stream_t stream);
 rwt_status rwt_upper_refresh(rwt_upper* up, rwt_stream_t stream);
 rwt_status rwt_upper_get_info(const rwt_upper* up, rwt_plan_info* h_info);
+/* Levels of the backward substitution: the device arrays of the plan of
+ * J U J (as rwt_plan_levels), in the reversed numbering -- entry i' is U's
+ * row n-1-i'. */
+rwt_status rwt_upper_levels(const rwt_upper* up, const int32_t** d_level, const int32_t** d_perm,
+                            const int32_t** d_level_ptr);
 rwt_status rwt_upper_solve(const rwt_upper* up, const void* d_B, int32_t k, int64_t ldb,
                            void* d_X, int64_t ldx, rwt_stream_t stream);
 rwt_status rwt_upper_solve_transpose(const rwt_upper* up, const void* d_G, int32_t k,
@@ -694,6 +716,14 @@ rwt_status rwt_batch_ws(const rwt_batch_desc* desc, size_t* h_bytes);
 rwt_status rwt_batch_create(const rwt_batch_desc* desc, void* d_ws, size_t ws_bytes,
                             rwt_batch** out, rwt_stream_t stream);
 rwt_status rwt_batch_run(rwt_batch* batch, rwt_stream_t stream);
+/* rwt_batch_run in its two parts, enqueued one after the other on one
+ * stream: the setup kernels (launch epoch, resets, candidate checks and
+ * the batched symbolic rewrite) and then the persistent kernel alone (so
+ * that a caller can time it with events recorded in between).  Calling
+ * rwt_batch_run_main without the setup of the same launch before it is an
+ * error the library cannot detect. */
+rwt_status rwt_batch_run_setup(rwt_batch* batch, rwt_stream_t stream);
+rwt_status rwt_batch_run_main(rwt_batch* batch, rwt_stream_t stream);
 /* stream must not be the legacy default stream (capture needs a real stream) */
 rwt_status rwt_batch_capture(rwt_batch* batch, rwt_stream_t stream);
 rwt_status rwt_batch_launch(rwt_batch* batch, rwt_stream_t stream);

@@ -136,6 +136,7 @@ SIGNATURES = {
     "rwt_last_error_string": (C.c_char_p, []),
     "rwt_last_hip_error": (C.c_int, []),
     "rwt_version": (C.c_char_p, []),
+    "rwt_source_hash": (C.c_char_p, []),
     "rwt_validate_ws": (SZ, []),
     "rwt_validate": (C.c_int, [C.POINTER(Csr), P, SZ, C.POINTER(I32), P]),
     "rwt_analyze_ws": (C.c_int, [C.POINTER(Csr), C.POINTER(SZ)]),
@@ -154,6 +155,7 @@ SIGNATURES = {
     "rwt_solve": (C.c_int, [P, P, I32, I64, P, I64, P]),
     "rwt_solve_transpose": (C.c_int, [P, P, I32, I64, P, I64, P]),
     "rwt_plan_check": (C.c_int, [P, P]),
+    "rwt_solve_withhold": (C.c_int, [P, I32, P, I32, I64, P, I64, P]),
     "rwt_apply_MT_ws": (C.c_int, [I32, I64, C.POINTER(SZ)]),
     "rwt_apply_MT": (C.c_int, [I32, I64, P, P, P, I32, P, I32, I64, P, I64, P, SZ, P]),
     "rwt_apply_MT_prepare": (C.c_int, [I32, I64, P, P, SZ, P]),
@@ -164,6 +166,8 @@ SIGNATURES = {
     "rwt_batch_ws": (C.c_int, [C.POINTER(BatchDesc), C.POINTER(SZ)]),
     "rwt_batch_create": (C.c_int, [C.POINTER(BatchDesc), P, SZ, C.POINTER(P), P]),
     "rwt_batch_run": (C.c_int, [P, P]),
+    "rwt_batch_run_setup": (C.c_int, [P, P]),
+    "rwt_batch_run_main": (C.c_int, [P, P]),
     "rwt_batch_capture": (C.c_int, [P, P]),
     "rwt_batch_launch": (C.c_int, [P, P]),
     "rwt_batch_stats": (C.c_int, [P, P, P]),
@@ -174,6 +178,7 @@ SIGNATURES = {
     "rwt_upper_create": (C.c_int, [C.POINTER(Csr), C.POINTER(PlanOpts), P, SZ, C.POINTER(P), P]),
     "rwt_upper_refresh": (C.c_int, [P, P]),
     "rwt_upper_get_info": (C.c_int, [P, C.POINTER(PlanInfo)]),
+    "rwt_upper_levels": (C.c_int, [P, C.POINTER(P), C.POINTER(P), C.POINTER(P)]),
     "rwt_upper_solve": (C.c_int, [P, P, I32, I64, P, I64, P]),
     "rwt_upper_solve_transpose": (C.c_int, [P, P, I32, I64, P, I64, P]),
     "rwt_solve_pair": (C.c_int, [P, P, P, I32, I64, P, I64, P]),
@@ -212,6 +217,16 @@ def load() -> C.CDLL:
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
+    # a library built from other sources than the ones next to it (a stale
+    # build shipped with the tree) is refused: rebuild it
+    from ._srchash import source_hash
+    from .build import FLAGS
+    want = source_hash(FLAGS)
+    have = lib.rwt_source_hash().decode()
+    if want is not None and have != want:
+        raise ImportError(
+            f"{LIB_PATH} was built from other sources (library {have}, sources {want}): "
+            "rebuild it with paper_2609_40159_amd.build.build()")
     _lib = lib
     return lib
 

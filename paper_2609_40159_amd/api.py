@@ -72,6 +72,23 @@ class CSRMatrix:
         return cls(rp, ci, v)
 
     def view(self) -> _lib.Csr:
+        # the library reads these pointers on the GPU: refuse host tensors,
+        # mixed devices and wrong index or value types before any launch
+        dev = self.rowptr.device
+        if dev.type != "cuda":
+            raise ValueError(f"the matrix is on {dev}; the library needs GPU tensors")
+        if self.rowptr.dtype != torch.int32 or self.colidx.dtype != torch.int32:
+            raise ValueError("rowptr and colidx must be int32")
+        _on(self.colidx, dev, "colidx")
+        if self.vals is not None:
+            _on(self.vals, dev, "vals")
+            if self.vals.dtype not in (torch.float64, torch.float32):
+                raise ValueError(f"unsupported value type {self.vals.dtype}")
+            if self.vals.numel() != self.colidx.numel():
+                raise ValueError("vals and colidx differ in length")
+        if not (self.rowptr.is_contiguous() and self.colidx.is_contiguous()
+                and (self.vals is None or self.vals.is_contiguous())):
+            raise ValueError("CSR arrays must be contiguous")
         c = _lib.Csr()
         c.n = self.n
         c.nnz = self.nnz
@@ -145,14 +162,53 @@ class Rewrite:
     mt_ws: torch.Tensor | None = None
 
 
-def _block(B: torch.Tensor | None, n: int, dtype) -> tuple[torch.Tensor | None, int]:
+def _same_device(t: torch.Tensor, device) -> bool:
+    d = torch.device(device)
+    if t.device.type != d.type:
+        return False
+    if d.type == "cuda":
+        want = d.index if d.index is not None else torch.cuda.current_device()
+        have = t.device.index if t.device.index is not None else torch.cuda.current_device()
+        return want == have
+    return True
+
+
+def _on(t: torch.Tensor | None, device, what: str, dtype=None) -> torch.Tensor | None:
+    """Refuse, before any launch, a tensor that is not on the given device
+    (a host pointer handed to a kernel faults the GPU) or not of dtype."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what} must be a torch tensor")
+    if not _same_device(t, device):
+        raise ValueError(f"{what} is on {t.device}, expected {torch.device(device)}")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{what} has dtype {t.dtype}, expected {dtype}")
+    return t
+
+
+def _block(B: torch.Tensor | None, n: int, dtype, device,
+           what: str = "dense block") -> tuple[torch.Tensor | None, int]:
     if B is None:
         return None, 0
+    _on(B, device, what)
     if B.dim() == 1:
         B = B.reshape(1, -1)
-    if B.shape[-1] != n or B.dtype != dtype or not B.is_contiguous():
-        raise ValueError(f"dense block must be a contiguous (k, {n}) tensor of {dtype}")
+    if B.dim() != 2 or B.shape[-1] != n or B.dtype != dtype or not B.is_contiguous():
+        raise ValueError(f"{what} must be a contiguous (k, {n}) tensor of {dtype}")
     return B, B.shape[0]
+
+
+def _out_like(out: torch.Tensor | None, B2: torch.Tensor, what: str = "output") -> torch.Tensor:
+    """The output block: new, or the caller's, which must match B2 exactly
+    (shape, dtype, device, contiguity) since the kernels write it as B2."""
+    if out is None:
+        return torch.empty_like(B2)
+    _on(out, B2.device, what, B2.dtype)
+    X = out.reshape(B2.shape) if out.numel() == B2.numel() and out.is_contiguous() else out
+    if X.shape != B2.shape or not X.is_contiguous():
+        raise ValueError(f"{what} must be a contiguous tensor of the right-hand side's shape")
+    return X
 
 
 class Rewriter:
@@ -165,7 +221,11 @@ class Rewriter:
         n = L.n
         dev = L.device
         self.L = L
-        self.level = level
+        self.level = _on(level, dev, "level", torch.int32).contiguous()
+        if isinstance(rows, torch.Tensor):
+            _on(rows, dev, "rows")
+        if isinstance(targets, torch.Tensor):
+            _on(targets, dev, "targets")
         self.rows = torch.as_tensor(rows, dtype=torch.int32).to(dev).contiguous()
         self.m = self.rows.numel()
         self.targets = (None if targets is None else
@@ -191,9 +251,13 @@ class Rewriter:
     def numeric(self, vals: torch.Tensor | None = None,
                 B: torch.Tensor | None = None) -> torch.Tensor | None:
         """Fill L' values (in place) and the multipliers; return B' for B."""
+        if vals is not None:
+            _on(vals, self.L.device, "vals", self.L.dtype)
+            if vals.numel() != self.L.nnz:
+                raise ValueError(f"vals must hold {self.L.nnz} entries")
         L = self.L if vals is None else self.L.with_vals(vals.contiguous())
         n = L.n
-        B2, k = _block(B, n, L.dtype)
+        B2, k = _block(B, n, L.dtype, L.device)
         Bp = torch.empty((k, n), dtype=L.dtype, device=L.device) if B2 is not None else None
         lpv = _lib.Csr()
         lpv.n = n
@@ -239,12 +303,18 @@ def _option(table: dict, value, what: str) -> int:
 class Plan:
     """Analysis + schedule of one matrix; solves L X = B and L^T Y = G."""
 
+    # the C entry points of this kind of plan (UpperPlan substitutes its own)
+    _C = dict(ws="rwt_plan_ws", create="rwt_plan_create", info="rwt_plan_get_info",
+              levels="rwt_plan_levels", destroy="rwt_plan_destroy", solve="rwt_solve",
+              solve_t="rwt_solve_transpose", check="rwt_plan_check")
+
     def __init__(self, L: CSRMatrix, algo: str = "auto", kmax: int = 1, block_rows: int = 0,
                  lanes_per_row: int = 0, narrow_rows: int = -1, watchdog_ms: int = 0,
                  rhs_chunk: int = 0, stage_outside: str = "auto"):
         lib = _lib.load()
         self.L = L
         self._lib = lib
+        self._fn = {k: getattr(lib, v) for k, v in self._C.items()}
         o = _lib.PlanOpts()
         o.algo = _option(_lib.ALGO, algo, "algo")
         o.block_rows = block_rows
@@ -256,24 +326,25 @@ class Plan:
         o.stage_outside = _option(STAGE, stage_outside, "stage_outside")
         self.opts = o
         sz = C.c_size_t(0)
-        check(lib.rwt_plan_ws(C.byref(L.view()), C.byref(o), C.byref(sz)))
+        view = L.view()
+        check(self._fn["ws"](C.byref(view), C.byref(o), C.byref(sz)))
         self.ws = _workspace(sz.value, L.device)
         h = C.c_void_p()
-        check(lib.rwt_plan_create(C.byref(L.view()), C.byref(o), _ptr(self.ws), self.ws.numel(),
-                                  C.byref(h), _stream()))
+        check(self._fn["create"](C.byref(view), C.byref(o), _ptr(self.ws), self.ws.numel(),
+                                 C.byref(h), _stream()))
         self._h = h
         self.kmax = kmax
 
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            self._lib.rwt_plan_destroy(h)
+            self._fn["destroy"](h)
             self._h = None
 
     @property
     def info(self) -> dict:
         inf = _lib.PlanInfo()
-        check(self._lib.rwt_plan_get_info(self._h, C.byref(inf)))
+        check(self._fn["info"](self._h, C.byref(inf)))
         d = {f: getattr(inf, f) for f, _ in inf._fields_ if f not in ("stats", "pad_")}
         d["algo_fwd"] = _lib.ALGO_NAME[d["algo_fwd"]]
         d["algo_bwd"] = _lib.ALGO_NAME[d["algo_bwd"]]
@@ -282,9 +353,11 @@ class Plan:
         return d
 
     def levels(self) -> tuple[torch.Tensor, torch.Tensor, torch.Tensor]:
-        """(level[n], perm[n], level_ptr[D+1]) views into the plan's workspace."""
+        """(level[n], perm[n], level_ptr[D+1]) views into the plan's workspace
+        (for an UpperPlan: of the reversed matrix J U J, row i' = U's row
+        n-1-i')."""
         a, b, c = C.c_void_p(), C.c_void_p(), C.c_void_p()
-        check(self._lib.rwt_plan_levels(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        check(self._fn["levels"](self._h, C.byref(a), C.byref(b), C.byref(c)))
         n = self.L.n
         D = self.info["stats"]["num_levels"]
         base = self.ws.data_ptr()
@@ -295,22 +368,22 @@ class Plan:
         return view(a, n), view(b, n), view(c, D + 1)
 
     def _run(self, fn, B: torch.Tensor, out: torch.Tensor | None):
-        B2, k = _block(B, self.L.n, self.L.dtype)
-        X = torch.empty_like(B2) if out is None else out
-        if X.shape != B2.shape or not X.is_contiguous():
-            raise ValueError("output must match the right-hand side block")
+        B2, k = _block(B, self.L.n, self.L.dtype, self.L.device)
+        if k > self.kmax:
+            raise ValueError(f"{k} right-hand sides, the plan was made for at most {self.kmax}")
+        X = _out_like(out, B2)
         check(fn(self._h, _ptr(B2), k, self.L.n, _ptr(X), self.L.n, _stream()))
         return X.reshape(B.shape)
 
     def solve(self, B: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-        return self._run(self._lib.rwt_solve, B, out)
+        return self._run(self._fn["solve"], B, out)
 
     def solve_transpose(self, G: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-        return self._run(self._lib.rwt_solve_transpose, G, out)
+        return self._run(self._fn["solve_t"], G, out)
 
     def check(self) -> None:
         """Raise if a device wait expired in the last solve (synchronizes)."""
-        check(self._lib.rwt_plan_check(self._h, _stream()))
+        check(self._fn["check"](self._h, _stream()))
 
 
 def solve(L: CSRMatrix, B: torch.Tensor, plan: Plan | None = None,
@@ -328,65 +401,16 @@ def solve(L: CSRMatrix, B: torch.Tensor, plan: Plan | None = None,
 
 class UpperPlan(Plan):
     """Solves U X = B and U^T Y = G for an upper-triangular CSR U (diagonal
-    first in each row), through the reversed lower matrix J U J."""
+    first in each row), through the reversed lower matrix J U J; same
+    options as Plan."""
 
-    def __init__(self, U: CSRMatrix, algo: str = "auto", kmax: int = 1, block_rows: int = 0,
-                 lanes_per_row: int = 0, narrow_rows: int = -1, watchdog_ms: int = 0,
-                 rhs_chunk: int = 0, stage_outside: str = "auto"):
-        lib = _lib.load()
-        self.L = U
-        self._lib = lib
-        o = _lib.PlanOpts()
-        o.algo = _option(_lib.ALGO, algo, "algo")
-        o.block_rows = block_rows
-        o.lanes_per_row = lanes_per_row
-        o.narrow_rows = narrow_rows
-        o.kmax = kmax
-        o.watchdog_ms = watchdog_ms
-        o.rhs_chunk = rhs_chunk
-        o.stage_outside = _option(STAGE, stage_outside, "stage_outside")
-        self.opts = o
-        sz = C.c_size_t(0)
-        check(lib.rwt_upper_ws(C.byref(U.view()), C.byref(o), C.byref(sz)))
-        self.ws = _workspace(sz.value, U.device)
-        h = C.c_void_p()
-        check(lib.rwt_upper_create(C.byref(U.view()), C.byref(o), _ptr(self.ws),
-                                   self.ws.numel(), C.byref(h), _stream()))
-        self._h = h
-        self.kmax = kmax
-
-    def __del__(self):
-        h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            self._lib.rwt_upper_destroy(h)
-            self._h = None
-
-    @property
-    def info(self) -> dict:
-        inf = _lib.PlanInfo()
-        check(self._lib.rwt_upper_get_info(self._h, C.byref(inf)))
-        d = {f: getattr(inf, f) for f, _ in inf._fields_ if f not in ("stats", "pad_")}
-        d["algo_fwd"] = _lib.ALGO_NAME[d["algo_fwd"]]
-        d["algo_bwd"] = _lib.ALGO_NAME[d["algo_bwd"]]
-        d["stage_outside"] = STAGE_NAME[d["stage_outside"]]
-        d["stats"] = inf.stats.as_dict()
-        return d
-
-    def levels(self):
-        raise NotImplementedError("the levels of an upper plan belong to its reversed matrix")
+    _C = dict(ws="rwt_upper_ws", create="rwt_upper_create", info="rwt_upper_get_info",
+              levels="rwt_upper_levels", destroy="rwt_upper_destroy", solve="rwt_upper_solve",
+              solve_t="rwt_upper_solve_transpose", check="rwt_upper_check")
 
     def refresh(self) -> None:
         """Take U's current values (after they were changed in place)."""
         check(self._lib.rwt_upper_refresh(self._h, _stream()))
-
-    def solve(self, B: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-        return self._run(self._lib.rwt_upper_solve, B, out)
-
-    def solve_transpose(self, G: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-        return self._run(self._lib.rwt_upper_solve_transpose, G, out)
-
-    def check(self) -> None:
-        check(self._lib.rwt_upper_check(self._h, _stream()))
 
 
 def solve_pair(Lp: Plan, Up: UpperPlan, B: torch.Tensor,
@@ -394,10 +418,12 @@ def solve_pair(Lp: Plan, Up: UpperPlan, B: torch.Tensor,
     """X = U^{-1} (L^{-1} B): one application of the preconditioner M = L U."""
     lib = _lib.load()
     n = Lp.L.n
-    B2, k = _block(B, n, Lp.L.dtype)
-    X = torch.empty_like(B2) if out is None else out
-    if X.shape != B2.shape or not X.is_contiguous():
-        raise ValueError("output must match the right-hand side block")
+    if Up.L.n != n or Up.L.dtype != Lp.L.dtype or not _same_device(Up.L.rowptr, Lp.L.device):
+        raise ValueError("the lower and upper plans differ in size, value type or device")
+    B2, k = _block(B, n, Lp.L.dtype, Lp.L.device)
+    if k > min(Lp.kmax, Up.kmax):
+        raise ValueError(f"{k} right-hand sides, the plans allow {min(Lp.kmax, Up.kmax)}")
+    X = _out_like(out, B2)
     check(lib.rwt_solve_pair(Lp._h, Up._h, _ptr(B2), k, n, _ptr(X), n, _stream()))
     return X.reshape(B.shape)
 
@@ -406,7 +432,7 @@ def apply_MT(rw: Rewrite, Y: torch.Tensor) -> torch.Tensor:
     """Y - C^T Y for the multipliers of a rewrite (grad_B of the rewritten system)."""
     lib = _lib.load()
     n = rw.L.n
-    Y2, k = _block(Y, n, rw.L.dtype)
+    Y2, k = _block(Y, n, rw.L.dtype, rw.L.device)
     nc = rw.crow.numel()
     if rw.mt_ws is None:
         sz = C.c_size_t(0)
@@ -425,7 +451,7 @@ def apply_M(rw: Rewrite, B: torch.Tensor) -> torch.Tensor:
     """M B = B - C B: the right-hand side of the rewritten system for a new B."""
     lib = _lib.load()
     n = rw.L.n
-    B2, k = _block(B, n, rw.L.dtype)
+    B2, k = _block(B, n, rw.L.dtype, rw.L.device)
     sz = C.c_size_t(0)
     check(lib.rwt_apply_M_ws(n, C.byref(sz)))
     ws = _workspace(sz.value, B.device)
@@ -439,14 +465,19 @@ def apply_M(rw: Rewrite, B: torch.Tensor) -> torch.Tensor:
 def grad_vals(L: CSRMatrix, gB: torch.Tensor, X: torch.Tensor) -> torch.Tensor:
     """-sum_q gB[row_p, q] * X[col_p, q] on every stored entry of L."""
     lib = _lib.load()
-    gB2, k = _block(gB, L.n, L.dtype)
-    X2, k2 = _block(X, L.n, L.dtype)
+    gB2, k = _block(gB, L.n, L.dtype, L.device, "gB")
+    X2, k2 = _block(X, L.n, L.dtype, L.device, "X")
     if k != k2:
         raise ValueError("gB and X must have the same number of columns")
     out = torch.empty(L.nnz, dtype=L.dtype, device=L.device)
     check(lib.rwt_grad_vals(C.byref(L.view()), _ptr(gB2), L.n, _ptr(X2), L.n, k, _ptr(out),
                             _stream()))
     return out
+
+
+def _check_info(info: "LevelInfo", device) -> None:
+    for name in ("level", "level_ptr", "cost", "device_stats"):
+        _on(getattr(info, name), device, f"analysis array {name}")
 
 
 GEN_STOPS = {0: "no_source", 1: "thin", 2: "moves", 3: "steps"}
@@ -483,6 +514,7 @@ def generate(L: CSRMatrix, info: LevelInfo, params, cap: int, level_sums: bool =
     ne = len(params)
     n, D = L.n, info.num_levels
     dev = L.device
+    _check_info(info, dev)
     sz = C.c_size_t(0)
     check(lib.rwt_generate_ws(n, D, ne, C.byref(sz)))
     ws = _workspace(sz.value, dev)
@@ -564,6 +596,7 @@ class Env:
             cap = min(self.n, steps)
         self.cap = int(cap)
         self.device = L.device
+        _check_info(info, self.device)
         sz = C.c_size_t(0)
         check(self.lib.rwt_env_ws(self.n, self.D, self.E, self.cap, C.byref(sz)))
         self.ws = _workspace(sz.value, self.device)
@@ -680,8 +713,10 @@ class Batch:
             arr[i].L = L.view()
             k = 0
             if B is not None:
-                B2, k = _block(B, L.n, L.dtype)
-                X2, k2 = _block(X, L.n, L.dtype)
+                if not _same_device(L.rowptr, dev):
+                    raise ValueError(f"matrix {i} is on {L.device}, the batch on {dev}")
+                B2, k = _block(B, L.n, L.dtype, dev, f"B of matrix {i}")
+                X2, k2 = _block(X, L.n, L.dtype, dev, f"X of matrix {i}")
                 if k != k2:
                     raise ValueError("B and X must have the same number of columns")
                 arr[i].B = B2.data_ptr()
@@ -741,6 +776,20 @@ class Batch:
         check(self._lib.rwt_batch_run(self._h, self.stream.cuda_stream))
         self._leave()
 
+    def run_timed(self) -> tuple:
+        """Enqueue one batched launch with events around its persistent
+        kernel, recorded on the batch's stream: (start, end) events of
+        the persistent kernel alone (the setup kernels run before)."""
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        self._enter()
+        check(self._lib.rwt_batch_run_setup(self._h, self.stream.cuda_stream))
+        a.record(self.stream)
+        check(self._lib.rwt_batch_run_main(self._h, self.stream.cuda_stream))
+        b.record(self.stream)
+        self._leave()
+        return a, b
+
     def capture(self) -> None:
         """Capture the launch sequence into a graph (replayed by launch())."""
         self._enter()
@@ -782,8 +831,8 @@ class Batch:
                 continue
             p = C.c_void_p()
             check(self._lib.rwt_batch_plan(self._h, m, C.byref(p)))
-            B2, k = _block(B, L.n, L.dtype)
-            X2, _ = _block(X, L.n, L.dtype)
+            B2, k = _block(B, L.n, L.dtype, L.device)
+            X2, _ = _block(X, L.n, L.dtype, L.device)
             check(self._lib.rwt_solve(p, _ptr(B2), k, L.n, _ptr(X2), L.n, self.stream.cuda_stream))
         self._leave()
 

@@ -6,6 +6,7 @@ import os
 import shutil
 import subprocess
 import sys
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -25,23 +26,47 @@ def sources() -> list[str]:
 
 
 def build(verbose: bool = False, jobs: int = 8) -> str:
-    """Compile every source (in parallel) and link the shared library."""
+    """Compile every source (at most `jobs` compilers at once) and link the
+    shared library, with the hash of the sources compiled in."""
+    try:
+        from ._srchash import source_hash
+    except ImportError:            # run as a script
+        sys.path.insert(0, HERE)
+        from _srchash import source_hash
     os.makedirs(BUILD, exist_ok=True)
-    procs = []
+    digest = source_hash(FLAGS)
+    defs = [f'-DRWT_SOURCE_HASH="{digest}"']
+    running = []
+    done = []
     objs = []
+
+    def reap(block: bool) -> None:
+        while running:
+            for item in list(running):
+                if item[1].poll() is not None:
+                    running.remove(item)
+                    done.append(item)
+            if not block or len(running) < jobs:
+                return
+            running[0][1].wait()
+
     for src in sources():
         obj = os.path.join(BUILD, os.path.basename(src) + ".o")
         objs.append(obj)
-        cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+        cmd = [HIPCC, *FLAGS, *defs, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
-        if len([p for _, p in procs if p.poll() is None]) >= jobs:
-            procs[0][1].wait()
+        reap(block=True)   # wait until fewer than `jobs` compilers run
+        log = tempfile.TemporaryFile()
+        running.append((src, subprocess.Popen(cmd, stdout=log, stderr=subprocess.STDOUT), log))
+    for item in running:
+        item[1].wait()
+    done.extend(running)
     failed = []
-    for src, p in procs:
-        out, _ = p.communicate()
-        text = out.decode(errors="replace")
+    for src, p, log in done:
+        log.seek(0)
+        text = log.read().decode(errors="replace")
+        log.close()
         lines = [l for l in text.splitlines()
                  if "packed-fp32-ops" not in l and "warning generated" not in l]
         if p.returncode != 0:

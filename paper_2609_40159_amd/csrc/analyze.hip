@@ -738,7 +738,11 @@ using namespace rwt;
 
 extern "C" const char* rwt_last_error_string(void) { return g_err; }
 extern "C" int rwt_last_hip_error(void) { return g_hip_err; }
-extern "C" const char* rwt_version(void) { return "rwtrsv 0.2 gfx950"; }
+#ifndef RWT_SOURCE_HASH
+#define RWT_SOURCE_HASH "unknown"
+#endif
+extern "C" const char* rwt_version(void) { return "rwtrsv 0.3 gfx950"; }
+extern "C" const char* rwt_source_hash(void) { return RWT_SOURCE_HASH; }
 
 static rwt_status check_csr(const rwt_csr* L, bool need_vals) {
     RWT_REQUIRE(L != nullptr, RWT_ERR_INVALID_ARG, "L is NULL");

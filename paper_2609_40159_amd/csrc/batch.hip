@@ -596,6 +596,7 @@ __global__ void __launch_bounds__(BT_THREADS) k_batch_main(BatchKArgs a) {
             b.err = &a.ctrl->err;
             b.ticks = a.ticks;
             b.lds_rows = M.R;
+            b.hold_row = -1;
             if (M.kc == 1) sf_block<double, false, 1>(b, s_raw);
             else sf_block<double, false, 4>(b, s_raw);
         } else if (tk.x == 2) {
@@ -895,7 +896,18 @@ P* at(void* base, size_t off) {
     return reinterpret_cast<P*>(static_cast<char*>(base) + off);
 }
 
-rwt_status enqueue_run(rwt_batch* b, hipStream_t s) {
+rwt_status enqueue_setup(rwt_batch* b, hipStream_t s);
+rwt_status enqueue_main(rwt_batch* b, hipStream_t s);
+
+rwt_status enqueue_run(rwt_batch* b, hipStream_t s, bool setup = true, bool main = true);
+
+rwt_status enqueue_run(rwt_batch* b, hipStream_t s, bool setup, bool main) {
+    if (setup) RWT_TRY(enqueue_setup(b, s));
+    if (main) RWT_TRY(enqueue_main(b, s));
+    return RWT_OK;
+}
+
+rwt_status enqueue_setup(rwt_batch* b, hipStream_t s) {
     const rwt_batch_desc& d = b->desc;
     const int32_t C = d.num_cand;
     hipLaunchKernelGGL(k_batch_epoch, dim3(1), dim3(64), 0, s, b->epoch);
@@ -941,6 +953,12 @@ rwt_status enqueue_run(rwt_batch* b, hipStream_t s) {
         RWT_TRY(scan_exclusive(b->counts_q, b->pat_ptr, b->qcap, b->scan_ws, s));
         RWT_TRY(batch_rewrite_pass(ra, 2, s));
     }
+    return RWT_OK;
+}
+
+rwt_status enqueue_main(rwt_batch* b, hipStream_t s) {
+    const rwt_batch_desc& d = b->desc;
+    const int32_t C = d.num_cand;
     BatchKArgs ka;
     ka.mats = b->d_mats;
     ka.cands = b->d_cands;
@@ -1251,6 +1269,16 @@ extern "C" rwt_status rwt_batch_create(const rwt_batch_desc* desc, void* d_ws, s
 extern "C" rwt_status rwt_batch_run(rwt_batch* b, rwt_stream_t stream) {
     RWT_REQUIRE(b != nullptr, RWT_ERR_INVALID_ARG, "null batch");
     return enqueue_run(b, hs(stream));
+}
+
+extern "C" rwt_status rwt_batch_run_setup(rwt_batch* b, rwt_stream_t stream) {
+    RWT_REQUIRE(b != nullptr, RWT_ERR_INVALID_ARG, "null batch");
+    return enqueue_setup(b, hs(stream));
+}
+
+extern "C" rwt_status rwt_batch_run_main(rwt_batch* b, rwt_stream_t stream) {
+    RWT_REQUIRE(b != nullptr, RWT_ERR_INVALID_ARG, "null batch");
+    return enqueue_main(b, hs(stream));
 }
 
 extern "C" rwt_status rwt_batch_capture(rwt_batch* b, rwt_stream_t stream) {

@@ -260,14 +260,17 @@ SolveArgs make_args(const rwt_plan* p) {
     a.stage_x = p->stage_x == 1;
     a.ctrl = p->ctrl;
     a.ticks = watchdog_ticks(p->opts.watchdog_ms);
+    a.hold_row = -1;
     return a;
 }
 
 // rows > 0: solve only the leading rows x rows block (a forward sync-free
 // solve of whole row blocks; used by the autotuner)
 rwt_status run_solve(const rwt_plan* p, bool transposed, Algo algo, const void* B, int32_t k,
-                     int64_t ldb, void* X, int64_t ldx, hipStream_t s, int32_t rows = 0) {
+                     int64_t ldb, void* X, int64_t ldx, hipStream_t s, int32_t rows = 0,
+                     int32_t hold_row = -1) {
     SolveArgs a = make_args(p);
+    a.hold_row = hold_row;
     if (rows > 0 && rows < a.n) {
         a.n = rows;
         a.nblocks = (rows + p->R - 1) / p->R;
@@ -622,7 +625,8 @@ extern "C" rwt_status rwt_plan_destroy(rwt_plan* p) {
 }
 
 static rwt_status solve_common(const rwt_plan* p, bool transposed, const void* B, int32_t k,
-                               int64_t ldb, void* X, int64_t ldx, rwt_stream_t stream) {
+                               int64_t ldb, void* X, int64_t ldx, rwt_stream_t stream,
+                               int32_t hold_row = -1) {
     RWT_REQUIRE(p != nullptr, RWT_ERR_INVALID_ARG, "null plan");
     RWT_REQUIRE(k >= 0 && k <= p->opts.kmax, RWT_ERR_INVALID_ARG, "k=%d outside [0, kmax=%d]", k,
                 p->opts.kmax);
@@ -631,7 +635,7 @@ static rwt_status solve_common(const rwt_plan* p, bool transposed, const void* B
     RWT_REQUIRE(ldb >= p->L.n && ldx >= p->L.n, RWT_ERR_INVALID_ARG, "leading dimension < n");
     if (k == 0 || p->L.n == 0) return RWT_OK;
     Algo algo = transposed ? p->bwd : p->fwd;
-    return run_solve(p, transposed, algo, B, k, ldb, X, ldx, hs(stream));
+    return run_solve(p, transposed, algo, B, k, ldb, X, ldx, hs(stream), 0, hold_row);
 }
 
 extern "C" rwt_status rwt_solve(const rwt_plan* p, const void* d_B, int32_t k, int64_t ldb,
@@ -643,6 +647,15 @@ extern "C" rwt_status rwt_solve_transpose(const rwt_plan* p, const void* d_G, in
                                           int64_t ldg, void* d_Y, int64_t ldy,
                                           rwt_stream_t stream) {
     return solve_common(p, true, d_G, k, ldg, d_Y, ldy, stream);
+}
+
+extern "C" rwt_status rwt_solve_withhold(const rwt_plan* p, int32_t row, const void* d_B,
+                                         int32_t k, int64_t ldb, void* d_X, int64_t ldx,
+                                         rwt_stream_t stream) {
+    RWT_REQUIRE(p != nullptr, RWT_ERR_INVALID_ARG, "null plan");
+    RWT_REQUIRE(row >= 0 && row < p->L.n, RWT_ERR_INVALID_ARG, "row %d outside [0, %d)", row,
+                p->L.n);
+    return solve_common(p, false, d_B, k, ldb, d_X, ldx, stream, row);
 }
 
 extern "C" rwt_status rwt_plan_check(const rwt_plan* p, rwt_stream_t stream) {

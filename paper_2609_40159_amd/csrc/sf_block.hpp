@@ -46,6 +46,7 @@ struct SfBlockArgs {
     int32_t* err;
     int64_t ticks;
     int32_t lds_rows;        // rows the LDS x area is laid out for
+    int32_t hold_row;        // >= 0: never publish this row to X (forces the watchdog path)
 };
 
 __host__ __device__ inline int sf_x_bytes(int rows, int k, int s) { return (rows * k * s + 15) & ~15; }
@@ -217,7 +218,7 @@ __device__ __forceinline__ void sf_block(const SfBlockArgs& b, unsigned char* s_
                     if (KT == 1 || q < k) {
                         T xi = (bq[tt] - acc[tt]) / e.diag;
                         xs[(d.i - r0) * k + q] = xi;
-                        st_relaxed(&X[d.i + (int64_t)q * b.ldx], xi);
+                        if (d.i != b.hold_row) st_relaxed(&X[d.i + (int64_t)q * b.ldx], xi);
                     }
                 }
             }
@@ -256,7 +257,8 @@ __device__ __forceinline__ void sf_block(const SfBlockArgs& b, unsigned char* s_
         if (pend) {
 #pragma unroll
             for (int tt = 0; tt < KT; ++tt)
-                if (KT == 1 || tt < k) st_relaxed(&X[pend_i + (int64_t)tt * b.ldx], pend_x[tt]);
+                if ((KT == 1 || tt < k) && pend_i != b.hold_row)
+                    st_relaxed(&X[pend_i + (int64_t)tt * b.ldx], pend_x[tt]);
             pend = false;
         }
         // (3)
@@ -316,7 +318,8 @@ __device__ __forceinline__ void sf_block(const SfBlockArgs& b, unsigned char* s_
     if (pend) {
 #pragma unroll
         for (int tt = 0; tt < KT; ++tt)
-            if (KT == 1 || tt < k) st_relaxed(&X[pend_i + (int64_t)tt * b.ldx], pend_x[tt]);
+            if ((KT == 1 || tt < k) && pend_i != b.hold_row)
+                st_relaxed(&X[pend_i + (int64_t)tt * b.ldx], pend_x[tt]);
     }
     __syncthreads();
 }

@@ -245,7 +245,7 @@ __device__ __forceinline__ void sf_block_staged(const SfBlockArgs& b, unsigned c
                         T* xi = &xs[(row.i - r0) * k + q];
                         const T xv = (*xi - acc[q]) / row.diag;
                         *xi = xv;
-                        st_relaxed(&X[row.i + (int64_t)q * b.ldx], xv);
+                        if (row.i != b.hold_row) st_relaxed(&X[row.i + (int64_t)q * b.ldx], xv);
                     }
             }
             // rows of this step beyond the staged ones: direct loads, and
@@ -285,7 +285,7 @@ __device__ __forceinline__ void sf_block_staged(const SfBlockArgs& b, unsigned c
                             T* xi = &xs[(i - r0) * k + q];
                             const T xv = (*xi - a2c[q]) / dg;
                             *xi = xv;
-                            st_relaxed(&X[i + (int64_t)q * b.ldx], xv);
+                            if (i != b.hold_row) st_relaxed(&X[i + (int64_t)q * b.ldx], xv);
                         }
                 }
             }

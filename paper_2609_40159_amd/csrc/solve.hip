@@ -89,7 +89,7 @@ __device__ __forceinline__ void solve_row(const SolveArgs& a, bool active, int32
                 if (KT == 1 || q < a.k) {
                     T xi = (B[i + (int64_t)q * a.ldb] - acc[t]) / diag;
                     if (LOCAL) xs[(int64_t)(i - r0) * a.k + q] = xi;
-                    st_relaxed(&X[i + (int64_t)q * a.ldx], xi);
+                    if (i != a.hold_row) st_relaxed(&X[i + (int64_t)q * a.ldx], xi);
                 }
             }
         }
@@ -218,6 +218,7 @@ __global__ void __launch_bounds__(SV_THREADS) k_solve_sf(SolveArgs a) {
     b.err = &a.ctrl->err;
     b.ticks = a.ticks;
     b.lds_rows = a.block_rows;
+    b.hold_row = a.hold_row;
     // tasks: (row block, column chunk) with the chunks of one block on
     // consecutive tickets; each chunk's blocks follow row order (reverse for
     // the transposed solve), so a task waits only on earlier tickets

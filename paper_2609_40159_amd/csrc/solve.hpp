@@ -38,6 +38,7 @@ struct SolveArgs {
     int32_t lds_bytes;         // sync-free: dynamic LDS per workgroup
     Ctrl* ctrl;
     int64_t ticks;
+    int32_t hold_row;          // >= 0: this row's values are never published (watchdog test)
 };
 
 enum class Algo { Level, SyncFree };

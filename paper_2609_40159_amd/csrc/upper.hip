@@ -287,6 +287,12 @@ static rwt_status upper_run(const rwt_upper* up, bool transposed, const void* d_
     return rev_inplace(d_X, ldx, n, k, up->U.dt, s);
 }
 
+extern "C" rwt_status rwt_upper_levels(const rwt_upper* up, const int32_t** d_level,
+                                       const int32_t** d_perm, const int32_t** d_level_ptr) {
+    RWT_REQUIRE(up != nullptr, RWT_ERR_INVALID_ARG, "null upper plan");
+    return rwt_plan_levels(up->plan, d_level, d_perm, d_level_ptr);
+}
+
 extern "C" rwt_status rwt_upper_solve(const rwt_upper* up, const void* d_B, int32_t k, int64_t ldb,
                                       void* d_X, int64_t ldx, rwt_stream_t stream) {
     return upper_run(up, false, d_B, k, ldb, d_X, ldx, stream);
