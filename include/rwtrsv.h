@@ -100,8 +100,8 @@ const char* rwt_last_error_string(void);
 int rwt_last_hip_error(void);
 /* "rwtrsv <major>.<minor> gfx950"; 0.2 added rwt_plan_opts.stage_outside
  * and rwt_plan_info.stage_outside (callers built against 0.1 must rebuild);
- * 0.3 added rwt_upper_levels, rwt_solve_withhold, rwt_batch_run_setup/_main
- * and rwt_source_hash */
+ * 0.3 added rwt_upper_levels, rwt_solve_withhold, rwt_batch_run_setup/_main,
+ * rwt_source_hash and rwt_apply_M_noalloc */
 const char* rwt_version(void);
 /* 16 hex digits identifying the sources and flags the library was built
  * from ("unknown" when the build did not say) */
@@ -370,6 +370,23 @@ rwt_status rwt_apply_M(int32_t n, int64_t nC, const int32_t* d_crow, const int32
                        const void* d_cval, rwt_dtype dt, const void* d_B, int32_t k,
                        int64_t ldb, void* d_out, int64_t ldo, void* d_ws, size_t ws_bytes,
                        rwt_stream_t stream);
+/* rwt_apply_M_noalloc: rwt_apply_M for callers that cannot allocate device
+ * memory or pass a workspace (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation).  Same arguments, result and
+ * errors as rwt_apply_M, without d_ws: the multipliers' row offsets go to a
+ * library-owned device array of RWT_APPLY_M_NOALLOC_MAX_N + 1 int32 entries
+ * (16 MiB, one copy per GPU the library runs on, held until the process
+ * ends; its device address is looked up on the first call on each device,
+ * which must be the current device).  n above RWT_APPLY_M_NOALLOC_MAX_N
+ * returns RWT_ERR_TOO_LARGE before any launch.  Every call on one GPU uses
+ * that GPU's one array: calls that overlap on one GPU (other streams, other
+ * host threads) race and must be serialized by the caller.  Nothing is
+ * allocated or freed by the call. */
+#define RWT_APPLY_M_NOALLOC_MAX_N (1 << 22)
+rwt_status rwt_apply_M_noalloc(int32_t n, int64_t nC, const int32_t* d_crow,
+                               const int32_t* d_ccol, const void* d_cval, rwt_dtype dt,
+                               const void* d_B, int32_t k, int64_t ldb, void* d_out, int64_t ldo,
+                               rwt_stream_t stream);
 rwt_status rwt_apply_MT_ws(int32_t n, int64_t nC, size_t* h_bytes);
 rwt_status rwt_apply_MT(int32_t n, int64_t nC, const int32_t* d_crow, const int32_t* d_ccol,
                         const void* d_cval, rwt_dtype dt, const void* d_Y, int32_t k, int64_t ldy,

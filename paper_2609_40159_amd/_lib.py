@@ -130,6 +130,8 @@ P = C.c_void_p
 I32 = C.c_int32
 I64 = C.c_int64
 SZ = C.c_size_t
+# largest n of rwt_apply_M_noalloc (RWT_APPLY_M_NOALLOC_MAX_N)
+APPLY_M_NOALLOC_MAX_N = 1 << 22
 
 # name -> (restype, argtypes); every symbol include/rwtrsv.h declares
 SIGNATURES = {
@@ -163,6 +165,7 @@ SIGNATURES = {
     "rwt_grad_vals": (C.c_int, [C.POINTER(Csr), P, I64, P, I64, I32, P, P]),
     "rwt_apply_M_ws": (C.c_int, [I32, C.POINTER(SZ)]),
     "rwt_apply_M": (C.c_int, [I32, I64, P, P, P, I32, P, I32, I64, P, I64, P, SZ, P]),
+    "rwt_apply_M_noalloc": (C.c_int, [I32, I64, P, P, P, I32, P, I32, I64, P, I64, P]),
     "rwt_batch_ws": (C.c_int, [C.POINTER(BatchDesc), C.POINTER(SZ)]),
     "rwt_batch_create": (C.c_int, [C.POINTER(BatchDesc), P, SZ, C.POINTER(P), P]),
     "rwt_batch_run": (C.c_int, [P, P]),

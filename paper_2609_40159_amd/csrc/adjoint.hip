@@ -4,6 +4,9 @@
 //   grad_L = -grad_B X^T on the stored pattern of L.
 // C^T is built with the stable radix sort so every sum runs in a fixed
 // order: the results do not depend on the schedule.
+#include <mutex>
+#include <vector>
+
 #include "prim.hpp"
 #include "rowmap.hpp"
 
@@ -196,10 +199,10 @@ extern "C" rwt_status rwt_apply_M_ws(int32_t n, size_t* h_bytes) {
     return RWT_OK;
 }
 
-extern "C" rwt_status rwt_apply_M(int32_t n, int64_t nC, const int32_t* d_crow,
-                                  const int32_t* d_ccol, const void* d_cval, rwt_dtype dt,
-                                  const void* d_B, int32_t k, int64_t ldb, void* d_out,
-                                  int64_t ldo, void* d_ws, size_t ws_bytes, rwt_stream_t stream) {
+static rwt_status apply_m_checks(int32_t n, int64_t nC, const int32_t* d_crow,
+                                 const int32_t* d_ccol, const void* d_cval, rwt_dtype dt,
+                                 const void* d_B, int32_t k, int64_t ldb, void* d_out,
+                                 int64_t ldo) {
     RWT_REQUIRE(n >= 0 && nC >= 0 && k >= 0, RWT_ERR_INVALID_ARG, "negative size");
     RWT_REQUIRE(nC < (int64_t(1) << 31), RWT_ERR_TOO_LARGE, "too many multipliers");
     RWT_REQUIRE(dt == RWT_F64 || dt == RWT_F32, RWT_ERR_INVALID_ARG, "bad dtype");
@@ -207,13 +210,13 @@ extern "C" rwt_status rwt_apply_M(int32_t n, int64_t nC, const int32_t* d_crow,
     RWT_REQUIRE(k == 0 || n == 0 || (d_B && d_out && ldb >= n && ldo >= n), RWT_ERR_INVALID_ARG,
                 "bad dense blocks");
     RWT_REQUIRE(k == 0 || n == 0 || d_B != d_out, RWT_ERR_INVALID_ARG, "output may not alias B");
-    size_t need = 0;
-    RWT_TRY(rwt_apply_M_ws(n, &need));
-    RWT_REQUIRE(d_ws && ws_bytes >= need, RWT_ERR_BUFFER_TOO_SMALL,
-                "apply_M workspace must hold %zu bytes", need);
-    if (n == 0 || k == 0) return RWT_OK;
-    hipStream_t s = hs(stream);
-    int32_t* ptr = static_cast<int32_t*>(d_ws);
+    return RWT_OK;
+}
+
+// M B with the row offsets of the multipliers built in ptr[n+1] (device)
+static rwt_status apply_m_run(int32_t n, int64_t nC, const int32_t* d_crow, const int32_t* d_ccol,
+                              const void* d_cval, rwt_dtype dt, const void* d_B, int32_t k,
+                              int64_t ldb, void* d_out, int64_t ldo, int32_t* ptr, hipStream_t s) {
     // the multipliers come grouped by row, rows ascending (rwt_rewrite_numeric)
     RWT_TRY(segment_starts(reinterpret_cast<const uint32_t*>(d_crow), nC, n, ptr, nullptr, s));
     const unsigned g = blocks_for((size_t)n * k, 256, 8192);
@@ -227,6 +230,66 @@ extern "C" rwt_status rwt_apply_M(int32_t n, int64_t nC, const int32_t* d_crow,
                            static_cast<float*>(d_out), ldo, n, k);
     RWT_LAUNCHED();
     return RWT_OK;
+}
+
+extern "C" rwt_status rwt_apply_M(int32_t n, int64_t nC, const int32_t* d_crow,
+                                  const int32_t* d_ccol, const void* d_cval, rwt_dtype dt,
+                                  const void* d_B, int32_t k, int64_t ldb, void* d_out,
+                                  int64_t ldo, void* d_ws, size_t ws_bytes, rwt_stream_t stream) {
+    RWT_TRY(apply_m_checks(n, nC, d_crow, d_ccol, d_cval, dt, d_B, k, ldb, d_out, ldo));
+    size_t need = 0;
+    RWT_TRY(rwt_apply_M_ws(n, &need));
+    RWT_REQUIRE(d_ws && ws_bytes >= need, RWT_ERR_BUFFER_TOO_SMALL,
+                "apply_M workspace must hold %zu bytes", need);
+    if (n == 0 || k == 0) return RWT_OK;
+    return apply_m_run(n, nC, d_crow, d_ccol, d_cval, dt, d_B, k, ldb, d_out, ldo,
+                       static_cast<int32_t*>(d_ws), hs(stream));
+}
+
+// ---------------------------------------------------------------------------
+// rwt_apply_M without a workspace: the row offsets live in a file-scope
+// device array.  Host code never passes the array's name to a kernel (on the
+// host it is only a stand-in for the symbol); the device address of each
+// GPU's copy is looked up once per device and kept.
+// ---------------------------------------------------------------------------
+__device__ __align__(256) int32_t scratch[RWT_APPLY_M_NOALLOC_MAX_N + 1];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<int32_t*> g_scratch_ptr;   // per device ordinal; nullptr until looked up
+
+rwt_status scratch_for_current_device(int32_t** out) {
+    int dev = -1;
+    RWT_HIP(hipGetDevice(&dev));
+    RWT_REQUIRE(dev >= 0, RWT_ERR_INVALID_ARG, "no current device");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr.size() <= (size_t)dev) g_scratch_ptr.resize((size_t)dev + 1, nullptr);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void* p = nullptr;
+        RWT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        RWT_REQUIRE(p != nullptr, RWT_ERR_HIP, "no device address for the apply_M scratch array");
+        g_scratch_ptr[dev] = static_cast<int32_t*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return RWT_OK;
+}
+}  // namespace
+
+extern "C" rwt_status rwt_apply_M_noalloc(int32_t n, int64_t nC, const int32_t* d_crow,
+                                          const int32_t* d_ccol, const void* d_cval, rwt_dtype dt,
+                                          const void* d_B, int32_t k, int64_t ldb, void* d_out,
+                                          int64_t ldo, rwt_stream_t stream) {
+    RWT_TRY(apply_m_checks(n, nC, d_crow, d_ccol, d_cval, dt, d_B, k, ldb, d_out, ldo));
+    RWT_REQUIRE(n <= RWT_APPLY_M_NOALLOC_MAX_N, RWT_ERR_TOO_LARGE,
+                "apply_M_noalloc handles at most %d rows (n = %d); use rwt_apply_M",
+                (int)RWT_APPLY_M_NOALLOC_MAX_N, (int)n);
+    int32_t* ptr = nullptr;
+    RWT_TRY(scratch_for_current_device(&ptr));
+    if (n == 0 || k == 0) return RWT_OK;
+    // every entry ptr[0..n] is rewritten by the segment-start kernel before
+    // the product reads it, so nothing left by an earlier call is read
+    return apply_m_run(n, nC, d_crow, d_ccol, d_cval, dt, d_B, k, ldb, d_out, ldo, ptr,
+                       hs(stream));
 }
 
 extern "C" rwt_status rwt_grad_vals(const rwt_csr* L, const void* d_gB, int64_t ldg,
