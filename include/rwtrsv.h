@@ -190,8 +190,17 @@ rwt_status rwt_rewrite_numeric(const rwt_csr* L, const int32_t* d_level,
  *                     dependencies outside the block; k right-hand sides
  *                     are split into chains of rhs_chunk columns that run
  *                     concurrently (each chain is a full sync-free solve);
- *   RWT_ALGO_AUTO     autotuned: both candidates are timed on the plan's
- *                     matrix and the faster kept.
+ *   RWT_ALGO_WALK     row-order walk (a synchronization-free schedule): one
+ *                     wavefront per right-hand-side column solves the rows
+ *                     in order, 64 at a time, resolving the dependencies
+ *                     inside each chunk of 64 rows in rounds of register
+ *                     ballots, one per link of the chunk's longest internal
+ *                     dependency chain; suits deep DAGs whose consecutive
+ *                     rows seldom depend on each other (the plan reports
+ *                     the mean rounds per chunk in rwt_plan_info.chunk_rounds);
+ *   RWT_ALGO_AUTO     autotuned: level-scheduled and sync-free are timed on
+ *                     the plan's matrix, and the walk too when the chunks
+ *                     need at most 12 rounds on average; the fastest is kept.
  * Unless fixed by the options, the sync-free block size, RHS chunk and
  * staging of outside values are chosen by timing solves on the plan's own
  * matrix (min(kmax, 64) columns).
@@ -199,7 +208,12 @@ rwt_status rwt_rewrite_numeric(const rwt_csr* L, const int32_t* d_level,
  * alive and may change the values between solves.  The plan's device
  * state lives in the caller's workspace (rwt_plan_ws bytes).
  * ---------------------------------------------------------------------- */
-typedef enum { RWT_ALGO_AUTO = 0, RWT_ALGO_LEVEL = 1, RWT_ALGO_SYNCFREE = 2 } rwt_algo;
+typedef enum {
+    RWT_ALGO_AUTO = 0,
+    RWT_ALGO_LEVEL = 1,
+    RWT_ALGO_SYNCFREE = 2,
+    RWT_ALGO_WALK = 3
+} rwt_algo;
 
 typedef struct {
     rwt_algo algo;            /* forward and transposed solves */
@@ -230,6 +244,8 @@ typedef struct {
     int32_t stage_outside;    /* 1 or 2, as in rwt_plan_opts: what the plan uses */
     double tuned_ms_level;    /* autotuner measurements (0 when not tuned) */
     double tuned_ms_syncfree;
+    double tuned_ms_walk;
+    double chunk_rounds;      /* mean over 64-row chunks of the rounds the walk needs */
 } rwt_plan_info;
 
 rwt_status rwt_plan_ws(const rwt_csr* L, const rwt_plan_opts* opts, size_t* h_bytes);
@@ -705,7 +721,8 @@ typedef struct {
     int32_t pattern_cap;                /* capacity of rewritten-row patterns (0: 64 per row) */
     int32_t watchdog_ms;
     int32_t cand_mode;                  /* candidate levels: 0 choose per matrix, 1 row-block
-                                           chains, 2 one level sweep per candidate */
+                                           chains, 2 one level sweep per candidate, 3 the
+                                           row-order walk (one wave per candidate) */
 } rwt_batch_desc;
 
 typedef struct {

@@ -18,7 +18,7 @@ STATUS = {
     -10: "HIP",
 }
 F64, F32 = 0, 1
-ALGO = {"auto": 0, "level": 1, "syncfree": 2}
+ALGO = {"auto": 0, "level": 1, "syncfree": 2, "walk": 3}
 ALGO_NAME = {v: k for k, v in ALGO.items()}
 
 
@@ -61,7 +61,8 @@ class PlanInfo(C.Structure):
                 ("narrow_rows", C.c_int32), ("num_blocks", C.c_int32), ("grid", C.c_int32),
                 ("rhs_chunk", C.c_int32), ("stage_outside", C.c_int32),
                 ("tuned_ms_level", C.c_double),
-                ("tuned_ms_syncfree", C.c_double)]
+                ("tuned_ms_syncfree", C.c_double), ("tuned_ms_walk", C.c_double),
+                ("chunk_rounds", C.c_double)]
 
 
 class BatchMatrix(C.Structure):

@@ -744,7 +744,7 @@ class Batch:
                               else (cand_rows.numel() if cand_rows is not None else 0))
         d.pattern_cap = pattern_cap
         d.watchdog_ms = watchdog_ms
-        d.cand_mode = {"auto": 0, "blocks": 1, "sweep": 2}[cand_mode]
+        d.cand_mode = {"auto": 0, "blocks": 1, "sweep": 2, "walk": 3}[cand_mode]
         self.desc = d
         sz = C.c_size_t(0)
         check(lib.rwt_batch_ws(C.byref(d), C.byref(sz)))
@@ -841,7 +841,9 @@ class Batch:
         check(self._lib.rwt_batch_plan(self._h, m, C.byref(p)))
         inf = _lib.PlanInfo()
         check(self._lib.rwt_plan_get_info(p, C.byref(inf)))
-        return {"algo": "one workgroup" if inf.num_blocks == 1 else "sync-free blocks",
+        algo = ("walk" if inf.algo_fwd == _lib.ALGO["walk"] else
+                "one workgroup" if inf.num_blocks == 1 else "sync-free blocks")
+        return {"algo": algo, "chunk_rounds": inf.chunk_rounds,
                 "block_rows": inf.block_rows, "lanes_per_row": inf.lanes_per_row,
                 "rhs_chunk": inf.rhs_chunk, "num_blocks": inf.num_blocks,
                 "tuned_ms": inf.tuned_ms_syncfree}

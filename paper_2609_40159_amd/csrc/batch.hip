@@ -34,18 +34,24 @@
 #include "prim.hpp"
 #include "sf_block.hpp"
 #include "u128.hpp"
+#include "walk.hpp"
 
 namespace rwt {
 
 namespace {
 
 constexpr int BT_THREADS = 256;
+// row-order walks: solve tasks run two columns (waves 0 and 1), level
+// tasks four candidates (one per wave)
+constexpr int WK_SOLVE_WAVES = 2;
+constexpr int WK_LEVEL_WAVES = 4;
 constexpr int BT_LDS = SF_LDS_BUDGET;
 constexpr int NSLAB_B = 2;
 
 struct BatchMatDev {
     int32_t n, R, lanes, nblocks, k, kc;   // kc: right-hand sides per solve chain
     int32_t D, sweep;                      // levels; candidates take the level sweep
+    int32_t walk, pad_w;                   // solves and candidates take the row-order walk
     int64_t ldb, ldx;
     const int32_t* perm;                   // rows in (level, row) order
     const int32_t* lptr;                   // level offsets in perm
@@ -85,7 +91,7 @@ struct BatchKArgs {
     const uint32_t* epoch;
     int64_t ticks;
     int32_t hist_cap;   // level-cost histogram entries that fit the launch's LDS
-    int32_t pad;
+    int32_t qcap;       // capacity of the candidate row lists (pat_ptr holds qcap + 1)
 };
 
 __device__ __forceinline__ uint32_t epoch_tag(uint32_t e) { return (e % 255u) + 1u; }
@@ -599,6 +605,60 @@ __global__ void __launch_bounds__(BT_THREADS) k_batch_main(BatchKArgs a) {
             b.hold_row = -1;
             if (M.kc == 1) sf_block<double, false, 1>(b, s_raw);
             else sf_block<double, false, 4>(b, s_raw);
+        } else if (tk.x == 3) {
+            // row-order walks of columns tk.z .. tk.z + tk.w - 1 of matrix tk.y,
+            // one wave each
+            const BatchMatDev& M = a.mats[tk.y];
+            const int w = threadIdx.x / WAVE;
+            if (w < tk.w) {
+                const int32_t q = tk.z + w;
+                WkArgs wa;
+                wa.n = M.n;
+                wa.ptr = M.rowptr;
+                wa.idx = M.colidx;
+                wa.vals = M.vals;
+                wa.rowptr = M.rowptr;
+                wa.dvals = M.vals;
+                wa.b = M.B + (int64_t)q * M.ldb;
+                wa.x = M.X + (int64_t)q * M.ldx;
+                wa.err = &a.ctrl->err;
+                wk_solve<double, false>(
+                    wa, reinterpret_cast<WkLds<double>*>(s_raw + (size_t)w * wk_lds_bytes<double>()));
+            }
+        } else if (tk.x == 4) {
+            // row-order walks of the levels of candidates tk.y .. tk.y + tk.z - 1
+            // (one matrix), one wave each, then their statistics
+            const int32_t c0 = tk.y, gs = tk.z;
+            const BatchMatDev& M = a.mats[a.cands[c0].m];
+            const int w = threadIdx.x / WAVE;
+            if (w < gs) {
+                const int32_t c = c0 + w;
+                const BatchCandDev& Cd = a.cands[c];
+                // each rewritten row's slot holds its offset in the row list
+                const int32_t qb = a.cand_ptr[c], qe = a.cand_bad[c] ? qb : a.cand_ptr[c + 1];
+                for (int32_t q = qb + lane_id(); q < qe; q += WAVE) {
+                    const int32_t r = a.rows[q];
+                    if (q - qb < (int32_t)MARK && ((Cd.bitmap[r >> 5] >> (r & 31)) & 1u))
+                        st_relaxed(&Cd.lev[r], (int32_t)((tag << 24) | MARK | (uint32_t)(q - qb)));
+                }
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                WkLvlArgs la;
+                la.n = M.n;
+                la.rowptr = M.rowptr;
+                la.colidx = M.colidx;
+                la.lev = Cd.lev;
+                la.tag = tag;
+                la.mark = MARK;
+                la.pat_ptr = a.pat_ptr;
+                la.pat = a.pat;
+                la.qb = qb;
+                la.qmax = a.qcap;
+                la.err = &a.ctrl->err;
+                wk_levels(la, reinterpret_cast<WkLvlLds*>(s_raw + (size_t)w * sizeof(WkLvlLds)));
+            }
+            __syncthreads();
+            for (int32_t s = 0; s < gs; ++s)
+                finalize_group(a, M, c0 + s, 1, a.cands[c0 + s].lev, tag, true, s_raw);
         } else if (tk.x == 2) {
             // a sweep group: candidates tk.y .. tk.y + tk.z - 1 of one matrix,
             // levels interleaved in the first one's (and its neighbours')
@@ -808,8 +868,8 @@ rwt_status layout_batch(const rwt_batch_desc* d, BatchLayout* L) {
     RWT_REQUIRE(d != nullptr && d->count >= 0 && d->num_cand >= 0, RWT_ERR_INVALID_ARG,
                 "bad batch descriptor");
     RWT_REQUIRE(d->count == 0 || d->mats != nullptr, RWT_ERR_INVALID_ARG, "null matrix list");
-    RWT_REQUIRE(d->cand_mode >= 0 && d->cand_mode <= 2, RWT_ERR_INVALID_ARG,
-                "cand_mode must be 0, 1 or 2");
+    RWT_REQUIRE(d->cand_mode >= 0 && d->cand_mode <= 3, RWT_ERR_INVALID_ARG,
+                "cand_mode must be 0, 1, 2 or 3");
     RWT_REQUIRE(d->num_cand == 0 ||
                     (d->h_cand_mat && d->d_cand_ptr && d->d_cand_rows && d->cand_rows_cap >= 0),
                 RWT_ERR_INVALID_ARG, "null candidate arrays");
@@ -876,7 +936,7 @@ rwt_status layout_batch(const rwt_batch_desc* d, BatchLayout* L) {
     L->bad = take(std::max(1, d->num_cand));
     L->stats = take(sizeof(rwt_cand_stats) * std::max(1, d->num_cand));
     L->counts = take(sizeof(int32_t) * ((size_t)L->qcap + 1));
-    L->patptr = take(sizeof(int32_t) * ((size_t)L->qcap + 1));
+    L->patptr = take(sizeof(int32_t) * ((size_t)L->qcap + 2));   // at least two: the walk reads q, q + 1
     L->pat = take(sizeof(int32_t) * (size_t)L->pat_cap);
     L->ovf = take(sizeof(int32_t) * std::max(1, L->qcap));
     L->ovf2 = take(sizeof(int32_t) * std::max(1, L->qcap));
@@ -977,7 +1037,7 @@ rwt_status enqueue_main(rwt_batch* b, hipStream_t s) {
     ka.epoch = b->epoch;
     ka.ticks = watchdog_ticks(d.watchdog_ms);
     ka.hist_cap = (b->lds_bytes - 256) / 4;
-    ka.pad = 0;
+    ka.qcap = b->qcap;
     if (b->ntasks > 0) {
         hipLaunchKernelGGL(k_batch_main, dim3(b->grid), dim3(BT_THREADS), b->lds_bytes, s, ka);
         RWT_LAUNCHED();
@@ -1041,6 +1101,11 @@ extern "C" rwt_status rwt_batch_create(const rwt_batch_desc* desc, void* d_ws, s
                                         &p, stream);
         if (st != RWT_OK) return fail(st);
         b->plans.push_back(p);
+        // the row-order walk where the plan's model finds that consecutive
+        // rows span few levels (deep, thin DAGs); the plan then solves with
+        // it too, so per-matrix solves match the batch bit for bit
+        const bool walk = p->walk_ok;
+        if (walk) p->fwd = p->bwd = Algo::Walk;
         BatchMatDev& d = hm[m];
         memset(&d, 0, sizeof d);
         d.n = M.L.n;
@@ -1063,6 +1128,8 @@ extern "C" rwt_status rwt_batch_create(const rwt_batch_desc* desc, void* d_ws, s
         d.lptr = p->level_ptr;
         d.B = static_cast<const double*>(M.B);
         d.X = static_cast<double*>(M.X);
+        d.walk = walk ? 1 : 0;
+        d.pad_w = 0;
         hr[m].n = M.L.n;
         hr[m].pad = 0;
         hr[m].rowptr = M.L.rowptr;
@@ -1158,10 +1225,15 @@ extern "C" rwt_status rwt_batch_create(const rwt_batch_desc* desc, void* d_ws, s
             return fail(RWT_ERR_HIP);
         }
         for (int32_t c = 0; c < desc->num_cand; ++c) cand_count[hc[c].m] += 1;
-        for (int32_t m = 0; m < desc->count; ++m)
-            hm[m].sweep = hm[m].D < (1 << 23) &&
+        for (int32_t m = 0; m < desc->count; ++m) {
+            // candidates: the walk (levels below 2^23, the walk's matrices, or
+            // every matrix with cand_mode 3), else the sweep or the chains
+            hm[m].walk = hm[m].D < (1 << 23) &&
+                         (desc->cand_mode == 3 || (desc->cand_mode == 0 && hm[m].walk));
+            hm[m].sweep = !hm[m].walk && hm[m].D < (1 << 23) &&
                           (desc->cand_mode == 2 ||
                            (desc->cand_mode == 0 && (int64_t)steps[m] >= 4 * (int64_t)hm[m].D));
+        }
     }
     {
         DeviceInfo di;
@@ -1175,9 +1247,13 @@ extern "C" rwt_status rwt_batch_create(const rwt_batch_desc* desc, void* d_ws, s
             size_t need = 16384;
             for (int32_t m = 0; m < desc->count; ++m) {
                 const size_t R = (size_t)hm[m].R;
-                if (b->mats[m].k > 0)
+                if (b->plans[m]->fwd == Algo::Walk && b->mats[m].k > 0)
+                    need = std::max(need, (size_t)WK_SOLVE_WAVES * wk_lds_bytes<double>());
+                if (hm[m].walk && cand_count[m] > 0)
+                    need = std::max(need, (size_t)WK_LEVEL_WAVES * sizeof(WkLvlLds));
+                if (b->mats[m].k > 0 && b->plans[m]->fwd != Algo::Walk)
                     need = std::max(need, (size_t)sf_x_bytes((int)R, hm[m].kc, 8) + (R + 1) * 4 + 16);
-                if (!hm[m].sweep && cand_count[m] > 0)
+                if (!hm[m].sweep && !hm[m].walk && cand_count[m] > 0)
                     need = std::max(need, chain_lds(R, chain_group(R)));
             }
             need = (need + 255) & ~size_t(255);
@@ -1202,9 +1278,16 @@ extern "C" rwt_status rwt_batch_create(const rwt_batch_desc* desc, void* d_ws, s
             tv.push_back({run, make_int4(kind, id, k, chunk)});
         }
     };
-    // one solve chain per chunk of kc right-hand-side columns
-    for (int32_t m = 0; m < desc->count; ++m)
+    // one solve chain per chunk of kc right-hand-side columns; row-order
+    // walks, which wait on nothing, go first, longest first
+    for (int32_t m = 0; m < desc->count; ++m) {
+        if (b->plans[m]->fwd == Algo::Walk) {
+            for (int32_t q = 0; q < b->mats[m].k; q += WK_SOLVE_WAVES)
+                tv.push_back({-hm[m].n, make_int4(3, m, q, std::min(WK_SOLVE_WAVES, b->mats[m].k - q))});
+            continue;
+        }
         for (int32_t c = 0; c * hm[m].kc < b->mats[m].k; ++c) add_chain(m, 0, m, c);
+    }
     b->solve_tasks = (int32_t)tv.size();
     // sweep candidates go in groups: up to gmax consecutive candidates of one
     // matrix (their level arrays are adjacent), one task each, ready at once.
@@ -1217,6 +1300,13 @@ extern "C" rwt_status rwt_batch_create(const rwt_batch_desc* desc, void* d_ws, s
     b->sweep_cands = 0;
     for (int32_t c = 0; c < desc->num_cand;) {
         const int32_t m = hc[c].m;
+        if (hm[m].walk) {
+            int32_t gs = 1;
+            while (gs < WK_LEVEL_WAVES && c + gs < desc->num_cand && hc[c + gs].m == m) ++gs;
+            tv.push_back({-hm[m].n, make_int4(4, c, gs, 0)});
+            c += gs;
+            continue;
+        }
         if (!hm[m].sweep) {
             // level chains in groups too: up to chain_group(R) consecutive
             // candidates of the matrix share each row-block task

@@ -115,6 +115,7 @@ struct PlanLayout {
 constexpr int R_MIN = 32;       // smallest row block (sizes the block tables)
 constexpr int TUNE_COLS = 64;   // right-hand sides the autotuner solves with (at most)
 constexpr int32_t TUNE_ROWS = 1 << 21;   // rows the sync-free candidates are timed on (at most)
+constexpr double WALK_ROUNDS_MAX = 12.0;   // largest mean rounds per chunk the walk is tried at
 
 // A row block size is usable when the block's x values and step starts fit
 // the LDS budget at the largest right-hand-side count.
@@ -165,6 +166,8 @@ struct PlanPtrs {
     int4 *desc_f, *desc_t;
     void* xtmp;
     void* xtmp2;
+    void* vt;
+    unsigned long long* span;
     void* scratch;
     size_t scratch_bytes;
 };
@@ -194,6 +197,8 @@ size_t carve_plan(void* base, const rwt_csr& L, int kmax, PlanPtrs* p) {
     p->desc_t = cv.take<int4>(n);
     p->xtmp = cv.take<char>((size_t)n * kmax * s);
     p->xtmp2 = cv.take<char>((size_t)n * std::min(kmax, TUNE_COLS) * s);
+    p->vt = cv.take<char>((size_t)noff * s);
+    p->span = cv.take<unsigned long long>(1);
     // scratch shared by the construction steps
     size_t sched = 0;
     {
@@ -219,7 +224,7 @@ rwt_status check_opts(const rwt_csr* L, const rwt_plan_opts* o) {
     RWT_REQUIRE(L->rowptr && (L->nnz == 0 || (L->colidx && L->vals)), RWT_ERR_INVALID_ARG,
                 "a plan needs pattern and values");
     RWT_REQUIRE(L->dt == RWT_F64 || L->dt == RWT_F32, RWT_ERR_INVALID_ARG, "bad dtype");
-    RWT_REQUIRE(o->algo >= RWT_ALGO_AUTO && o->algo <= RWT_ALGO_SYNCFREE, RWT_ERR_INVALID_ARG,
+    RWT_REQUIRE(o->algo >= RWT_ALGO_AUTO && o->algo <= RWT_ALGO_WALK, RWT_ERR_INVALID_ARG,
                 "bad algorithm");
     RWT_REQUIRE(o->kmax >= 0 && o->kmax <= 4096, RWT_ERR_INVALID_ARG, "kmax out of range");
     RWT_REQUIRE(o->lanes_per_row == 0 ||
@@ -271,6 +276,7 @@ rwt_status run_solve(const rwt_plan* p, bool transposed, Algo algo, const void* 
                      int32_t hold_row = -1) {
     SolveArgs a = make_args(p);
     a.hold_row = hold_row;
+    a.vt = p->vt;
     if (rows > 0 && rows < a.n) {
         a.n = rows;
         a.nblocks = (rows + p->R - 1) / p->R;
@@ -285,6 +291,15 @@ rwt_status run_solve(const rwt_plan* p, bool transposed, Algo algo, const void* 
     } else {
         a.B = B;
         a.ldb = ldb;
+    }
+    if (algo == Algo::Walk) {
+        // no cross-wave readiness: only the control words are reset; the
+        // transposed walk reads the values in successor-list order
+        RWT_TRY(fill_u8(a.ctrl, sizeof(Ctrl), s));
+        if (transposed)
+            RWT_TRY(walk_gather_vals(p->csc.map, (int64_t)p->L.nnz - p->L.n, p->L.vals, p->vt,
+                                     p->L.dt, s));
+        return walk_launch(a, p->L.dt, transposed, s);
     }
     RWT_TRY(solve_prepare(a, p->L.dt, s));
     size_t lds = 0;
@@ -409,6 +424,8 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
     p->desc_t = pp.desc_t;
     p->xtmp = pp.xtmp;
     p->xtmp2 = pp.xtmp2;
+    p->vt = pp.vt;
+    p->span = pp.span;
     p->lanes = lanes;
     p->kc = kcs.front();
     DeviceInfo di;
@@ -432,8 +449,11 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
     LevelOut lo{pp.level, pp.perm, pp.level_ptr, pp.rows, pp.cost, pp.dstats};
     if ((st = compute_levels(*L, p->csc, lo, pp.actrl, pp.scratch, s, opts->watchdog_ms)) != RWT_OK)
         return fail(st);
+    if ((st = chunk_rounds(L->rowptr, L->colidx, n, pp.span, s)) != RWT_OK) return fail(st);
     Ctrl hc;
-    if (hipMemcpyAsync(&hc, pp.actrl, sizeof hc, hipMemcpyDeviceToHost, s) != hipSuccess ||
+    unsigned long long span_sum = 0;
+    if (hipMemcpyAsync(&span_sum, pp.span, sizeof span_sum, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&hc, pp.actrl, sizeof hc, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipMemcpyAsync(&p->stats, pp.dstats, sizeof p->stats, hipMemcpyDeviceToHost, s) !=
             hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) {
@@ -449,6 +469,13 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
         return fail(RWT_ERR_NOT_LOWER);
     }
     p->D = p->stats.num_levels;
+    // the row-order walk resolves a chunk's internal dependencies in rounds,
+    // one per link of the chunk's longest internal chain: it suits matrices
+    // whose chunks of consecutive rows need few rounds (deep, thin DAGs with
+    // spread-out dependencies), not grids in natural order (each row depends
+    // on the one before: 64 rounds)
+    p->chunk_rounds = (double)span_sum / (double)((n + 63) / 64);
+    p->walk_ok = p->chunk_rounds <= WALK_ROUNDS_MAX;
     // level segments: runs of narrow levels go to one workgroup
     std::vector<int32_t> rows(p->D);
     if (hipMemcpy(rows.data(), pp.rows, sizeof(int32_t) * p->D, hipMemcpyDeviceToHost) != hipSuccess) {
@@ -506,13 +533,16 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
     };
     // algorithm, RHS chunk and block size: measured on the plan's own matrix
     // (with kt = min(kmax, TUNE_COLS) columns) unless forced
-    p->fwd = p->bwd = opts->algo == RWT_ALGO_LEVEL ? Algo::Level : Algo::SyncFree;
+    p->fwd = p->bwd = opts->algo == RWT_ALGO_LEVEL ? Algo::Level
+                      : opts->algo == RWT_ALGO_WALK  ? Algo::Walk
+                                                     : Algo::SyncFree;
     const int kt = std::min(kmax, opts->tune_cols > 0 ? opts->tune_cols : TUNE_COLS);
     const bool tune_algo = opts->algo == RWT_ALGO_AUTO;
-    const bool tune_sf = opts->algo != RWT_ALGO_LEVEL &&
+    const bool blocks_used = opts->algo == RWT_ALGO_AUTO || opts->algo == RWT_ALGO_SYNCFREE;
+    const bool tune_sf = blocks_used &&
                          (kcs.size() > 1 ||
                           block_candidates(*opts, L->dt, n, kcs.front(), lanes).size() > 1);
-    const bool tune_stage = opts->algo != RWT_ALGO_LEVEL && opts->stage_outside == 0 && n > 0;
+    const bool tune_stage = blocks_used && opts->stage_outside == 0 && n > 0;
     p->stage_x = opts->stage_outside == 2 ? 2 : 1;
     if (tune_algo || tune_sf || tune_stage) {
         const int64_t nf = (int64_t)n * kt;
@@ -577,6 +607,12 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
                 return fail(RWT_ERR_DEADLOCK);
             }
             p->fwd = p->bwd = p->tuned_level < best_sf ? Algo::Level : Algo::SyncFree;
+            // the row-order walk, on the whole matrix, where the model says
+            // it may win
+            if (p->walk_ok) {
+                p->tuned_walk = time_solve_rows(p, Algo::Walk, kt, s, 3, 0);
+                if (p->tuned_walk < std::min(p->tuned_level, best_sf)) p->fwd = p->bwd = Algo::Walk;
+            }
         }
     }
     if ((st = build_blocks(R)) != RWT_OK) return fail(st);
@@ -592,8 +628,11 @@ extern "C" rwt_status rwt_plan_get_info(const rwt_plan* p, rwt_plan_info* h) {
     RWT_REQUIRE(p != nullptr && h != nullptr, RWT_ERR_INVALID_ARG, "null argument");
     memset(h, 0, sizeof *h);
     h->stats = p->stats;
-    h->algo_fwd = p->fwd == Algo::Level ? RWT_ALGO_LEVEL : RWT_ALGO_SYNCFREE;
-    h->algo_bwd = p->bwd == Algo::Level ? RWT_ALGO_LEVEL : RWT_ALGO_SYNCFREE;
+    auto code = [](Algo a) {
+        return a == Algo::Level ? RWT_ALGO_LEVEL : a == Algo::Walk ? RWT_ALGO_WALK : RWT_ALGO_SYNCFREE;
+    };
+    h->algo_fwd = code(p->fwd);
+    h->algo_bwd = code(p->bwd);
     h->block_rows = p->R;
     h->lanes_per_row = p->lanes;
     h->narrow_rows = p->opts.narrow_rows;
@@ -605,8 +644,11 @@ extern "C" rwt_status rwt_plan_get_info(const rwt_plan* p, rwt_plan_info* h) {
                                       ? syncfree_lds_bytes(p->R, p->kc, p->L.dt, p->lanes)
                                       : 0,
                                   p->cus);
+    if (p->fwd == Algo::Walk) h->grid = (p->opts.kmax + 3) / 4;
     h->tuned_ms_level = p->tuned_level;
     h->tuned_ms_syncfree = p->tuned_sf;
+    h->tuned_ms_walk = p->tuned_walk;
+    h->chunk_rounds = p->chunk_rounds;
     return RWT_OK;
 }
 

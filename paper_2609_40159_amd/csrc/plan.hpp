@@ -31,7 +31,11 @@ struct rwt_plan {
     int32_t lanes = 4;
     int32_t stage_x = 1;      // sync-free: helper waves stage outside x values (1) or not (2)
     int cus = 256;
-    double tuned_level = 0, tuned_sf = 0;
+    double tuned_level = 0, tuned_sf = 0, tuned_walk = 0;
+    void* vt = nullptr;                  // values in successor-list order (transposed walk)
+    unsigned long long* span = nullptr;  // device word: rounds summed over 64-row chunks
+    double chunk_rounds = 0;             // mean rounds the walk needs per 64-row chunk
+    bool walk_ok = false;                // the row-order walk suits this matrix
 };
 
 namespace rwt {

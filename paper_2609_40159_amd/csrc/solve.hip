@@ -26,6 +26,7 @@
 
 #include "sf_block.hpp"
 #include "sf_staged.hpp"
+#include "walk.hpp"
 
 #include "prim.hpp"
 
@@ -245,6 +246,68 @@ __global__ void __launch_bounds__(SV_THREADS) k_solve_sf(SolveArgs a) {
     }
 }
 
+// One wave per right-hand-side column, each walking the rows in order
+// (walk.hpp); waves past the last column return at once (the walk uses no
+// workgroup barrier).
+constexpr int WALK_WAVES = 2;   // two walks per workgroup: 2 x 39 KB of LDS (FP64)
+template <typename T, bool TRANS>
+__global__ void __launch_bounds__(SV_THREADS) k_solve_walk(SolveArgs a) {
+    extern __shared__ __align__(16) unsigned char s_raw[];
+    const int w = threadIdx.x / WAVE;
+    const int32_t q = blockIdx.x * WALK_WAVES + w;
+    if (q >= a.k) return;
+    WkLds<T>* L = reinterpret_cast<WkLds<T>*>(s_raw + (size_t)w * wk_lds_bytes<T>());
+    WkArgs wa;
+    wa.n = a.n;
+    wa.ptr = TRANS ? a.cptr : a.rowptr;
+    wa.idx = TRANS ? a.crow : a.colidx;
+    wa.vals = TRANS ? a.vt : a.vals;
+    wa.rowptr = a.rowptr;
+    wa.dvals = a.vals;
+    wa.b = static_cast<const T*>(a.B) + (int64_t)q * a.ldb;
+    wa.x = static_cast<T*>(a.X) + (int64_t)q * a.ldx;
+    wa.err = &a.ctrl->err;
+    wk_solve<T, TRANS>(wa, L);
+}
+
+template <typename T>
+__global__ void k_gather_vals(const int32_t* map, int64_t m, const T* vals, T* out) {
+    const int64_t st = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m; p += st)
+        out[p] = vals[map[p]];
+}
+
+// The rounds the walk would take on each 64-row chunk (the longest chain
+// of dependencies inside the chunk, plus one), summed over the chunks: the
+// walk's rounds without its values, one wave per chunk.
+__global__ void k_chunk_rounds(const int32_t* rowptr, const int32_t* colidx, int32_t n,
+                               unsigned long long* out) {
+    const int lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+    const int64_t nch = ((int64_t)n + WAVE - 1) / WAVE;
+    unsigned long long acc = 0;
+    for (int64_t c = wave; c < nch; c += nw) {
+        const int32_t lo = (int32_t)(c * WAVE);
+        const int32_t i = lo + lane;
+        uint64_t dep = 0;
+        if (i < n)
+            for (int32_t p = rowptr[i + 1] - 2; p >= rowptr[i]; --p) {   // last entry: diagonal
+                const int32_t j = colidx[p];
+                if (j < lo) break;                                     // columns ascend
+                if (j < i) dep |= 1ull << (j - lo);
+            }
+        uint64_t done = __ballot(i >= n);
+        int rounds = 0;
+        while (done != ~0ull && rounds < WAVE) {
+            done |= __ballot(!((done >> lane) & 1ull) && (dep & ~done) == 0);
+            ++rounds;
+        }
+        acc += (unsigned long long)rounds;
+    }
+    if (lane == 0 && acc != 0) atomicAdd(out, acc);
+}
+
 template <typename T, bool TRANS>
 rwt_status launch_typed(const SolveArgs& a, Algo algo, unsigned grid, hipStream_t s) {
     const bool multi = (algo == Algo::Level ? a.k : a.kc) > 1;
@@ -306,6 +369,48 @@ rwt_status solve_prepare(const SolveArgs& a, rwt_dtype dt, hipStream_t s) {
     else
         hipLaunchKernelGGL(k_prefill<float>, dim3(g), dim3(256), 0, s, static_cast<float*>(a.X),
                            a.ldx, a.n, a.k, cw);
+    RWT_LAUNCHED();
+    return RWT_OK;
+}
+
+rwt_status walk_launch(const SolveArgs& a, rwt_dtype dt, bool transposed, hipStream_t s) {
+    if (a.n == 0 || a.k == 0) return RWT_OK;
+    const int waves = a.k < WALK_WAVES ? a.k : WALK_WAVES;
+    const unsigned grid = (unsigned)((a.k + WALK_WAVES - 1) / WALK_WAVES);
+    const dim3 blk(WAVE * waves);
+    if (dt == RWT_F64) {
+        const size_t lds = (size_t)waves * wk_lds_bytes<double>();
+        if (transposed) hipLaunchKernelGGL((k_solve_walk<double, true>), dim3(grid), blk, lds, s, a);
+        else hipLaunchKernelGGL((k_solve_walk<double, false>), dim3(grid), blk, lds, s, a);
+    } else {
+        const size_t lds = (size_t)waves * wk_lds_bytes<float>();
+        if (transposed) hipLaunchKernelGGL((k_solve_walk<float, true>), dim3(grid), blk, lds, s, a);
+        else hipLaunchKernelGGL((k_solve_walk<float, false>), dim3(grid), blk, lds, s, a);
+    }
+    RWT_LAUNCHED();
+    return RWT_OK;
+}
+
+rwt_status walk_gather_vals(const int32_t* map, int64_t m, const void* vals, void* out,
+                            rwt_dtype dt, hipStream_t s) {
+    if (m <= 0) return RWT_OK;
+    const unsigned g = blocks_for((size_t)m, 256, 8192);
+    if (dt == RWT_F64)
+        hipLaunchKernelGGL(k_gather_vals<double>, dim3(g), dim3(256), 0, s, map, m,
+                           static_cast<const double*>(vals), static_cast<double*>(out));
+    else
+        hipLaunchKernelGGL(k_gather_vals<float>, dim3(g), dim3(256), 0, s, map, m,
+                           static_cast<const float*>(vals), static_cast<float*>(out));
+    RWT_LAUNCHED();
+    return RWT_OK;
+}
+
+rwt_status chunk_rounds(const int32_t* rowptr, const int32_t* colidx, int32_t n,
+                        unsigned long long* d_out, hipStream_t s) {
+    RWT_TRY(fill_u8(d_out, sizeof(unsigned long long), s));
+    if (n <= 0) return RWT_OK;
+    const unsigned g = blocks_for(((size_t)n + WAVE - 1) / WAVE * WAVE, 256, 2048);
+    hipLaunchKernelGGL(k_chunk_rounds, dim3(g), dim3(256), 0, s, rowptr, colidx, n, d_out);
     RWT_LAUNCHED();
     return RWT_OK;
 }

@@ -39,9 +39,23 @@ struct SolveArgs {
     Ctrl* ctrl;
     int64_t ticks;
     int32_t hold_row;          // >= 0: this row's values are never published (watchdog test)
+    const void* vt;            // row-order walk, transposed: values in successor-list order
 };
 
-enum class Algo { Level, SyncFree };
+enum class Algo { Level, SyncFree, Walk };
+
+// Row-order walk (walk.hpp): one wave per right-hand-side column, two
+// per workgroup; for the transposed walk a.vt must hold the values in
+// successor-list order (walk_gather_vals).
+rwt_status walk_launch(const SolveArgs& a, rwt_dtype dt, bool transposed, hipStream_t s);
+rwt_status walk_gather_vals(const int32_t* map, int64_t m, const void* vals, void* out,
+                            rwt_dtype dt, hipStream_t s);
+// 64-row chunks of consecutive rows: the sum over chunks of the rounds the
+// walk needs on the chunk (its longest chain of internal dependencies plus
+// one), into *d_out (zeroed by the call); the walk suits matrices whose
+// chunks need few rounds (the pattern must be valid)
+rwt_status chunk_rounds(const int32_t* rowptr, const int32_t* colidx, int32_t n,
+                        unsigned long long* d_out, hipStream_t s);
 
 // Fill X with the not-ready sentinel and reset the control block.
 rwt_status solve_prepare(const SolveArgs& a, rwt_dtype dt, hipStream_t s);

@@ -1,0 +1,592 @@
+// Row-order wave walker: one wavefront solves a whole column of a
+// triangular system in walk order, 64 rows (a chunk) at a time.
+//
+// Section 2.1 solves a row once all its dependencies are done; level-set
+// and block schedules pay a synchronization per level (a barrier or a
+// cross-workgroup hand-off, about 0.6-1.5 us on this part).  On deep,
+// thin DAGs -- thousands of levels of a few rows each, dependencies spread
+// over hundreds of rows -- a chunk of 64 consecutive rows spans only a few
+// levels, so one wave can walk the rows in order and resolve the chunk's
+// internal dependencies itself, in a few rounds of register ballots,
+// instead of one global synchronization per level:
+//   stage   the chunk's entry pointers are loaded two chunks ahead; its
+//           contiguous CSR (or successor-list) entries are copied one chunk
+//           ahead straight into an LDS buffer (global_load_lds: no
+//           registers, coalesced), its right-hand sides into registers;
+//   flat    the wave turns the value of every staged entry whose dependency
+//           lies before the chunk into the product v * x_dep (x from an LDS
+//           ring of the last WK_W solved values, older ones from HBM), one
+//           entry per lane and round, so a long row does not serialize a
+//           lane;
+//   sum     each lane adds its row's products in walk order;
+//   rounds  a lane whose in-chunk dependencies (a 64-bit mask of lanes)
+//           are all solved adds those terms and solves its row; a ballot
+//           marks the newly solved rows; repeat until the chunk is done.
+// A row's terms are always added in walk order of its dependencies
+// (ascending column forward, descending successor row transposed), so
+// the result does not depend on the chunking.  A chunk with more entries
+// than the stage holds reads them from HBM instead.
+//
+// Positions: the walk visits position t = 0..n-1; forward t = row,
+// transposed t = n-1-row (L^T is solved from the last row up through the
+// successor lists).  Every dependency of the row at t has a smaller
+// position.  Lane l of chunk c holds position 64c + l.
+#pragma once
+
+#include "common.hpp"
+
+namespace rwt {
+
+constexpr int WK_W = 2048;            // ring: the last WK_W solved values (power of 2)
+constexpr int WK_ECAP = 960;          // entries staged per chunk (multiple of 64; a chunk
+                                      // of rows of about 9 entries holds about 580)
+
+typedef __attribute__((address_space(3))) void* wk_lds_ptr;
+typedef __attribute__((address_space(1))) void* wk_glb_ptr;
+
+// Copy words [0, count) of src into LDS dst, 64 four-byte words per
+// instruction, lane l taking word 64u + l (words past count repeat the
+// last one and land past count in dst); CAP words at most (wave-uniform
+// loop).  Completion is waited for with vmcnt.
+template <int CAP>
+__device__ __forceinline__ void wk_copy_words(const uint32_t* src, int32_t count, uint32_t* dst) {
+    const int lane = lane_id();
+    count = __builtin_amdgcn_readfirstlane(count);   // the same in every lane
+    const int32_t last = count > 0 ? count - 1 : 0;
+#pragma unroll
+    for (int u = 0; u < CAP / WAVE; ++u) {
+        if (u * WAVE >= count) break;
+        const int32_t w = min(u * WAVE + lane, last);
+        __builtin_amdgcn_global_load_lds((wk_glb_ptr)(src + w), (wk_lds_ptr)(dst + u * WAVE), 4, 0,
+                                         0);
+    }
+}
+
+template <typename T>
+struct WkLds {
+    T xr[WK_W];                     // x at position t in xr[t & (WK_W - 1)]
+    T ev[2][WK_ECAP];               // staged values (double-buffered), then products
+    int32_t ej[2][WK_ECAP];         // staged dependency rows
+    int32_t rp[WAVE + 1];           // entry starts of the chunk's rows, by local row index
+};
+
+template <typename T>
+__host__ __device__ constexpr int wk_lds_bytes() {
+    return (int)((sizeof(WkLds<T>) + 15) & ~size_t(15));
+}
+
+struct WkArgs {
+    int32_t n;
+    const int32_t* ptr;      // forward: rowptr; transposed: successor-list starts
+    const int32_t* idx;      // forward: colidx; transposed: successor rows
+    const void* vals;        // forward: CSR values; transposed: values in successor order
+    const int32_t* rowptr;   // transposed: diagonal positions
+    const void* dvals;       // transposed: CSR values (diagonals)
+    const void* b;           // one column
+    void* x;                 // one column
+    int32_t* err;            // set when a chunk cannot finish (a dependency not below its row)
+};
+
+// chunk c holds rows [lo, lo + cnt)
+struct WkChunk {
+    int32_t lo, cnt;
+};
+template <bool TRANS>
+__device__ __forceinline__ WkChunk wk_chunk(int32_t n, int32_t c) {
+    const int32_t t0 = c * WAVE;
+    const int32_t cnt = min(WAVE, n - t0);
+    return WkChunk{TRANS ? n - t0 - cnt : t0, cnt};
+}
+
+// entry pointers of a chunk (loaded two chunks ahead)
+struct WkPtr {
+    int32_t rpv;     // ptr[lo + min(local index of this lane, cnt)]
+    int32_t endv;    // ptr[lo + cnt]
+    int32_t dpos;    // transposed: position of this lane's diagonal in the CSR
+};
+
+// Loads for a chunk past the last are clamped to the last chunk (their
+// results are never used): every load is issued unconditionally, so the
+// compiler's in-order wait counts stay exact.
+template <bool TRANS>
+__device__ __forceinline__ WkPtr wk_load_ptr(const WkArgs& a, int32_t c, int32_t nchunks) {
+    const int lane = lane_id();
+    const WkChunk ch = wk_chunk<TRANS>(a.n, min(c, nchunks - 1));
+    WkPtr p;
+    p.rpv = a.ptr[ch.lo + min(lane, ch.cnt)];
+    p.endv = a.ptr[ch.lo + ch.cnt];
+    p.dpos = 0;
+    if (TRANS) p.dpos = a.rowptr[ch.lo + max(ch.cnt - 1 - lane, 0) + 1] - 1;
+    return p;
+}
+
+template <typename T>
+struct WkRhs {
+    T b, diag;
+};
+template <typename T, bool TRANS>
+__device__ __forceinline__ WkRhs<T> wk_load_rhs(const WkArgs& a, int32_t c, int32_t nchunks,
+                                                const WkPtr& p) {
+    const int lane = lane_id();
+    const WkChunk ch = wk_chunk<TRANS>(a.n, min(c, nchunks - 1));
+    const int32_t li = TRANS ? max(ch.cnt - 1 - lane, 0) : min(lane, ch.cnt - 1);
+    WkRhs<T> r;
+    r.b = static_cast<const T*>(a.b)[ch.lo + li];
+    r.diag = TRANS ? static_cast<const T*>(a.dvals)[p.dpos] : T(1);
+    return r;
+}
+
+// the chunk's entries (at most WK_ECAP) into LDS buffer buf
+template <typename T>
+__device__ __forceinline__ void wk_stage_entries(const WkArgs& a, const WkPtr& p, WkLds<T>* L,
+                                                 int buf) {
+    const int32_t base = __shfl(p.rpv, 0);
+    const int32_t cnt = min(p.endv - base, WK_ECAP);
+    constexpr int WPE = (int)sizeof(T) / 4;   // words per value
+    wk_copy_words<WK_ECAP>(reinterpret_cast<const uint32_t*>(a.idx + base), cnt,
+                           reinterpret_cast<uint32_t*>(L->ej[buf]));
+    wk_copy_words<WK_ECAP * WPE>(
+        reinterpret_cast<const uint32_t*>(static_cast<const T*>(a.vals) + base), cnt * WPE,
+        reinterpret_cast<uint32_t*>(L->ev[buf]));
+}
+
+// One chunk's rows once the products of the dependencies before the chunk
+// are known: each row's sum, then the rounds over the in-chunk
+// dependencies.  STAGED: entries from LDS, products already formed; else
+// from HBM (a chunk larger than the stage).  A row with more than WK_LONG
+// dependencies, and every row of an unstaged chunk, is summed by the whole
+// wave (64 entries a step, then a butterfly sum: a fixed order); the others
+// by their own lane, in walk order.
+constexpr int WK_LONG = 24;
+
+template <typename T, bool TRANS, bool STAGED>
+__device__ __forceinline__ T wk_rows(const WkArgs& a, WkLds<T>* L, const int32_t* ej, const T* ev,
+                                     int32_t base, int32_t lo, int32_t cnt, int32_t t0, T b_i,
+                                     T diag) {
+    const int lane = lane_id();
+    const int32_t n = a.n;
+    const int32_t hi = lo + cnt - 1;
+    const T* vals = static_cast<const T*>(a.vals);
+    const T* X = static_cast<const T*>(a.x);
+    auto pos_of = [&](int32_t r) { return TRANS ? n - 1 - r : r; };
+    auto outside = [&](int32_t r) { return TRANS ? r > hi : r < lo; };
+    auto lane_of = [&](int32_t r) { return TRANS ? hi - r : r - lo; };
+    auto J = [&](int32_t e) -> int32_t { return STAGED ? ej[e] : a.idx[base + e]; };
+    auto V = [&](int32_t e) -> T { return STAGED ? ev[e] : vals[base + e]; };
+    // a product of a dependency before the chunk: formed already, or now
+    auto term = [&](int32_t e, int32_t r) -> T {
+        if (STAGED) return ev[e];
+        const int32_t t = pos_of(r);
+        const T x = t >= t0 + WAVE - WK_W ? L->xr[t & (WK_W - 1)] : ld_relaxed(&X[r]);
+        return vals[base + e] * x;
+    };
+    const bool act = lane < cnt;
+    const int32_t li = TRANS ? cnt - 1 - lane : lane;
+    int32_t eb = 0, ee = 0;
+    if (act) {
+        eb = L->rp[li];
+        ee = L->rp[li + 1];
+    }
+    // off-diagonal entries [eb, oe); forward rows end with their diagonal
+    const int32_t oe = TRANS ? ee : ee - 1;
+    if (act && !TRANS) diag = V(ee - 1);
+    T acc = T(0);
+    uint64_t dep = 0;
+    // forward: first in-chunk entry (in-chunk entries are a suffix);
+    // transposed: last in-chunk entry (a prefix)
+    int32_t split = TRANS ? eb - 1 : oe;
+    const bool coop = act && (!STAGED || oe - eb > WK_LONG);
+    for (uint64_t m = __ballot(coop); m != 0; m &= m - 1) {
+        const int o = __builtin_ctzll(m);
+        const int32_t cb = __shfl(eb, o), ce = __shfl(oe, o);
+        T part = T(0);
+        uint64_t dm = 0;
+        int32_t sp = TRANS ? cb - 1 : ce;
+        for (int32_t e0 = cb; e0 < ce; e0 += WAVE) {
+            const int32_t e = e0 + lane;
+            if (e < ce) {
+                const int32_t r = J(e);
+                if (outside(r)) {
+                    part += term(e, r);
+                } else {
+                    dm |= 1ull << lane_of(r);
+                    sp = TRANS ? max(sp, e) : min(sp, e);
+                }
+            }
+        }
+        part = wave_sum(part);
+        for (int s = WAVE / 2; s > 0; s >>= 1) dm |= __shfl_xor(dm, s);
+        sp = TRANS ? wave_max(sp) : wave_min(sp);
+        if (lane == o) {
+            acc = part;
+            dep = dm;
+            split = sp;
+        }
+    }
+    if (act && !coop) {
+        // (STAGED) four entries per step, loads issued together; terms added
+        // in walk order (forward ascending, transposed descending entries)
+        constexpr int U4 = 4;
+        if (!TRANS) {
+            for (int32_t e0 = eb; e0 < oe; e0 += U4) {
+                int32_t r[U4];
+                T v[U4];
+#pragma unroll
+                for (int u = 0; u < U4; ++u) {
+                    const int32_t e = min(e0 + u, oe - 1);
+                    r[u] = J(e);
+                    v[u] = V(e);
+                }
+#pragma unroll
+                for (int u = 0; u < U4; ++u) {
+                    if (e0 + u >= oe) break;
+                    if (outside(r[u])) {
+                        acc += v[u];
+                    } else {
+                        dep |= 1ull << lane_of(r[u]);
+                        split = min(split, e0 + u);
+                    }
+                }
+            }
+        } else {
+            for (int32_t e0 = oe - 1; e0 >= eb; e0 -= U4) {
+                int32_t r[U4];
+                T v[U4];
+#pragma unroll
+                for (int u = 0; u < U4; ++u) {
+                    const int32_t e = max(e0 - u, eb);
+                    r[u] = J(e);
+                    v[u] = V(e);
+                }
+#pragma unroll
+                for (int u = 0; u < U4; ++u) {
+                    if (e0 - u < eb) break;
+                    if (outside(r[u])) {
+                        acc += v[u];
+                    } else {
+                        dep |= 1ull << lane_of(r[u]);
+                        split = max(split, e0 - u);
+                    }
+                }
+            }
+        }
+    }
+    // rounds: each solves at least the lowest unsolved position of a valid
+    // (lower triangular) system, so at most WAVE of them
+    uint64_t done = __ballot(!act);
+    T xi = T(0);
+    for (int round = 0; done != ~0ull && round < WAVE; ++round) {
+        const bool ready = act && !((done >> lane) & 1ull) && (dep & ~done) == 0;
+        if (ready) {
+            if (!TRANS) {
+                for (int32_t e = split; e < oe; ++e)
+                    acc += V(e) * L->xr[pos_of(J(e)) & (WK_W - 1)];
+            } else {
+                for (int32_t e = split; e >= eb; --e)
+                    acc += V(e) * L->xr[pos_of(J(e)) & (WK_W - 1)];
+            }
+            xi = (b_i - acc) / diag;
+            L->xr[(t0 + lane) & (WK_W - 1)] = xi;
+        }
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        done |= __ballot(ready);
+    }
+    if (done != ~0ull && lane == 0)   // a dependency on or after its own row
+        __hip_atomic_store(a.err, (int32_t)RWT_ERR_INVALID_ARG, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    return xi;
+}
+
+// Solve one column: rows in walk order, chunk by chunk.  Every lane of the
+// wave calls it.
+template <typename T, bool TRANS>
+__device__ void wk_solve(const WkArgs& a, WkLds<T>* L) {
+    const int lane = lane_id();
+    const int32_t n = a.n;
+    if (n <= 0) return;
+    const int32_t nchunks = (n + WAVE - 1) / WAVE;
+    T* X = static_cast<T*>(a.x);
+    WkPtr p_cur = wk_load_ptr<TRANS>(a, 0, nchunks);
+    WkPtr p_nxt = wk_load_ptr<TRANS>(a, 1, nchunks);
+    WkRhs<T> r_nxt = wk_load_rhs<T, TRANS>(a, 0, nchunks, p_cur);
+    wk_stage_entries<T>(a, p_cur, L, 0);
+    for (int32_t c = 0; c < nchunks; ++c) {
+        const int buf = c & 1;
+        const WkChunk ch = wk_chunk<TRANS>(n, c);
+        const int32_t lo = ch.lo, cnt = ch.cnt, hi = lo + cnt - 1;
+        const int32_t t0 = c * WAVE;                       // first position of the chunk
+        const WkRhs<T> r_cur = r_nxt;
+        // this chunk's stage has landed (its loads were issued a chunk ago)
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        const int32_t base = __shfl(p_cur.rpv, 0);
+        const int32_t E = p_cur.endv - base;
+        // the next chunks' loads; nothing in this chunk waits for them
+        // except a dependency older than the ring or a chunk larger than
+        // the stage
+        const WkPtr p_n2 = wk_load_ptr<TRANS>(a, c + 2, nchunks);
+        r_nxt = wk_load_rhs<T, TRANS>(a, c + 1, nchunks, p_nxt);
+        if (c + 1 < nchunks) wk_stage_entries<T>(a, p_nxt, L, buf ^ 1);
+        int32_t* ej = L->ej[buf];
+        T* ev = L->ev[buf];
+        L->rp[lane] = p_cur.rpv - base;
+        if (lane == 0) L->rp[cnt] = E;
+        T xi;
+        if (E <= WK_ECAP) {
+            // flat products of the staged entries whose dependency precedes
+            // the chunk, x from the ring; dependencies older than the ring
+            // in a second pass (rare: it waits for HBM)
+            const int32_t ring_lo = t0 + WAVE - WK_W;
+            bool far = false;
+            // unrolled over the stage so that the loads of several entries
+            // are in flight together (LDS latency, not issue, bounds it)
+            constexpr int U = WK_ECAP / WAVE;
+            int32_t rv[U];
+            T vv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t e = lane + u * WAVE;
+                rv[u] = e < E ? ej[e] : (TRANS ? hi : lo);   // padding: an in-chunk row
+                vv[u] = e < E ? ev[e] : T(0);
+            }
+            T xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t t = TRANS ? n - 1 - rv[u] : rv[u];
+                xv[u] = (t < t0 && t >= ring_lo) ? L->xr[t & (WK_W - 1)] : T(0);
+                far = far || t < ring_lo;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t e = lane + u * WAVE;
+                const int32_t t = TRANS ? n - 1 - rv[u] : rv[u];
+                if (e < E && t < t0 && t >= ring_lo) ev[e] = vv[u] * xv[u];
+            }
+            if (__ballot(far) != 0) {
+                for (int32_t e = lane; e < E; e += WAVE) {
+                    const int32_t r = ej[e];
+                    const int32_t t = TRANS ? n - 1 - r : r;
+                    if (t < ring_lo) ev[e] = ev[e] * ld_relaxed(&X[r]);
+                }
+            }
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+            xi = wk_rows<T, TRANS, true>(a, L, ej, ev, base, lo, cnt, t0, r_cur.b, r_cur.diag);
+        } else {
+            xi = wk_rows<T, TRANS, false>(a, L, ej, ev, base, lo, cnt, t0, r_cur.b, r_cur.diag);
+        }
+        // publish the chunk (rows contiguous: one coalesced store)
+        if (lane < cnt) X[TRANS ? hi - lane : lo + lane] = xi;
+        p_cur = p_nxt;
+        p_nxt = p_n2;
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
+// ---------------------------------------------------------------------------
+// The same walk for the levels of a rewritten matrix L' (Section 2.1: the
+// level of a row is 0 without dependencies, else 1 + the largest level of
+// its dependencies), for one candidate rewrite set: rows keep L's
+// dependencies unless rewritten, in which case their new list comes from
+// the batched symbolic rewrite.  Levels are an order-free maximum, so a
+// lane's in-chunk dependencies are read straight from its mask of lanes.
+// ---------------------------------------------------------------------------
+struct WkLvlLds {
+    int32_t lr[WK_W];               // level at position t in lr[t & (WK_W - 1)]
+    int32_t ej[2][WK_ECAP];         // staged dependency rows (double-buffered)
+    int32_t el[WK_ECAP];            // their levels when before the chunk
+    int32_t rp[WAVE + 1];
+};
+
+struct WkLvlArgs {
+    int32_t n;
+    const int32_t* rowptr;       // L
+    const int32_t* colidx;
+    int32_t* lev;                // per row: before the walk, rewritten rows hold
+                                 // (tag << 24) | mark | list offset; after it,
+                                 // (tag << 24) | level
+    uint32_t tag, mark;
+    const int32_t* pat_ptr;      // new dependency lists, by list position (diagonal last)
+    const int32_t* pat;
+    int32_t qb;                  // the candidate's first list position (marks hold offsets from it)
+    int32_t qmax;                // list positions < qmax; pat_ptr holds at least qmax + 1 and 2 entries
+    int32_t* err;
+};
+
+// slots of rows marked as rewritten this launch hold their list offset
+__device__ __forceinline__ bool wk_marked(int32_t v, uint32_t tag, uint32_t mark) {
+    return ((uint32_t)v >> 24) == tag && ((uint32_t)v & mark);
+}
+
+__device__ void wk_levels(const WkLvlArgs& a, WkLvlLds* L) {
+    const int lane = lane_id();
+    const int32_t n = a.n;
+    if (n <= 0) return;
+    const int32_t nchunks = (n + WAVE - 1) / WAVE;
+    const uint32_t tagbits = a.tag << 24;
+    const int32_t lmask = (int32_t)(a.mark - 1u);
+    // pointers and rewrite marks two chunks ahead, a rewritten row's list
+    // bounds and the entries one chunk ahead; loads past the last chunk are
+    // clamped to it (unused), so that every load is issued unconditionally
+    struct P {
+        int32_t rpv, endv, slot;
+    };
+    auto load_p = [&](int32_t c) -> P {
+        const int32_t lo = min(c, nchunks - 1) * WAVE, cnt = min(WAVE, n - lo);
+        P p;
+        p.rpv = a.rowptr[lo + min(lane, cnt)];
+        p.endv = a.rowptr[lo + cnt];
+        p.slot = ld_relaxed(&a.lev[lo + min(lane, cnt - 1)]);
+        return p;
+    };
+    struct Q {
+        int32_t nb, ne;   // a rewritten row's new list (diagonal excluded); ne < nb: L's list
+    };
+    auto load_q = [&](const P& p) -> Q {
+        const bool rw = wk_marked(p.slot, a.tag, a.mark);
+        const int32_t q = max(min(a.qb + (rw ? (p.slot & lmask) : 0), a.qmax - 1), 0);
+        const int32_t nb = a.pat_ptr[q], ne = a.pat_ptr[q + 1] - 1;
+        return rw ? Q{nb, ne} : Q{0, -1};
+    };
+    auto stage = [&](const P& p, int buf) {
+        const int32_t base = __shfl(p.rpv, 0);
+        wk_copy_words<WK_ECAP>(reinterpret_cast<const uint32_t*>(a.colidx + base),
+                               min(p.endv - base, WK_ECAP), reinterpret_cast<uint32_t*>(L->ej[buf]));
+    };
+    P p_cur = load_p(0), p_nxt = load_p(1);
+    Q q_nxt = load_q(p_cur);
+    stage(p_cur, 0);
+    for (int32_t c = 0; c < nchunks; ++c) {
+        const int buf = c & 1;
+        const int32_t lo = c * WAVE, cnt = min(WAVE, n - lo);
+        const Q q_cur = q_nxt;
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        const int32_t base = __shfl(p_cur.rpv, 0);
+        const int32_t E = p_cur.endv - base;
+        const bool act = lane < cnt;
+        const int32_t i = lo + lane;
+        auto lvl_out = [&](int32_t r) -> int32_t {
+            return r >= lo + WAVE - WK_W ? L->lr[r & (WK_W - 1)]
+                                         : (ld_relaxed(&a.lev[r]) & lmask);
+        };
+        int32_t best = -1;       // largest level of the dependencies before the chunk
+        uint64_t dep = 0;        // dependencies in the chunk, by lane
+        // rewritten rows first (their lists come from HBM), one at a time by
+        // the whole wave, before the next chunk's loads are issued
+        const bool rw = act && q_cur.ne >= q_cur.nb;
+        for (uint64_t m = __ballot(rw); m != 0; m &= m - 1) {
+            const int owner = __builtin_ctzll(m);
+            const int32_t nb = __shfl(q_cur.nb, owner), ne = __shfl(q_cur.ne, owner);
+            const int32_t io = lo + owner;
+            int32_t mx = -1;
+            uint64_t dm = 0;
+            for (int32_t p0 = nb; p0 < ne; p0 += WAVE) {
+                const int32_t pp = p0 + lane;
+                int32_t r = pp < ne ? a.pat[pp] : -1;
+                if (pp < ne && (r < 0 || r >= io)) {
+                    __hip_atomic_store(a.err, (int32_t)RWT_ERR_INVALID_ARG, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    r = -1;
+                }
+                if (r >= 0 && r < lo) mx = max(mx, lvl_out(r));
+                if (r >= lo) dm |= 1ull << (r - lo);
+            }
+            mx = wave_max(mx);
+            // OR of the lanes' in-chunk masks
+            for (int o = WAVE / 2; o > 0; o >>= 1) dm |= __shfl_xor(dm, o);
+            if (lane == owner) {
+                best = mx;
+                dep = dm;
+            }
+        }
+        // the next chunks' loads
+        const P p_n2 = load_p(c + 2);
+        q_nxt = load_q(p_nxt);
+        if (c + 1 < nchunks) stage(p_nxt, buf ^ 1);
+        const int32_t* ej = L->ej[buf];
+        L->rp[lane] = p_cur.rpv - base;
+        if (lane == 0) L->rp[cnt] = E;
+        if (E <= WK_ECAP) {
+            // levels of the staged dependencies before the chunk: ring, then
+            // (rare) older ones from HBM in a second pass
+            const int32_t ring_lo = lo + WAVE - WK_W;
+            bool far = false;
+            constexpr int U = WK_ECAP / WAVE;
+            int32_t rv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t e = lane + u * WAVE;
+                rv[u] = e < E ? ej[e] : lo;   // padding: an in-chunk row
+            }
+            int32_t lv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                lv[u] = (rv[u] < lo && rv[u] >= ring_lo) ? L->lr[rv[u] & (WK_W - 1)] : -1;
+                far = far || rv[u] < ring_lo;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t e = lane + u * WAVE;
+                if (e < E) L->el[e] = lv[u];
+            }
+            if (__ballot(far) != 0)
+                for (int32_t e = lane; e < E; e += WAVE) {
+                    const int32_t r = ej[e];
+                    if (r < ring_lo) L->el[e] = ld_relaxed(&a.lev[r]) & lmask;
+                }
+        }
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        // L's rows: long ones (and every row of an unstaged chunk) by the
+        // whole wave, the others by their own lane
+        const bool staged = E <= WK_ECAP;
+        const int32_t eb = act ? L->rp[lane] : 0, ee = act ? L->rp[lane + 1] - 1 : 0;   // no diagonal
+        const bool coop = act && !rw && (!staged || ee - eb > WK_LONG);
+        for (uint64_t m = __ballot(coop); m != 0; m &= m - 1) {
+            const int o = __builtin_ctzll(m);
+            const int32_t cb = __shfl(eb, o), ce = __shfl(ee, o);
+            int32_t mx = -1;
+            uint64_t dm = 0;
+            for (int32_t e0 = cb; e0 < ce; e0 += WAVE) {
+                const int32_t e = e0 + lane;
+                if (e < ce) {
+                    const int32_t r = staged ? ej[e] : a.colidx[base + e];
+                    if (r < lo) mx = max(mx, staged ? L->el[e] : lvl_out(r));
+                    else dm |= 1ull << (r - lo);
+                }
+            }
+            mx = wave_max(mx);
+            for (int s = WAVE / 2; s > 0; s >>= 1) dm |= __shfl_xor(dm, s);
+            if (lane == o) {
+                best = mx;
+                dep = dm;
+            }
+        }
+        if (act && !rw && !coop)
+            for (int32_t e = eb; e < ee; ++e) {
+                const int32_t r = ej[e];
+                if (r < lo) best = max(best, L->el[e]);
+                else dep |= 1ull << (r - lo);
+            }
+        uint64_t done = __ballot(!act);
+        int32_t li = 0;
+        for (int round = 0; done != ~0ull && round < WAVE; ++round) {
+            const bool ready = act && !((done >> lane) & 1ull) && (dep & ~done) == 0;
+            if (ready) {
+                int32_t mx = best;
+                for (uint64_t d = dep; d != 0; d &= d - 1)
+                    mx = max(mx, L->lr[(lo + __builtin_ctzll(d)) & (WK_W - 1)]);
+                li = mx + 1;
+                L->lr[i & (WK_W - 1)] = li;
+            }
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+            done |= __ballot(ready);
+        }
+        if (done != ~0ull && lane == 0)   // a dependency on or after its own row
+            __hip_atomic_store(a.err, (int32_t)RWT_ERR_INVALID_ARG, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        if (act) st_relaxed(&a.lev[i], (int32_t)(tagbits | (uint32_t)li));
+        p_cur = p_nxt;
+        p_nxt = p_n2;
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
+}  // namespace rwt

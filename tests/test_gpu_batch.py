@@ -162,17 +162,25 @@ def test_batch_explicit_targets(orc):
 
 
 def test_batch_solve_bitwise_equals_single_plan(orc):
-    """Same block size and lanes: the batched block body is the plain one."""
+    """The schedule the batch chose per matrix (the row-order walk, or
+    sync-free blocks with the same block size and lanes: the batched block
+    body is the plain one) gives the single-matrix plan's bits."""
     from paper_2609_40159_amd.api import Plan
     mats = [m for m in mixed_matrices() if m[2] > 0]
     bt, gm, rhs = make_batch(mats, [])
     bt.run()
+    kinds = set()
     for i, ((name, L, k), (G, Bd, Xd)) in enumerate(zip(mats, gm)):
         pi = bt.plan_info(i)
-        p = Plan(G, algo="syncfree", kmax=k, block_rows=pi["block_rows"],
-                 lanes_per_row=pi["lanes_per_row"], rhs_chunk=pi["rhs_chunk"])
+        kinds.add(pi["algo"] == "walk")
+        if pi["algo"] == "walk":
+            p = Plan(G, algo="walk", kmax=k)
+        else:
+            p = Plan(G, algo="syncfree", kmax=k, block_rows=pi["block_rows"],
+                     lanes_per_row=pi["lanes_per_row"], rhs_chunk=pi["rhs_chunk"])
         X1 = p.solve(Bd)
         assert torch.equal(X1, Xd), name
+    assert kinds == {True, False}     # both kinds of schedule in the batch
 
 
 def test_batch_graph_replays_with_changing_candidates(orc):
@@ -316,14 +324,15 @@ def test_batch_argument_errors():
 
 
 def test_batch_candidate_modes_agree(orc):
-    """Row-block chains and per-candidate level sweeps give the same
-    statistics (both equal to the oracle's), for every matrix and mode."""
+    """Row-block chains, per-candidate level sweeps and row-order walks give
+    the same statistics (all equal to the oracle's), for every matrix and
+    mode."""
     mats = mixed_matrices()
     cands = explicit(candidate_sets(orc, mats, 5), levels_of(orc, mats))
     levels = levels_of(orc, mats)
     need = pattern_need(orc, mats, cands, levels)
     got = {}
-    for mode in ("blocks", "sweep", "auto"):
+    for mode in ("blocks", "sweep", "walk", "auto"):
         bt, gm, rhs = make_batch(mats, cands, with_targets=True, pattern_cap=need, cand_mode=mode)
         info = bt.info
         if mode == "blocks":
