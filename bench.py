@@ -77,7 +77,7 @@ def parse():
     ap.add_argument("--cpu-batch-stride", type=int, default=4,
                     help="the batched CPU baseline runs every this many matrices of the batch")
     ap.add_argument("--no-compare", action="store_true",
-                    help="skip the comparison solves (original DAG, forced schedules)")
+                    help="skip the comparison runs (original DAG, forced schedules, per-matrix batch)")
     ap.add_argument("--block-rows", type=int, default=0,
                     help="128^3 step plan: rows per sync-free block (0: timed at plan creation; "
                          "fix it for counter runs)")
@@ -310,6 +310,12 @@ def run_batched(args, man, gen, dev, hop_ns):
     full.capture()
     res["graph_ms"] = timed_events(full.launch, 3, warm=1, stream=full.stream)
     del full
+    head = {"elapsed_s": elapsed, "steps": K, "step_bytes": b_step,
+            "main_ms": res["main_kernel_ms"]}
+    cpu_in = {"cand_mat": cand_mat, "rows_l": rows_l, "levels": [inf.level.cpu().numpy()
+                                                                 for inf in infos]}
+    if args.no_compare:   # counter runs: the timed launches only
+        return res, head, cpu_in
     # ---- solves only: one launch vs one launch per matrix (same schedules) ----
     solves = Batch(mats, [], None, None, block_rows=R)
     solves.capture()
@@ -352,10 +358,6 @@ def run_batched(args, man, gen, dev, hop_ns):
     res["batched_stats_equal_plain"] = bool(same)
     del cands
     log("candidate-only batch timed")
-    head = {"elapsed_s": elapsed, "steps": K, "step_bytes": b_step,
-            "main_ms": res["main_kernel_ms"]}
-    cpu_in = {"cand_mat": cand_mat, "rows_l": rows_l, "levels": [inf.level.cpu().numpy()
-                                                                 for inf in infos]}
     return res, head, cpu_in
 
 

@@ -249,9 +249,9 @@ __global__ void __launch_bounds__(SV_THREADS) k_solve_sf(SolveArgs a) {
 // One wave per right-hand-side column, each walking the rows in order
 // (walk.hpp); waves past the last column return at once (the walk uses no
 // workgroup barrier).
-constexpr int WALK_WAVES = 2;   // two walks per workgroup: 2 x 39 KB of LDS (FP64)
+constexpr int WALK_WAVES = 2;   // two walks per workgroup: 2 x 28 KB of LDS (FP64)
 template <typename T, bool TRANS>
-__global__ void __launch_bounds__(SV_THREADS) k_solve_walk(SolveArgs a) {
+__global__ void __launch_bounds__(WAVE * WALK_WAVES) k_solve_walk(SolveArgs a) {
     extern __shared__ __align__(16) unsigned char s_raw[];
     const int w = threadIdx.x / WAVE;
     const int32_t q = blockIdx.x * WALK_WAVES + w;

@@ -10,9 +10,12 @@
 // internal dependencies itself, in a few rounds of register ballots,
 // instead of one global synchronization per level:
 //   stage   the chunk's entry pointers are loaded two chunks ahead; its
-//           contiguous CSR (or successor-list) entries are copied one chunk
-//           ahead straight into an LDS buffer (global_load_lds: no
-//           registers, coalesced), its right-hand sides into registers;
+//           contiguous CSR (or successor-list) entries one chunk ahead into
+//           registers (coalesced, lane l holding entries l, l + 64, ...),
+//           its right-hand sides likewise.  (Copies straight into LDS
+//           would need no registers, but the compiler makes every later
+//           LDS access wait for such a copy, which exposes a full memory
+//           latency per chunk.);
 //   flat    the wave turns the value of every staged entry whose dependency
 //           lies before the chunk into the product v * x_dep (x from an LDS
 //           ring of the last WK_W solved values, older ones from HBM), one
@@ -41,32 +44,105 @@ constexpr int WK_W = 2048;            // ring: the last WK_W solved values (powe
 constexpr int WK_ECAP = 960;          // entries staged per chunk (multiple of 64; a chunk
                                       // of rows of about 9 entries holds about 580)
 
-typedef __attribute__((address_space(3))) void* wk_lds_ptr;
-typedef __attribute__((address_space(1))) void* wk_glb_ptr;
+constexpr int WK_U = WK_ECAP / WAVE;  // staged entries per lane
 
-// Copy words [0, count) of src into LDS dst, 64 four-byte words per
-// instruction, lane l taking word 64u + l (words past count repeat the
-// last one and land past count in dst); CAP words at most (wave-uniform
-// loop).  Completion is waited for with vmcnt.
-template <int CAP>
-__device__ __forceinline__ void wk_copy_words(const uint32_t* src, int32_t count, uint32_t* dst) {
+// Entries [0, count) of src (count <= WK_ECAP, the same in every lane) into
+// registers: lane l takes entries l, l + 64, ...; slots past count repeat
+// the last entry (never used).  Every slot is loaded, so the number of
+// loads in flight is fixed and the compiler's waits for the loads issued
+// before these stay exact (a variable count makes it wait for all of them);
+// with count = 0 the loads read safe[0] instead, which must be readable
+// (the value is never used).
+template <typename V>
+__device__ __forceinline__ void wk_fetch(const V* src, int32_t count, const void* safe,
+                                         V (&dst)[WK_U]) {
     const int lane = lane_id();
-    count = __builtin_amdgcn_readfirstlane(count);   // the same in every lane
+    count = __builtin_amdgcn_readfirstlane(count);
+    const V* s = count > 0 ? src : static_cast<const V*>(safe);
     const int32_t last = count > 0 ? count - 1 : 0;
 #pragma unroll
-    for (int u = 0; u < CAP / WAVE; ++u) {
-        if (u * WAVE >= count) break;
-        const int32_t w = min(u * WAVE + lane, last);
-        __builtin_amdgcn_global_load_lds((wk_glb_ptr)(src + w), (wk_lds_ptr)(dst + u * WAVE), 4, 0,
-                                         0);
-    }
+    for (int u = 0; u < WK_U; ++u) dst[u] = s[min(u * WAVE + lane, last)];
+}
+
+// Wait for every vector memory access of this wave (vmcnt(0)), as an
+// instruction the compiler knows of: its own later waits count from it.
+__device__ __forceinline__ void wk_wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// Wave-wide reductions through DPP lane moves (ALU speed) instead of LDS
+// shuffles; every lane must be active.  Lanes exchange partners inside
+// quads (xor 1, xor 2), then across the two quads of each 8 (half mirror)
+// and the two 8s of each 16 (mirror), so every lane of a 16-lane row holds
+// the row's total; the four row totals are combined as (r0 + r1) +
+// (r2 + r3).  A fixed order: the result is the same in every lane and on
+// every run.
+template <int CTRL>
+__device__ __forceinline__ uint32_t wk_dpp(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double wk_dpp(double v) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint64_t lo = wk_dpp<CTRL>((uint32_t)b), hi = wk_dpp<CTRL>((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)((hi << 32) | lo));
+}
+template <int CTRL>
+__device__ __forceinline__ float wk_dpp(float v) {
+    return __uint_as_float(wk_dpp<CTRL>(__float_as_uint(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ uint64_t wk_dpp(uint64_t v) {
+    const uint64_t lo = wk_dpp<CTRL>((uint32_t)v), hi = wk_dpp<CTRL>((uint32_t)(v >> 32));
+    return (hi << 32) | lo;
+}
+template <int CTRL>
+__device__ __forceinline__ int32_t wk_dpp(int32_t v) {
+    return (int32_t)wk_dpp<CTRL>((uint32_t)v);
+}
+__device__ __forceinline__ uint32_t wk_lane_val(uint32_t v, int l) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+__device__ __forceinline__ int32_t wk_lane_val(int32_t v, int l) {
+    return __builtin_amdgcn_readlane(v, l);
+}
+__device__ __forceinline__ double wk_lane_val(double v, int l) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint64_t lo = wk_lane_val((uint32_t)b, l), hi = wk_lane_val((uint32_t)(b >> 32), l);
+    return __longlong_as_double((long long)((hi << 32) | lo));
+}
+__device__ __forceinline__ float wk_lane_val(float v, int l) {
+    return __uint_as_float(wk_lane_val(__float_as_uint(v), l));
+}
+__device__ __forceinline__ uint64_t wk_lane_val(uint64_t v, int l) {
+    return ((uint64_t)wk_lane_val((uint32_t)(v >> 32), l) << 32) | wk_lane_val((uint32_t)v, l);
+}
+constexpr int WK_DPP_XOR1 = 0xB1;          // quad_perm [1, 0, 3, 2]
+constexpr int WK_DPP_XOR2 = 0x4E;          // quad_perm [2, 3, 0, 1]
+constexpr int WK_DPP_HALF_MIRROR = 0x141;  // lane i <-> 7 - i within 8
+constexpr int WK_DPP_MIRROR = 0x140;       // lane i <-> 15 - i within 16
+template <typename V, typename Op>
+__device__ __forceinline__ V wk_reduce(V v, Op op) {
+    v = op(v, wk_dpp<WK_DPP_XOR1>(v));
+    v = op(v, wk_dpp<WK_DPP_XOR2>(v));
+    v = op(v, wk_dpp<WK_DPP_HALF_MIRROR>(v));
+    v = op(v, wk_dpp<WK_DPP_MIRROR>(v));
+    return op(op(wk_lane_val(v, 0), wk_lane_val(v, 16)), op(wk_lane_val(v, 32), wk_lane_val(v, 48)));
+}
+template <typename T>
+__device__ __forceinline__ T wk_sum(T v) {
+    return wk_reduce(v, [](T x, T y) { return x + y; });
+}
+__device__ __forceinline__ uint64_t wk_or(uint64_t v) {
+    return wk_reduce(v, [](uint64_t x, uint64_t y) { return x | y; });
+}
+__device__ __forceinline__ int32_t wk_max(int32_t v) {
+    return wk_reduce(v, [](int32_t x, int32_t y) { return x > y ? x : y; });
 }
 
 template <typename T>
 struct WkLds {
     T xr[WK_W];                     // x at position t in xr[t & (WK_W - 1)]
-    T ev[2][WK_ECAP];               // staged values (double-buffered), then products
-    int32_t ej[2][WK_ECAP];         // staged dependency rows
+    T ev[WK_ECAP];                  // the chunk's values; products for dependencies before it
+    int32_t ej[WK_ECAP];            // the chunk's dependency rows
     int32_t rp[WAVE + 1];           // entry starts of the chunk's rows, by local row index
 };
 
@@ -136,18 +212,19 @@ __device__ __forceinline__ WkRhs<T> wk_load_rhs(const WkArgs& a, int32_t c, int3
     return r;
 }
 
-// the chunk's entries (at most WK_ECAP) into LDS buffer buf
+// the chunk's entries (at most WK_ECAP) into registers
 template <typename T>
-__device__ __forceinline__ void wk_stage_entries(const WkArgs& a, const WkPtr& p, WkLds<T>* L,
-                                                 int buf) {
-    const int32_t base = __shfl(p.rpv, 0);
+struct WkStage {
+    int32_t j[WK_U];
+    T v[WK_U];
+};
+template <typename T>
+__device__ __forceinline__ void wk_stage_entries(const WkArgs& a, const WkPtr& p, WkStage<T>& st) {
+    const int32_t base = wk_lane_val(p.rpv, 0);
     const int32_t cnt = min(p.endv - base, WK_ECAP);
-    constexpr int WPE = (int)sizeof(T) / 4;   // words per value
-    wk_copy_words<WK_ECAP>(reinterpret_cast<const uint32_t*>(a.idx + base), cnt,
-                           reinterpret_cast<uint32_t*>(L->ej[buf]));
-    wk_copy_words<WK_ECAP * WPE>(
-        reinterpret_cast<const uint32_t*>(static_cast<const T*>(a.vals) + base), cnt * WPE,
-        reinterpret_cast<uint32_t*>(L->ev[buf]));
+    // a.ptr holds n + 1 >= 2 words: 8 readable bytes for an empty chunk
+    wk_fetch<int32_t>(a.idx + base, cnt, a.ptr, st.j);
+    wk_fetch<T>(static_cast<const T*>(a.vals) + base, cnt, a.ptr, st.v);
 }
 
 // One chunk's rows once the products of the dependencies before the chunk
@@ -155,9 +232,10 @@ __device__ __forceinline__ void wk_stage_entries(const WkArgs& a, const WkPtr& p
 // dependencies.  STAGED: entries from LDS, products already formed; else
 // from HBM (a chunk larger than the stage).  A row with more than WK_LONG
 // dependencies, and every row of an unstaged chunk, is summed by the whole
-// wave (64 entries a step, then a butterfly sum: a fixed order); the others
-// by their own lane, in walk order.
+// wave (64 entries a step, then a fixed-order reduction); the others by
+// their own lane, in walk order.
 constexpr int WK_LONG = 24;
+constexpr int WK_KREG = 4;   // in-chunk dependencies a lane keeps in registers for the rounds
 
 template <typename T, bool TRANS, bool STAGED>
 __device__ __forceinline__ T wk_rows(const WkArgs& a, WkLds<T>* L, const int32_t* ej, const T* ev,
@@ -192,35 +270,33 @@ __device__ __forceinline__ T wk_rows(const WkArgs& a, WkLds<T>* L, const int32_t
     if (act && !TRANS) diag = V(ee - 1);
     T acc = T(0);
     uint64_t dep = 0;
-    // forward: first in-chunk entry (in-chunk entries are a suffix);
-    // transposed: last in-chunk entry (a prefix)
+    // the in-chunk entries: forward a suffix [split, oe), transposed a
+    // prefix [eb, split]
     int32_t split = TRANS ? eb - 1 : oe;
     const bool coop = act && (!STAGED || oe - eb > WK_LONG);
     for (uint64_t m = __ballot(coop); m != 0; m &= m - 1) {
         const int o = __builtin_ctzll(m);
-        const int32_t cb = __shfl(eb, o), ce = __shfl(oe, o);
+        const int32_t cb = wk_lane_val(eb, o), ce = wk_lane_val(oe, o);
         T part = T(0);
         uint64_t dm = 0;
-        int32_t sp = TRANS ? cb - 1 : ce;
+        int32_t nout = 0;   // entries outside the chunk (the same in every lane)
         for (int32_t e0 = cb; e0 < ce; e0 += WAVE) {
             const int32_t e = e0 + lane;
+            bool out = false;
             if (e < ce) {
                 const int32_t r = J(e);
-                if (outside(r)) {
-                    part += term(e, r);
-                } else {
-                    dm |= 1ull << lane_of(r);
-                    sp = TRANS ? max(sp, e) : min(sp, e);
-                }
+                out = outside(r);
+                if (out) part += term(e, r);
+                else dm |= 1ull << lane_of(r);
             }
+            nout += __builtin_popcountll(__ballot(out));
         }
-        part = wave_sum(part);
-        for (int s = WAVE / 2; s > 0; s >>= 1) dm |= __shfl_xor(dm, s);
-        sp = TRANS ? wave_max(sp) : wave_min(sp);
+        part = wk_sum(part);
+        dm = wk_or(dm);
         if (lane == o) {
             acc = part;
             dep = dm;
-            split = sp;
+            split = TRANS ? ce - 1 - nout : cb + nout;
         }
     }
     if (act && !coop) {
@@ -271,21 +347,49 @@ __device__ __forceinline__ T wk_rows(const WkArgs& a, WkLds<T>* L, const int32_t
             }
         }
     }
+    // the first WK_KREG in-chunk terms of each row in registers, in walk
+    // order: value and the lane holding the dependency's x
+    const int32_t nk = act ? (TRANS ? split - eb + 1 : oe - split) : 0;
+    T dv[WK_KREG];
+    int32_t dl[WK_KREG];
+#pragma unroll
+    for (int k = 0; k < WK_KREG; ++k) {
+        dv[k] = T(0);
+        dl[k] = lane;
+        if (k < nk) {
+            const int32_t e = TRANS ? split - k : split + k;
+            dv[k] = V(e);
+            dl[k] = lane_of(J(e)) & (WAVE - 1);
+        }
+    }
+    const bool kused[WK_KREG] = {__ballot(nk > 0) != 0, __ballot(nk > 1) != 0,
+                                 __ballot(nk > 2) != 0, __ballot(nk > 3) != 0};
     // rounds: each solves at least the lowest unsolved position of a valid
-    // (lower triangular) system, so at most WAVE of them
+    // (lower triangular) system, so at most WAVE of them.  The x of an
+    // in-chunk dependency comes from its lane (solved in an earlier round);
+    // terms past the first WK_KREG from the ring.
     uint64_t done = __ballot(!act);
     T xi = T(0);
     for (int round = 0; done != ~0ull && round < WAVE; ++round) {
         const bool ready = act && !((done >> lane) & 1ull) && (dep & ~done) == 0;
+        T xk[WK_KREG];
+#pragma unroll
+        for (int k = 0; k < WK_KREG; ++k) xk[k] = kused[k] ? __shfl(xi, dl[k]) : T(0);
         if (ready) {
-            if (!TRANS) {
-                for (int32_t e = split; e < oe; ++e)
-                    acc += V(e) * L->xr[pos_of(J(e)) & (WK_W - 1)];
-            } else {
-                for (int32_t e = split; e >= eb; --e)
-                    acc += V(e) * L->xr[pos_of(J(e)) & (WK_W - 1)];
+            T s = acc;
+#pragma unroll
+            for (int k = 0; k < WK_KREG; ++k)
+                if (k < nk) s += dv[k] * xk[k];
+            if (nk > WK_KREG) {
+                if (!TRANS) {
+                    for (int32_t e = split + WK_KREG; e < oe; ++e)
+                        s += V(e) * L->xr[pos_of(J(e)) & (WK_W - 1)];
+                } else {
+                    for (int32_t e = split - WK_KREG; e >= eb; --e)
+                        s += V(e) * L->xr[pos_of(J(e)) & (WK_W - 1)];
+                }
             }
-            xi = (b_i - acc) / diag;
+            xi = (b_i - s) / diag;
             L->xr[(t0 + lane) & (WK_W - 1)] = xi;
         }
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
@@ -309,57 +413,53 @@ __device__ void wk_solve(const WkArgs& a, WkLds<T>* L) {
     WkPtr p_cur = wk_load_ptr<TRANS>(a, 0, nchunks);
     WkPtr p_nxt = wk_load_ptr<TRANS>(a, 1, nchunks);
     WkRhs<T> r_nxt = wk_load_rhs<T, TRANS>(a, 0, nchunks, p_cur);
-    wk_stage_entries<T>(a, p_cur, L, 0);
+    WkStage<T> st;
+    wk_stage_entries<T>(a, p_cur, st);
+    int32_t* ej = L->ej;
+    T* ev = L->ev;
+    // the previous chunk's solution: stored together with the next chunk's
+    // loads, so that the wait for those loads (every load issued a chunk
+    // earlier is waited for together) does not wait for a store just issued
+    T x_prev = T(0);
+    int32_t at_prev = -1;
     for (int32_t c = 0; c < nchunks; ++c) {
-        const int buf = c & 1;
         const WkChunk ch = wk_chunk<TRANS>(n, c);
         const int32_t lo = ch.lo, cnt = ch.cnt, hi = lo + cnt - 1;
         const int32_t t0 = c * WAVE;                       // first position of the chunk
         const WkRhs<T> r_cur = r_nxt;
-        // this chunk's stage has landed (its loads were issued a chunk ago)
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        const int32_t base = __shfl(p_cur.rpv, 0);
+        const int32_t base = wk_lane_val(p_cur.rpv, 0);
         const int32_t E = p_cur.endv - base;
-        // the next chunks' loads; nothing in this chunk waits for them
-        // except a dependency older than the ring or a chunk larger than
-        // the stage
-        const WkPtr p_n2 = wk_load_ptr<TRANS>(a, c + 2, nchunks);
-        r_nxt = wk_load_rhs<T, TRANS>(a, c + 1, nchunks, p_nxt);
-        if (c + 1 < nchunks) wk_stage_entries<T>(a, p_nxt, L, buf ^ 1);
-        int32_t* ej = L->ej[buf];
-        T* ev = L->ev[buf];
         L->rp[lane] = p_cur.rpv - base;
         if (lane == 0) L->rp[cnt] = E;
-        T xi;
-        if (E <= WK_ECAP) {
-            // flat products of the staged entries whose dependency precedes
-            // the chunk, x from the ring; dependencies older than the ring
-            // in a second pass (rare: it waits for HBM)
-            const int32_t ring_lo = t0 + WAVE - WK_W;
+        const bool staged = E <= WK_ECAP;
+        const int32_t ring_lo = t0 + WAVE - WK_W;
+        if (!staged) {
+            // the chunk reads its entries from HBM; the staged registers go
+            // unused, but the wait below keeps the compiler's count of the
+            // loads in flight the same on both paths
+            wk_wait_vm();
+        } else {
+            // the staged entries into LDS, the value of every dependency
+            // before the chunk multiplied by its x from the ring on the way;
+            // dependencies older than the ring in a second pass (rare: it
+            // waits for HBM)
             bool far = false;
-            // unrolled over the stage so that the loads of several entries
-            // are in flight together (LDS latency, not issue, bounds it)
-            constexpr int U = WK_ECAP / WAVE;
-            int32_t rv[U];
-            T vv[U];
+            T xv[WK_U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
+            for (int u = 0; u < WK_U; ++u) {
                 const int32_t e = lane + u * WAVE;
-                rv[u] = e < E ? ej[e] : (TRANS ? hi : lo);   // padding: an in-chunk row
-                vv[u] = e < E ? ev[e] : T(0);
-            }
-            T xv[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int32_t t = TRANS ? n - 1 - rv[u] : rv[u];
-                xv[u] = (t < t0 && t >= ring_lo) ? L->xr[t & (WK_W - 1)] : T(0);
+                const int32_t r = e < E ? st.j[u] : (TRANS ? hi : lo);   // padding: in the chunk
+                const int32_t t = TRANS ? n - 1 - r : r;
+                xv[u] = (t < t0 && t >= ring_lo) ? L->xr[t & (WK_W - 1)] : T(1);
                 far = far || t < ring_lo;
             }
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
+            for (int u = 0; u < WK_U; ++u) {
                 const int32_t e = lane + u * WAVE;
-                const int32_t t = TRANS ? n - 1 - rv[u] : rv[u];
-                if (e < E && t < t0 && t >= ring_lo) ev[e] = vv[u] * xv[u];
+                if (e < E) {
+                    ej[e] = st.j[u];
+                    ev[e] = st.v[u] * xv[u];
+                }
             }
             if (__ballot(far) != 0) {
                 for (int32_t e = lane; e < E; e += WAVE) {
@@ -368,16 +468,31 @@ __device__ void wk_solve(const WkArgs& a, WkLds<T>* L) {
                     if (t < ring_lo) ev[e] = ev[e] * ld_relaxed(&X[r]);
                 }
             }
-            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        }
+        // the next chunks' loads (the staging registers are free again) and
+        // the previous chunk's store; the rows of a staged chunk wait for
+        // none of them.  Pointers and right-hand sides first: the copies at
+        // the end of the chunk wait for them (loads complete in order), not
+        // for the staged entries.  Past the last chunk the loads repeat it.
+        const WkPtr p_n2 = wk_load_ptr<TRANS>(a, c + 2, nchunks);
+        r_nxt = wk_load_rhs<T, TRANS>(a, c + 1, nchunks, p_nxt);
+        wk_stage_entries<T>(a, p_nxt, st);
+        if (at_prev >= 0) X[at_prev] = x_prev;
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        T xi;
+        if (staged) {
             xi = wk_rows<T, TRANS, true>(a, L, ej, ev, base, lo, cnt, t0, r_cur.b, r_cur.diag);
         } else {
             xi = wk_rows<T, TRANS, false>(a, L, ej, ev, base, lo, cnt, t0, r_cur.b, r_cur.diag);
+            wk_wait_vm();   // its own loads, so that both paths end with the same loads in flight
         }
-        // publish the chunk (rows contiguous: one coalesced store)
-        if (lane < cnt) X[TRANS ? hi - lane : lo + lane] = xi;
+        // rows contiguous: one coalesced store (issued with the next loads)
+        x_prev = xi;
+        at_prev = lane < cnt ? (TRANS ? hi - lane : lo + lane) : -1;
         p_cur = p_nxt;
         p_nxt = p_n2;
     }
+    if (at_prev >= 0) X[at_prev] = x_prev;
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
@@ -391,7 +506,7 @@ __device__ void wk_solve(const WkArgs& a, WkLds<T>* L) {
 // ---------------------------------------------------------------------------
 struct WkLvlLds {
     int32_t lr[WK_W];               // level at position t in lr[t & (WK_W - 1)]
-    int32_t ej[2][WK_ECAP];         // staged dependency rows (double-buffered)
+    int32_t ej[WK_ECAP];            // the chunk's dependency rows
     int32_t el[WK_ECAP];            // their levels when before the chunk
     int32_t rp[WAVE + 1];
 };
@@ -446,20 +561,19 @@ __device__ void wk_levels(const WkLvlArgs& a, WkLvlLds* L) {
         const int32_t nb = a.pat_ptr[q], ne = a.pat_ptr[q + 1] - 1;
         return rw ? Q{nb, ne} : Q{0, -1};
     };
-    auto stage = [&](const P& p, int buf) {
-        const int32_t base = __shfl(p.rpv, 0);
-        wk_copy_words<WK_ECAP>(reinterpret_cast<const uint32_t*>(a.colidx + base),
-                               min(p.endv - base, WK_ECAP), reinterpret_cast<uint32_t*>(L->ej[buf]));
+    int32_t sj[WK_U];   // the chunk's entries, staged in registers
+    auto stage = [&](const P& p) {
+        const int32_t base = wk_lane_val(p.rpv, 0);
+        wk_fetch<int32_t>(a.colidx + base, min(p.endv - base, WK_ECAP), a.rowptr, sj);
     };
     P p_cur = load_p(0), p_nxt = load_p(1);
     Q q_nxt = load_q(p_cur);
-    stage(p_cur, 0);
+    stage(p_cur);
+    int32_t* ej = L->ej;
     for (int32_t c = 0; c < nchunks; ++c) {
-        const int buf = c & 1;
         const int32_t lo = c * WAVE, cnt = min(WAVE, n - lo);
         const Q q_cur = q_nxt;
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        const int32_t base = __shfl(p_cur.rpv, 0);
+        const int32_t base = wk_lane_val(p_cur.rpv, 0);
         const int32_t E = p_cur.endv - base;
         const bool act = lane < cnt;
         const int32_t i = lo + lane;
@@ -470,11 +584,11 @@ __device__ void wk_levels(const WkLvlArgs& a, WkLvlLds* L) {
         int32_t best = -1;       // largest level of the dependencies before the chunk
         uint64_t dep = 0;        // dependencies in the chunk, by lane
         // rewritten rows first (their lists come from HBM), one at a time by
-        // the whole wave, before the next chunk's loads are issued
+        // the whole wave
         const bool rw = act && q_cur.ne >= q_cur.nb;
         for (uint64_t m = __ballot(rw); m != 0; m &= m - 1) {
             const int owner = __builtin_ctzll(m);
-            const int32_t nb = __shfl(q_cur.nb, owner), ne = __shfl(q_cur.ne, owner);
+            const int32_t nb = wk_lane_val(q_cur.nb, owner), ne = wk_lane_val(q_cur.ne, owner);
             const int32_t io = lo + owner;
             int32_t mx = -1;
             uint64_t dm = 0;
@@ -489,41 +603,41 @@ __device__ void wk_levels(const WkLvlArgs& a, WkLvlLds* L) {
                 if (r >= 0 && r < lo) mx = max(mx, lvl_out(r));
                 if (r >= lo) dm |= 1ull << (r - lo);
             }
-            mx = wave_max(mx);
-            // OR of the lanes' in-chunk masks
-            for (int o = WAVE / 2; o > 0; o >>= 1) dm |= __shfl_xor(dm, o);
+            mx = wk_max(mx);
+            dm = wk_or(dm);   // OR of the lanes' in-chunk masks
             if (lane == owner) {
                 best = mx;
                 dep = dm;
             }
         }
-        // the next chunks' loads
-        const P p_n2 = load_p(c + 2);
-        q_nxt = load_q(p_nxt);
-        if (c + 1 < nchunks) stage(p_nxt, buf ^ 1);
-        const int32_t* ej = L->ej[buf];
         L->rp[lane] = p_cur.rpv - base;
         if (lane == 0) L->rp[cnt] = E;
-        if (E <= WK_ECAP) {
-            // levels of the staged dependencies before the chunk: ring, then
-            // (rare) older ones from HBM in a second pass
+        if (E > WK_ECAP) {
+            // the chunk reads its entries from HBM; the staged registers go
+            // unused, but the wait keeps the compiler's count of the loads
+            // in flight the same on both paths
+            wk_wait_vm();
+        } else {
+            // the staged entries into LDS with the levels of the dependencies
+            // before the chunk: ring, then (rare) older ones from HBM in a
+            // second pass
             const int32_t ring_lo = lo + WAVE - WK_W;
             bool far = false;
-            constexpr int U = WK_ECAP / WAVE;
-            int32_t rv[U];
+            int32_t rv[WK_U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
+            for (int u = 0; u < WK_U; ++u) {
                 const int32_t e = lane + u * WAVE;
-                rv[u] = e < E ? ej[e] : lo;   // padding: an in-chunk row
+                rv[u] = e < E ? sj[u] : lo;   // padding: an in-chunk row
+                if (e < E) ej[e] = rv[u];
             }
-            int32_t lv[U];
+            int32_t lv[WK_U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
+            for (int u = 0; u < WK_U; ++u) {
                 lv[u] = (rv[u] < lo && rv[u] >= ring_lo) ? L->lr[rv[u] & (WK_W - 1)] : -1;
                 far = far || rv[u] < ring_lo;
             }
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
+            for (int u = 0; u < WK_U; ++u) {
                 const int32_t e = lane + u * WAVE;
                 if (e < E) L->el[e] = lv[u];
             }
@@ -533,6 +647,12 @@ __device__ void wk_levels(const WkLvlArgs& a, WkLvlLds* L) {
                     if (r < ring_lo) L->el[e] = ld_relaxed(&a.lev[r]) & lmask;
                 }
         }
+        // the next chunks' loads (the staging registers are free again):
+        // pointers and list bounds first, since the copies at the end of the
+        // chunk wait for them (loads complete in order), then the entries
+        const P p_n2 = load_p(c + 2);
+        q_nxt = load_q(p_nxt);
+        stage(p_nxt);
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
         // L's rows: long ones (and every row of an unstaged chunk) by the
         // whole wave, the others by their own lane
@@ -541,7 +661,7 @@ __device__ void wk_levels(const WkLvlArgs& a, WkLvlLds* L) {
         const bool coop = act && !rw && (!staged || ee - eb > WK_LONG);
         for (uint64_t m = __ballot(coop); m != 0; m &= m - 1) {
             const int o = __builtin_ctzll(m);
-            const int32_t cb = __shfl(eb, o), ce = __shfl(ee, o);
+            const int32_t cb = wk_lane_val(eb, o), ce = wk_lane_val(ee, o);
             int32_t mx = -1;
             uint64_t dm = 0;
             for (int32_t e0 = cb; e0 < ce; e0 += WAVE) {
@@ -552,26 +672,46 @@ __device__ void wk_levels(const WkLvlArgs& a, WkLvlLds* L) {
                     else dm |= 1ull << (r - lo);
                 }
             }
-            mx = wave_max(mx);
-            for (int s = WAVE / 2; s > 0; s >>= 1) dm |= __shfl_xor(dm, s);
+            mx = wk_max(mx);
+            dm = wk_or(dm);
             if (lane == o) {
                 best = mx;
                 dep = dm;
             }
         }
+        if (!staged) wk_wait_vm();   // as in the row walk: the same loads in flight on both paths
         if (act && !rw && !coop)
             for (int32_t e = eb; e < ee; ++e) {
                 const int32_t r = ej[e];
                 if (r < lo) best = max(best, L->el[e]);
                 else dep |= 1ull << (r - lo);
             }
+        // rounds as in the row walk: the levels of the first WK_KREG in-chunk
+        // dependencies from their lanes, any others from the ring
+        int32_t dl[WK_KREG];
+        uint64_t drest = dep;
+#pragma unroll
+        for (int k = 0; k < WK_KREG; ++k) {
+            dl[k] = drest != 0 ? __builtin_ctzll(drest) : lane;
+            drest &= drest - 1;
+        }
+        const bool kused[WK_KREG] = {__ballot(dep != 0) != 0,
+                                     __ballot(__builtin_popcountll(dep) > 1) != 0,
+                                     __ballot(__builtin_popcountll(dep) > 2) != 0,
+                                     __ballot(__builtin_popcountll(dep) > 3) != 0};
         uint64_t done = __ballot(!act);
-        int32_t li = 0;
+        int32_t li = -1;   // level of this lane's row once solved
         for (int round = 0; done != ~0ull && round < WAVE; ++round) {
             const bool ready = act && !((done >> lane) & 1ull) && (dep & ~done) == 0;
+            int32_t lk[WK_KREG];
+#pragma unroll
+            for (int k = 0; k < WK_KREG; ++k) lk[k] = kused[k] ? __shfl(li, dl[k]) : -1;
             if (ready) {
                 int32_t mx = best;
-                for (uint64_t d = dep; d != 0; d &= d - 1)
+#pragma unroll
+                // unused slots read -1: their own unsolved lane, or none
+                for (int k = 0; k < WK_KREG; ++k) mx = max(mx, lk[k]);
+                for (uint64_t d = drest; d != 0; d &= d - 1)
                     mx = max(mx, L->lr[(lo + __builtin_ctzll(d)) & (WK_W - 1)]);
                 li = mx + 1;
                 L->lr[i & (WK_W - 1)] = li;
@@ -582,7 +722,7 @@ __device__ void wk_levels(const WkLvlArgs& a, WkLvlLds* L) {
         if (done != ~0ull && lane == 0)   // a dependency on or after its own row
             __hip_atomic_store(a.err, (int32_t)RWT_ERR_INVALID_ARG, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
-        if (act) st_relaxed(&a.lev[i], (int32_t)(tagbits | (uint32_t)li));
+        if (act) st_relaxed(&a.lev[i], (int32_t)(tagbits | (uint32_t)max(li, 0)));
         p_cur = p_nxt;
         p_nxt = p_n2;
     }
