@@ -46,7 +46,10 @@ constexpr int BT_THREADS = 256;
 constexpr int WK_SOLVE_WAVES = 2;
 constexpr int WK_LEVEL_WAVES = 4;
 constexpr int BT_LDS = SF_LDS_BUDGET;
-constexpr int NSLAB_B = 2;
+// candidate rows whose rewritten pattern outgrows both LDS tiers are redone
+// in workspace slabs (one wave each, n + 1 entries per buffer), this many at
+// a time
+constexpr int NSLAB_B = 64;
 
 struct BatchMatDev {
     int32_t n, R, lanes, nblocks, k, kc;   // kc: right-hand sides per solve chain
