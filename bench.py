@@ -272,7 +272,7 @@ def run_batched(args, man, gen, dev, hop_ns):
            "candidate_rows": bi["nrows"], "upload_s": bi["upload_s"],
            "analyze_all_s": bi["analyze_all_s"]}
     log(f"batch uploaded and analysed; {C} candidates")
-    pcap = 256 * max(1, bi["nrows"])
+    pcap = 64 * max(1, bi["nrows"])   # >= 48 per row: one-pass patterns
     full = Batch(mats, cand_mat, bi["d_ptr"], bi["d_rows"], None, pattern_cap=pcap)
     R = [full.plan_info(m)["block_rows"] for m in range(len(mats))]
     res["create_ms"] = full.info["create_ms"]

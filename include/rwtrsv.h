@@ -718,7 +718,11 @@ typedef struct {
     const int32_t* d_cand_rows;         /* device */
     const int32_t* d_cand_targets;      /* device or NULL */
     int32_t cand_rows_cap;              /* capacity of the concatenated row lists */
-    int32_t pattern_cap;                /* capacity of rewritten-row patterns (0: 64 per row) */
+    int32_t pattern_cap;                /* capacity of rewritten-row patterns (0: 64 per row).
+                                           With at least 48 per row of cand_rows_cap they are
+                                           built in one pass: a fixed slot of 32 entries per
+                                           row, longer rows in the rest of the capacity;
+                                           otherwise in two (lengths, then patterns) */
     int32_t watchdog_ms;
     int32_t cand_mode;                  /* candidate levels: 0 choose per matrix, 1 row-block
                                            chains, 2 one level sweep per candidate, 3 the
@@ -741,7 +745,8 @@ typedef struct {
     int32_t captured;     /* a graph is instantiated */
     double create_ms;
     int32_t sweep_cands;  /* candidates scored by one level sweep */
-    int32_t pad_;
+    int32_t pattern_slot; /* entries of a row's fixed pattern slot (one-pass patterns),
+                             0 when the patterns take two passes */
 } rwt_batch_info;
 
 typedef struct rwt_batch rwt_batch;

@@ -86,7 +86,7 @@ class CandStats(C.Structure):
 class BatchInfo(C.Structure):
     _fields_ = [("tasks", C.c_int32), ("solve_tasks", C.c_int32), ("grid", C.c_int32),
                 ("captured", C.c_int32), ("create_ms", C.c_double), ("sweep_cands", C.c_int32),
-                ("pad_", C.c_int32)]
+                ("pattern_slot", C.c_int32)]
 
 
 class GenParams(C.Structure):

@@ -742,7 +742,9 @@ class Batch:
         d.d_cand_targets = None if cand_targets is None else cand_targets.data_ptr()
         d.cand_rows_cap = int(cand_rows_cap if cand_rows_cap is not None
                               else (cand_rows.numel() if cand_rows is not None else 0))
-        d.pattern_cap = pattern_cap
+        if not 0 <= int(pattern_cap) < 2 ** 31:
+            raise ValueError(f"pattern_cap must be in [0, 2^31), got {pattern_cap}")
+        d.pattern_cap = int(pattern_cap)
         d.watchdog_ms = watchdog_ms
         d.cand_mode = {"auto": 0, "blocks": 1, "sweep": 2, "walk": 3}[cand_mode]
         self.desc = d

@@ -50,6 +50,18 @@ constexpr int BT_LDS = SF_LDS_BUDGET;
 // in workspace slabs (one wave each, n + 1 entries per buffer), this many at
 // a time
 constexpr int NSLAB_B = 64;
+// setup control words: [0] first overflow count, [3] too large, [4]
+// capacity error, [5] rejected row lists, [6] bad list offsets, [7] second
+// overflow count, [8] entries of the pattern overflow region in use, [9]
+// the one-pass patterns did not fit (the two passes follow)
+constexpr int RWCTRL_WORDS = 16;
+// one-pass patterns: a fixed slot of this many entries per candidate row
+// (power-law rows rewritten one level down average about 18 entries, a few
+// percent exceed 32), used when the pattern capacity holds at least
+// PATTERN_ONE_PASS_MIN entries per row; else the lengths pass, a scan and
+// the pattern pass
+constexpr int PATTERN_SLOT = 32;
+constexpr int PATTERN_ONE_PASS_MIN = 48;
 
 struct BatchMatDev {
     int32_t n, R, lanes, nblocks, k, kc;   // kc: right-hand sides per solve chain
@@ -253,7 +265,7 @@ __device__ __forceinline__ void sweep_group(const BatchKArgs& a, const BatchMatD
                 const int32_t q = ((mv >> 24) == tag && (mv & MARK))
                                       ? qb + (int32_t)(mv & (MARK - 1))
                                       : lower_bound_g(a.rows, qb, a.cand_ptr[c + 1], i);
-                const int32_t nb = a.pat_ptr[q], ne = a.pat_ptr[q + 1] - 1;   // new diagonal last
+                const int32_t nb = a.pat_ptr[q], ne = nb + a.counts_q[q] - 1;   // new diagonal last
                 int32_t best = -1;
                 for (int32_t p = nb; p < ne; ++p) {
                     const int32_t j = a.pat[p];
@@ -388,7 +400,7 @@ __device__ __forceinline__ void level_block_group(const BatchKArgs& a, const Bat
             for (uint32_t m = act ? rw : 0u; m != 0; m &= m - 1) {
                 const int s = __builtin_ctz(m);
                 const int32_t q = a.cand_ptr[c0 + s] + (int32_t)((uint32_t)lv[(i - r0) * gs + s] & ~LDS_MARK);
-                const int32_t nb = a.pat_ptr[q], ne = a.pat_ptr[q + 1] - 1;   // new diagonal last
+                const int32_t nb = a.pat_ptr[q], ne = nb + a.counts_q[q] - 1;   // new diagonal last
                 int32_t best = -1;
                 for (int32_t p = nb + gl; p < ne; p += G) {
                     const int32_t j = a.pat[p];
@@ -653,6 +665,7 @@ __global__ void __launch_bounds__(BT_THREADS) k_batch_main(BatchKArgs a) {
                 la.tag = tag;
                 la.mark = MARK;
                 la.pat_ptr = a.pat_ptr;
+                la.pat_len = a.counts_q;
                 la.pat = a.pat;
                 la.qb = qb;
                 la.qmax = a.qcap;
@@ -721,7 +734,7 @@ __global__ void k_batch_begin(const BatchMatDev* mats, int32_t count, uint32_t* 
         ctrl->ticket = 0;
         ctrl->err = 0;
         ctrl->heartbeat = 0;
-        for (int i = 0; i < 8; ++i) rwctrl[i] = 0;
+        for (int i = 0; i < RWCTRL_WORDS; ++i) rwctrl[i] = 0;
     }
     for (int64_t i = tid; i < C; i += nth) {
         cand_done[i] = 0;
@@ -741,6 +754,29 @@ __global__ void k_batch_begin(const BatchMatDev* mats, int32_t count, uint32_t* 
             M.X[i + q * M.ldx] = s;
         }
     }
+}
+
+// Before the two-pass patterns that follow one-pass patterns that did not
+// fit: the overflow lists and marks start again.  Only when *gate != 0.
+__global__ void k_batch_redo_reset(const int32_t* gate, int32_t* rwctrl, int32_t* counts_q,
+                                   unsigned char* ovf_mark, int32_t qcap) {
+    if (ld_relaxed(gate) == 0) return;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    if (tid == 0) {
+        rwctrl[0] = 0;
+        rwctrl[7] = 0;
+    }
+    for (int64_t i = tid; i <= qcap; i += nth) counts_q[i] = 0;
+    for (int64_t i = tid; i < qcap; i += nth) ovf_mark[i] = 0;
+}
+
+// dst[0 .. count) = src[...], only when *gate != 0
+__global__ void k_copy_gated(const int32_t* gate, const int32_t* src, int32_t* dst, int64_t count) {
+    if (ld_relaxed(gate) == 0) return;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = tid; i < count; i += nth) dst[i] = src[i];
 }
 
 // The candidate list as a whole: offsets start at 0, never decrease and end
@@ -820,6 +856,7 @@ struct rwt_batch {
     rwt_cand_stats* stats = nullptr;
     int32_t* counts_q = nullptr;
     int32_t* pat_ptr = nullptr;
+    int32_t* pat_ptr2 = nullptr;
     int32_t* pat = nullptr;
     int32_t* ovf = nullptr;
     int32_t* ovf2 = nullptr;
@@ -832,6 +869,7 @@ struct rwt_batch {
     Ctrl* ctrl = nullptr;
     uint32_t* epoch = nullptr;
     int32_t qcap = 0, pat_cap = 0;
+    int32_t slot_len = 0;          // one-pass patterns: fixed slot per row (0: two passes)
     int grid = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -861,7 +899,7 @@ rwt_plan_opts batch_plan_opts(const rwt_batch_desc* d, const rwt_batch_matrix& m
 
 struct BatchLayout {
     std::vector<size_t> plan_off, plan_bytes;
-    size_t mats, cands, candmat, rwmats, tasks, bitmaps, levs, done, bad, stats, counts, patptr, pat, ovf, ovf2,
+    size_t mats, cands, candmat, rwmats, tasks, bitmaps, levs, done, bad, stats, counts, patptr, patptr2, pat, ovf, ovf2,
         ovfmark, rwctrl, slab, scan, ctrl, epoch, blkmin, total;
     int64_t bitmap_words, lev_words, slab_stride;
     int32_t qcap, pat_cap, slab_cap, ntasks_max;
@@ -939,12 +977,13 @@ rwt_status layout_batch(const rwt_batch_desc* d, BatchLayout* L) {
     L->bad = take(std::max(1, d->num_cand));
     L->stats = take(sizeof(rwt_cand_stats) * std::max(1, d->num_cand));
     L->counts = take(sizeof(int32_t) * ((size_t)L->qcap + 1));
-    L->patptr = take(sizeof(int32_t) * ((size_t)L->qcap + 2));   // at least two: the walk reads q, q + 1
+    L->patptr = take(sizeof(int32_t) * ((size_t)L->qcap + 2));
+    L->patptr2 = take(sizeof(int32_t) * ((size_t)L->qcap + 2));   // two-pass starts after one pass
     L->pat = take(sizeof(int32_t) * (size_t)L->pat_cap);
     L->ovf = take(sizeof(int32_t) * std::max(1, L->qcap));
     L->ovf2 = take(sizeof(int32_t) * std::max(1, L->qcap));
     L->ovfmark = take(std::max(1, L->qcap));
-    L->rwctrl = take(sizeof(int32_t) * 8);
+    L->rwctrl = take(sizeof(int32_t) * RWCTRL_WORDS);
     L->slab = take((size_t)NSLAB_B * (size_t)L->slab_stride);
     L->scan = take(scan_ws((int64_t)L->qcap + 1));
     L->ctrl = take(sizeof(Ctrl));
@@ -1002,6 +1041,10 @@ rwt_status enqueue_setup(rwt_batch* b, hipStream_t s) {
         ra.pat_ptr = b->pat_ptr;
         ra.pat = b->pat;
         ra.pat_cap = b->pat_cap;
+        ra.slot_len = b->slot_len;
+        ra.bump = b->rwctrl + 8;
+        ra.redo = b->rwctrl + 9;
+        ra.gate = nullptr;
         ra.ovf = b->ovf;
         ra.ovf2 = b->ovf2;
         ra.ovf_mark = b->ovf_mark;
@@ -1012,9 +1055,26 @@ rwt_status enqueue_setup(rwt_batch* b, hipStream_t s) {
         ra.slab_cap = b->slab_cap;
         ra.nslab = NSLAB_B;
         ra.cand_mat = b->d_cand_mat;
-        RWT_TRY(batch_rewrite_pass(ra, 1, s));
-        RWT_TRY(scan_exclusive(b->counts_q, b->pat_ptr, b->qcap, b->scan_ws, s));
-        RWT_TRY(batch_rewrite_pass(ra, 2, s));
+        if (b->slot_len > 0) {
+            RWT_TRY(batch_rewrite_pass(ra, 3, s));
+            // the two passes, which run only if the one pass did not fit
+            const unsigned gq = blocks_for((size_t)b->qcap + 1, 256, 4096);
+            ra.gate = b->rwctrl + 9;
+            hipLaunchKernelGGL(k_batch_redo_reset, dim3(gq), dim3(256), 0, s, ra.gate, b->rwctrl,
+                               b->counts_q, b->ovf_mark, b->qcap);
+            RWT_LAUNCHED();
+            RWT_TRY(batch_rewrite_pass(ra, 1, s));
+            RWT_TRY(scan_exclusive(b->counts_q, b->pat_ptr2, b->qcap, b->scan_ws, s));
+            ra.pat_ptr = b->pat_ptr2;
+            RWT_TRY(batch_rewrite_pass(ra, 2, s));
+            hipLaunchKernelGGL(k_copy_gated, dim3(gq), dim3(256), 0, s, ra.gate, b->pat_ptr2,
+                               b->pat_ptr, (int64_t)b->qcap + 1);
+            RWT_LAUNCHED();
+        } else {
+            RWT_TRY(batch_rewrite_pass(ra, 1, s));
+            RWT_TRY(scan_exclusive(b->counts_q, b->pat_ptr, b->qcap, b->scan_ws, s));
+            RWT_TRY(batch_rewrite_pass(ra, 2, s));
+        }
     }
     return RWT_OK;
 }
@@ -1153,6 +1213,7 @@ extern "C" rwt_status rwt_batch_create(const rwt_batch_desc* desc, void* d_ws, s
     b->stats = at<rwt_cand_stats>(d_ws, L.stats);
     b->counts_q = at<int32_t>(d_ws, L.counts);
     b->pat_ptr = at<int32_t>(d_ws, L.patptr);
+    b->pat_ptr2 = at<int32_t>(d_ws, L.patptr2);
     b->pat = at<int32_t>(d_ws, L.pat);
     b->ovf = at<int32_t>(d_ws, L.ovf);
     b->ovf2 = at<int32_t>(d_ws, L.ovf2);
@@ -1166,6 +1227,7 @@ extern "C" rwt_status rwt_batch_create(const rwt_batch_desc* desc, void* d_ws, s
     b->epoch = at<uint32_t>(d_ws, L.epoch);
     b->qcap = L.qcap;
     b->pat_cap = L.pat_cap;
+    b->slot_len = (int64_t)L.pat_cap >= (int64_t)PATTERN_ONE_PASS_MIN * L.qcap ? PATTERN_SLOT : 0;
     // candidates: matrix, bitmap and level array slices
     std::vector<BatchCandDev> hc(desc->num_cand);
     {
@@ -1442,7 +1504,7 @@ extern "C" rwt_status rwt_batch_get_info(const rwt_batch* b, rwt_batch_info* h) 
     h->captured = b->exec != nullptr;
     h->create_ms = b->create_ms;
     h->sweep_cands = b->sweep_cands;
-    h->pad_ = 0;
+    h->pattern_slot = b->slot_len;
     return RWT_OK;
 }
 

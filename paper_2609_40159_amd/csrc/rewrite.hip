@@ -99,7 +99,34 @@ struct RwArgs {
     int32_t pat_cap;
     unsigned char* cand_bad_out;   // batched: candidate rejected when its pattern does not fit
     int32_t cand_index;
+    int32_t* pat_start_out;        // batched, one pass: start of each position's pattern
+    int32_t slot_len;              // batched, one pass: fixed slot per position
+    int32_t* bump;                 // batched, one pass: overflow region in use
+    int32_t* redo;                 // batched, one pass: set when the overflow region is full
+    int32_t qcap;
 };
+
+// One-pass batched patterns: where position q's pattern of len entries
+// goes (its fixed slot, or the overflow region after qcap slots); -1 when
+// the capacity is exceeded, which asks for the two-pass form (lengths, a
+// scan, exact places) after this pass.  Wave-uniform.
+__device__ __forceinline__ int64_t pattern_place(const RwArgs& a, int32_t q, int32_t len) {
+    int64_t ob;
+    if (len <= a.slot_len) {
+        ob = (int64_t)q * a.slot_len;
+    } else {
+        int32_t o = 0;
+        if (lane_id() == 0) o = atomicAdd(a.bump, len);
+        o = __shfl(o, 0);
+        // (a counter past 2^31 - 1 reads negative: full as well)
+        ob = o < 0 ? (int64_t)a.pat_cap : (int64_t)a.qcap * a.slot_len + o;
+    }
+    if (ob + len > a.pat_cap) {
+        if (lane_id() == 0) atomicExch(a.redo, 1);
+        return -1;
+    }
+    return ob;
+}
 
 // Order this wave's earlier buffer writes before its later reads (the
 // buffers may be LDS or global memory).
@@ -122,7 +149,8 @@ __device__ __forceinline__ int lower_bound_lds(const int32_t* a, int len, int32_
 // Rewrite one row with one wave.  Returns false on capacity overflow.
 // QMODE 0: symbolic or numeric rewrite of one matrix; QMODE 1: only the new
 // row length, stored at counts_q[q]; QMODE 2: only the new pattern, stored
-// at pat_out[pat_ptr[q]...].
+// at pat_out[pat_ptr[q]...]; QMODE 3: both, the pattern placed by
+// pattern_place.
 template <typename T, bool NUMERIC, int QMODE = 0>
 __device__ bool rewrite_row(const RwArgs& a, int32_t q, const Bufs& bf) {
     const int lane = lane_id();
@@ -269,6 +297,14 @@ __device__ bool rewrite_row(const RwArgs& a, int32_t q, const Bufs& bf) {
             return true;
         }
         for (int32_t p = lane; p < alen; p += WAVE) a.pat_out[ob + p] = acol[p];
+    } else if (QMODE == 3) {
+        const int64_t ob = pattern_place(a, q, alen);
+        if (ob < 0) return true;
+        for (int32_t p = lane; p < alen; p += WAVE) a.pat_out[ob + p] = acol[p];
+        if (lane == 0) {
+            a.counts_q[q] = alen;
+            a.pat_start_out[q] = (int32_t)ob;
+        }
     } else if (lane == 0) {
         a.counts[r] = alen;
         a.csub[q] = nsub;
@@ -534,9 +570,13 @@ struct BatchRwArgsDev {
     const int32_t* targets;
     int32_t qcap;
     int32_t* counts_q;
-    const int32_t* pat_ptr;
+    int32_t* pat_ptr;
     int32_t* pat;
     int32_t pat_cap;
+    int32_t slot_len;
+    int32_t* bump;
+    int32_t* redo;
+    const int32_t* gate;
     int32_t* ovf;    // positions that overflowed the small LDS tier
     int32_t* ovf2;   // positions that overflowed the large LDS tier
     unsigned char* ovf_mark;
@@ -576,6 +616,11 @@ __device__ inline RwArgs batch_row_args(const BatchRwArgsDev& ba, int32_t q) {
     a.pat_ptr = ba.pat_ptr;
     a.pat_out = ba.pat;
     a.pat_cap = ba.pat_cap;
+    a.pat_start_out = ba.pat_ptr;
+    a.slot_len = ba.slot_len;
+    a.bump = ba.bump;
+    a.redo = ba.redo;
+    a.qcap = ba.qcap;
     return a;
 }
 
@@ -589,6 +634,14 @@ __device__ bool batch_noop_row(const BatchRwArgsDev& ba, const RwArgs& a, int32_
     const int32_t rb = a.rowptr[r], len = a.rowptr[r + 1] - rb;
     if (QMODE == 1) {
         if (lane_id() == 0) ba.counts_q[q] = len;
+    } else if (QMODE == 3) {
+        const int64_t ob = pattern_place(a, q, len);
+        if (ob < 0) return true;
+        for (int32_t p = lane_id(); p < len; p += WAVE) ba.pat[ob + p] = a.colidx[rb + p];
+        if (lane_id() == 0) {
+            ba.counts_q[q] = len;
+            ba.pat_ptr[q] = (int32_t)ob;
+        }
     } else {
         const int32_t ob = ba.pat_ptr[q];
         if (ba.pat_ptr[q + 1] - ob != len || (int64_t)ob + len > ba.pat_cap) {
@@ -606,6 +659,8 @@ __device__ bool batch_noop_row(const BatchRwArgsDev& ba, const RwArgs& a, int32_
 // Same two LDS tiers as the single-matrix rewrite: TIER 1 over every
 // candidate position, TIER 2 over the positions that overflowed it; the
 // pattern pass (QMODE 2) follows the marks of the length pass (QMODE 1).
+// The one-pass form (QMODE 3) marks overflows like the length pass and
+// writes each pattern in the tier where it fits.
 template <int QMODE, int TIER>
 __global__ void __launch_bounds__((TIER == 1 ? RW_WAVES1 : RW_WAVES2) * WAVE)
     k_batch_rw_lds(BatchRwArgsDev ba) {
@@ -613,6 +668,7 @@ __global__ void __launch_bounds__((TIER == 1 ? RW_WAVES1 : RW_WAVES2) * WAVE)
     constexpr int WAVES = TIER == 1 ? RW_WAVES1 : RW_WAVES2;
     constexpr int PER_WAVE = rw_wave_bytes(CAP, 8);
     __shared__ __align__(16) unsigned char s_buf[WAVES * PER_WAVE];
+    if (ba.gate && ld_relaxed(ba.gate) == 0) return;   // the one pass sufficed
     const int w = threadIdx.x / WAVE;
     const Bufs bf = carve_bufs<CAP, 8>(s_buf + w * PER_WAVE);
     const int64_t count = TIER == 1 ? min(ba.cand_ptr[ba.C], ba.qcap) : ba.ctrl[0];
@@ -622,7 +678,7 @@ __global__ void __launch_bounds__((TIER == 1 ? RW_WAVES1 : RW_WAVES2) * WAVE)
         const int32_t q = TIER == 1 ? (int32_t)idx : ba.ovf[idx];
         if (TIER == 1) {
             if (ba.cand_bad[cand_of(ba.cand_ptr, ba.C, q)]) {
-                if (QMODE == 1 && lane_id() == 0) ba.counts_q[q] = 0;
+                if (QMODE != 2 && lane_id() == 0) ba.counts_q[q] = 0;
                 continue;
             }
         }
@@ -630,7 +686,7 @@ __global__ void __launch_bounds__((TIER == 1 ? RW_WAVES1 : RW_WAVES2) * WAVE)
         if (TIER == 1 && batch_noop_row<QMODE>(ba, a, q)) continue;
         if (QMODE == 2 && ba.ovf_mark[q] >= TIER) continue;
         const bool ok = rewrite_row<double, false, QMODE>(a, q, bf);
-        if (!ok && QMODE == 1 && lane_id() == 0) {
+        if (!ok && QMODE != 2 && lane_id() == 0) {
             if (TIER == 1) {
                 const int slot = atomicAdd(&ba.ctrl[0], 1);
                 ba.ovf[slot] = q;
@@ -646,6 +702,7 @@ __global__ void __launch_bounds__((TIER == 1 ? RW_WAVES1 : RW_WAVES2) * WAVE)
 
 template <int QMODE>
 __global__ void __launch_bounds__(WAVE) k_batch_rw_slab(BatchRwArgsDev ba) {
+    if (ba.gate && ld_relaxed(ba.gate) == 0) return;
     const int32_t cnt = ba.ctrl[7];
     const int S = 8;
     for (int32_t s = blockIdx.x; s < cnt; s += gridDim.x) {
@@ -676,6 +733,10 @@ rwt_status batch_rewrite_pass(const BatchRwArgs& h, int qmode, hipStream_t s) {
     ba.pat_ptr = h.pat_ptr;
     ba.pat = h.pat;
     ba.pat_cap = h.pat_cap;
+    ba.slot_len = h.slot_len;
+    ba.bump = h.bump;
+    ba.redo = h.redo;
+    ba.gate = h.gate;
     ba.ovf = h.ovf;
     ba.ovf2 = h.ovf2;
     ba.ovf_mark = h.ovf_mark;
@@ -692,12 +753,18 @@ rwt_status batch_rewrite_pass(const BatchRwArgs& h, int qmode, hipStream_t s) {
         hipLaunchKernelGGL((k_batch_rw_lds<1, 2>), dim3(256), dim3(RW_WAVES2 * WAVE), 0, s, ba);
         RWT_LAUNCHED();
         hipLaunchKernelGGL(k_batch_rw_slab<1>, dim3(h.nslab), dim3(WAVE), 0, s, ba);
-    } else {
+    } else if (qmode == 2) {
         hipLaunchKernelGGL((k_batch_rw_lds<2, 1>), dim3(g), dim3(RW_WAVES1 * WAVE), 0, s, ba);
         RWT_LAUNCHED();
         hipLaunchKernelGGL((k_batch_rw_lds<2, 2>), dim3(256), dim3(RW_WAVES2 * WAVE), 0, s, ba);
         RWT_LAUNCHED();
         hipLaunchKernelGGL(k_batch_rw_slab<2>, dim3(h.nslab), dim3(WAVE), 0, s, ba);
+    } else {
+        hipLaunchKernelGGL((k_batch_rw_lds<3, 1>), dim3(g), dim3(RW_WAVES1 * WAVE), 0, s, ba);
+        RWT_LAUNCHED();
+        hipLaunchKernelGGL((k_batch_rw_lds<3, 2>), dim3(256), dim3(RW_WAVES2 * WAVE), 0, s, ba);
+        RWT_LAUNCHED();
+        hipLaunchKernelGGL(k_batch_rw_slab<3>, dim3(h.nslab), dim3(WAVE), 0, s, ba);
     }
     RWT_LAUNCHED();
     return RWT_OK;

@@ -519,10 +519,11 @@ struct WkLvlArgs {
                                  // (tag << 24) | mark | list offset; after it,
                                  // (tag << 24) | level
     uint32_t tag, mark;
-    const int32_t* pat_ptr;      // new dependency lists, by list position (diagonal last)
+    const int32_t* pat_ptr;      // new dependency lists, by list position: start (diagonal last)
+    const int32_t* pat_len;      // and length
     const int32_t* pat;
     int32_t qb;                  // the candidate's first list position (marks hold offsets from it)
-    int32_t qmax;                // list positions < qmax; pat_ptr holds at least qmax + 1 and 2 entries
+    int32_t qmax;                // list positions < qmax (at least 1 entry in pat_ptr, pat_len)
     int32_t* err;
 };
 
@@ -558,7 +559,7 @@ __device__ void wk_levels(const WkLvlArgs& a, WkLvlLds* L) {
     auto load_q = [&](const P& p) -> Q {
         const bool rw = wk_marked(p.slot, a.tag, a.mark);
         const int32_t q = max(min(a.qb + (rw ? (p.slot & lmask) : 0), a.qmax - 1), 0);
-        const int32_t nb = a.pat_ptr[q], ne = a.pat_ptr[q + 1] - 1;
+        const int32_t nb = a.pat_ptr[q], ne = nb + a.pat_len[q] - 1;
         return rw ? Q{nb, ne} : Q{0, -1};
     };
     int32_t sj[WK_U];   // the chunk's entries, staged in registers

@@ -291,6 +291,66 @@ def test_batch_pattern_capacity_is_reported(orc):
     assert e.value.name == "TOO_LARGE"
 
 
+def test_batch_one_pass_and_two_pass_patterns_agree(orc):
+    """Rewritten-row patterns built in one pass (a 32-entry slot per row,
+    longer rows in the rest of the capacity) and in two passes (lengths, a
+    scan, then patterns) give the same statistics, equal to the oracle's:
+    rows past the slot, past both LDS tiers (targets down to level 0) and
+    rows and no-op rows included.  When the one-pass layout does not fit the
+    capacity but the exact sizes do, the two passes follow within the same
+    launch; a capacity below the exact sizes is reported as TOO_LARGE."""
+    from paper_2609_40159_amd.api import RwtError
+    mats = mixed_matrices()
+    levels = levels_of(orc, mats)
+    # deep targets (down to level 0: long rows) and one level down (short)
+    for cands in (explicit(candidate_sets(orc, mats, 7), levels),
+                  explicit([(m, r, None) for m, r, _ in candidate_sets(orc, mats, 8)], levels)):
+        need = pattern_need(orc, mats, cands, levels)
+        nrows = sum(len(r) for _, r, _ in cands)
+        # room for every row past its slot: the one pass fits; the exact
+        # sizes: one pass then (if it does not fit) the two passes, or the
+        # two passes alone below 48 entries per row
+        one, gm, rhs = make_batch(mats, cands, with_targets=True,
+                                  pattern_cap=max(need + 32 * nrows, 48 * nrows))
+        two, _, _ = make_batch(mats, cands, with_targets=True, pattern_cap=need)
+        assert one.info["pattern_slot"] == 32
+        assert two.info["pattern_slot"] == (32 if need >= 48 * nrows else 0)
+        got = {}
+        for name, bt in (("one", one), ("two", two)):
+            bt.capture()
+            for _ in range(2):
+                bt.launch()
+                torch.cuda.synchronize()
+                got[name] = bt.stats()
+                check_cands(orc, mats, cands, got[name], levels)
+        assert got["one"] == got["two"]
+        check_solves(orc, mats, gm, rhs)
+    # rows of a dense factor rewritten one level down: nearly all longer
+    # than the slot, more than the 16 entries per row left after the slots
+    dense = [("random_dense", synth.random_lower(200, 0.5, 24), 0)]
+    lv = levels_of(orc, dense)
+    deep = explicit([(0, np.arange(100, 200, dtype=np.int32), None)], lv)
+    L = dense[0][1]
+    rw = orc.rewrite(L.n, L.rowptr, L.colidx, L.vals, lv[0], deep[0][1], deep[0][2])
+    lens = np.diff(rw.rowptr)[100:200]
+    assert (lens > 32).mean() > 0.9 and lens.sum() > 48 * 100 - 32 * 100
+    small, _, _ = make_batch(dense, deep, with_targets=True, pattern_cap=48 * 100)
+    assert small.info["pattern_slot"] == 32
+    small.run()
+    with pytest.raises(RwtError) as e:
+        small.stats()
+    assert e.value.name == "TOO_LARGE"
+    exact = int(lens.sum())   # one-pass layout would need 32 * 100 more
+    for cap in (exact, 256 * 100):
+        bt, _, _ = make_batch(dense, deep, with_targets=True, pattern_cap=cap)
+        assert bt.info["pattern_slot"] == 32
+        bt.capture()
+        for _ in range(2):
+            bt.launch()
+            torch.cuda.synchronize()
+            check_cands(orc, dense, deep, bt.stats(), lv)
+
+
 def test_batch_solves_only_and_candidates_only(orc):
     mats = [("lap2d_20", synth.laplacian_2d(20, 20), 4), ("chain", synth.laplacian_2d(300, 1), 1)]
     bt, gm, rhs = make_batch(mats, [])
