@@ -52,9 +52,10 @@ constexpr int BT_LDS = SF_LDS_BUDGET;
 constexpr int NSLAB_B = 64;
 // setup control words: [0] first overflow count, [3] too large, [4]
 // capacity error, [5] rejected row lists, [6] bad list offsets, [7] second
-// overflow count, [8] entries of the pattern overflow region in use, [9]
-// the one-pass patterns did not fit (the two passes follow)
-constexpr int RWCTRL_WORDS = 16;
+// overflow count, [9] the one-pass patterns did not fit (the two passes
+// follow), [16, 16 + PATTERN_BUMPS) entries of each part of the pattern
+// overflow region in use
+constexpr int RWCTRL_WORDS = 16 + PATTERN_BUMPS;
 // one-pass patterns: a fixed slot of this many entries per candidate row
 // (power-law rows rewritten one level down average about 18 entries, a few
 // percent exceed 32), used when the pattern capacity holds at least
@@ -1042,7 +1043,7 @@ rwt_status enqueue_setup(rwt_batch* b, hipStream_t s) {
         ra.pat = b->pat;
         ra.pat_cap = b->pat_cap;
         ra.slot_len = b->slot_len;
-        ra.bump = b->rwctrl + 8;
+        ra.bump = b->rwctrl + 16;
         ra.redo = b->rwctrl + 9;
         ra.gate = nullptr;
         ra.ovf = b->ovf;

@@ -15,6 +15,8 @@ struct BatchRwMat {
 };
 
 // Host description of a batched symbolic pass over candidate rows.
+constexpr int PATTERN_BUMPS = 64;   // one-pass patterns: parts of the overflow region
+
 struct BatchRwArgs {
     const BatchRwMat* mats;     // device
     const int32_t* cand_ptr;    // device, C+1
@@ -28,7 +30,7 @@ struct BatchRwArgs {
     int32_t* pat;               // device, pat_cap
     int32_t pat_cap;
     int32_t slot_len;           // qmode 3: entries of each position's fixed slot
-    int32_t* bump;              // qmode 3: entries taken from the overflow region
+    int32_t* bump;              // qmode 3: PATTERN_BUMPS counters of the overflow region's parts
     int32_t* redo;              // qmode 3 sets it when the overflow region is full
     const int32_t* gate;        // qmodes 1, 2: run only when *gate != 0 (NULL: always)
     int32_t* ovf;               // device, qcap: positions over the small LDS tier

@@ -115,11 +115,17 @@ __device__ __forceinline__ int64_t pattern_place(const RwArgs& a, int32_t q, int
     if (len <= a.slot_len) {
         ob = (int64_t)q * a.slot_len;
     } else {
+        // the overflow region is split in PATTERN_BUMPS parts with a
+        // counter each (position q takes part q mod PATTERN_BUMPS), so that
+        // the atomics spread over as many addresses
+        const int64_t base = (int64_t)a.qcap * a.slot_len;
+        const int64_t part = ((int64_t)a.pat_cap - base) / PATTERN_BUMPS;
+        const int32_t k = q & (PATTERN_BUMPS - 1);
         int32_t o = 0;
-        if (lane_id() == 0) o = atomicAdd(a.bump, len);
+        if (lane_id() == 0) o = atomicAdd(a.bump + k, len);
         o = __shfl(o, 0);
         // (a counter past 2^31 - 1 reads negative: full as well)
-        ob = o < 0 ? (int64_t)a.pat_cap : (int64_t)a.qcap * a.slot_len + o;
+        ob = (o < 0 || o + (int64_t)len > part) ? (int64_t)a.pat_cap : base + k * part + o;
     }
     if (ob + len > a.pat_cap) {
         if (lane_id() == 0) atomicExch(a.redo, 1);
@@ -152,7 +158,7 @@ __device__ __forceinline__ int lower_bound_lds(const int32_t* a, int len, int32_
 // at pat_out[pat_ptr[q]...]; QMODE 3: both, the pattern placed by
 // pattern_place.
 template <typename T, bool NUMERIC, int QMODE = 0>
-__device__ bool rewrite_row(const RwArgs& a, int32_t q, const Bufs& bf) {
+__device__ __forceinline__ bool rewrite_row(const RwArgs& a, int32_t q, const Bufs& bf) {
     const int lane = lane_id();
     const int32_t r = a.set_rows[q];
     const int32_t t = a.targets ? a.targets[q] : a.level[r] - 1;
@@ -601,8 +607,7 @@ __device__ inline int32_t cand_of(const int32_t* cand_ptr, int32_t C, int32_t q)
 __device__ inline RwArgs batch_row_args(const BatchRwArgsDev& ba, int32_t q) {
     const int32_t c = cand_of(ba.cand_ptr, ba.C, q);
     const BatchRwMat& M = ba.mats[ba.cand_mat[c]];
-    RwArgs a;
-    memset(&a, 0, sizeof a);
+    RwArgs a{};
     a.cand_bad_out = ba.cand_bad;
     a.cand_index = c;
     a.n = M.n;

@@ -143,6 +143,8 @@ struct WkLds {
     T xr[WK_W];                     // x at position t in xr[t & (WK_W - 1)]
     T ev[WK_ECAP];                  // the chunk's values; products for dependencies before it
     int32_t ej[WK_ECAP];            // the chunk's dependency rows
+    uint64_t sm[WK_U];              // entry e's bit: forward, its dependency is in the chunk;
+                                    // transposed, before it (where a row's second part starts)
     int32_t rp[WAVE + 1];           // entry starts of the chunk's rows, by local row index
 };
 
@@ -299,56 +301,46 @@ __device__ __forceinline__ T wk_rows(const WkArgs& a, WkLds<T>* L, const int32_t
             split = TRANS ? ce - 1 - nout : cb + nout;
         }
     }
-    if (act && !coop) {
-        // (STAGED) four entries per step, loads issued together; terms added
-        // in walk order (forward ascending, transposed descending entries)
+    if (STAGED && act && !coop) {
+        // where the row's second part starts, from the chunk's entry masks
+        // (forward: outside entries [eb, split), in-chunk [split, oe);
+        // transposed: in-chunk [eb, split], outside (split, oe))
+        int32_t first = oe;
+        for (int32_t w = eb >> 6; (w << 6) < oe; ++w) {
+            uint64_t m = L->sm[w];
+            if ((w << 6) < eb) m &= ~0ull << (eb & 63);
+            if (m != 0) {
+                first = min((w << 6) + (int32_t)__builtin_ctzll(m), oe);
+                break;
+            }
+        }
+        split = TRANS ? first - 1 : first;
+        // the outside terms, four per step with their loads issued together,
+        // added in walk order (forward ascending, transposed descending)
         constexpr int U4 = 4;
         if (!TRANS) {
-            for (int32_t e0 = eb; e0 < oe; e0 += U4) {
-                int32_t r[U4];
+            for (int32_t e0 = eb; e0 < split; e0 += U4) {
                 T v[U4];
 #pragma unroll
-                for (int u = 0; u < U4; ++u) {
-                    const int32_t e = min(e0 + u, oe - 1);
-                    r[u] = J(e);
-                    v[u] = V(e);
-                }
+                for (int u = 0; u < U4; ++u) v[u] = ev[min(e0 + u, split - 1)];
 #pragma unroll
-                for (int u = 0; u < U4; ++u) {
-                    if (e0 + u >= oe) break;
-                    if (outside(r[u])) {
-                        acc += v[u];
-                    } else {
-                        dep |= 1ull << lane_of(r[u]);
-                        split = min(split, e0 + u);
-                    }
-                }
+                for (int u = 0; u < U4; ++u)
+                    if (e0 + u < split) acc += v[u];
             }
         } else {
-            for (int32_t e0 = oe - 1; e0 >= eb; e0 -= U4) {
-                int32_t r[U4];
+            for (int32_t e0 = oe - 1; e0 > split; e0 -= U4) {
                 T v[U4];
 #pragma unroll
-                for (int u = 0; u < U4; ++u) {
-                    const int32_t e = max(e0 - u, eb);
-                    r[u] = J(e);
-                    v[u] = V(e);
-                }
+                for (int u = 0; u < U4; ++u) v[u] = ev[max(e0 - u, split + 1)];
 #pragma unroll
-                for (int u = 0; u < U4; ++u) {
-                    if (e0 - u < eb) break;
-                    if (outside(r[u])) {
-                        acc += v[u];
-                    } else {
-                        dep |= 1ull << lane_of(r[u]);
-                        split = max(split, e0 - u);
-                    }
-                }
+                for (int u = 0; u < U4; ++u)
+                    if (e0 - u > split) acc += v[u];
             }
         }
     }
-    // the first WK_KREG in-chunk terms of each row in registers, in walk
-    // order: value and the lane holding the dependency's x
+    // the in-chunk terms: the first WK_KREG of each row in registers, in
+    // walk order (value and the lane holding the dependency's x), and the
+    // mask of in-chunk dependencies (long rows have it already)
     const int32_t nk = act ? (TRANS ? split - eb + 1 : oe - split) : 0;
     T dv[WK_KREG];
     int32_t dl[WK_KREG];
@@ -360,14 +352,20 @@ __device__ __forceinline__ T wk_rows(const WkArgs& a, WkLds<T>* L, const int32_t
             const int32_t e = TRANS ? split - k : split + k;
             dv[k] = V(e);
             dl[k] = lane_of(J(e)) & (WAVE - 1);
+            dep |= 1ull << dl[k];
         }
     }
+    if (STAGED && act && !coop)
+        for (int32_t k = WK_KREG; k < nk; ++k)
+            dep |= 1ull << (lane_of(ej[TRANS ? split - k : split + k]) & (WAVE - 1));
     const bool kused[WK_KREG] = {__ballot(nk > 0) != 0, __ballot(nk > 1) != 0,
                                  __ballot(nk > 2) != 0, __ballot(nk > 3) != 0};
     // rounds: each solves at least the lowest unsolved position of a valid
     // (lower triangular) system, so at most WAVE of them.  The x of an
     // in-chunk dependency comes from its lane (solved in an earlier round);
-    // terms past the first WK_KREG from the ring.
+    // terms past the first WK_KREG from the ring, which then takes each x
+    // as it is solved (else once, after the rounds).
+    const bool ring_rounds = __ballot(nk > WK_KREG) != 0;
     uint64_t done = __ballot(!act);
     T xi = T(0);
     for (int round = 0; done != ~0ull && round < WAVE; ++round) {
@@ -390,11 +388,12 @@ __device__ __forceinline__ T wk_rows(const WkArgs& a, WkLds<T>* L, const int32_t
                 }
             }
             xi = (b_i - s) / diag;
-            L->xr[(t0 + lane) & (WK_W - 1)] = xi;
+            if (ring_rounds) L->xr[(t0 + lane) & (WK_W - 1)] = xi;
         }
-        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        if (ring_rounds) asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
         done |= __ballot(ready);
     }
+    if (!ring_rounds && act) L->xr[(t0 + lane) & (WK_W - 1)] = xi;
     if (done != ~0ull && lane == 0)   // a dependency on or after its own row
         __hip_atomic_store(a.err, (int32_t)RWT_ERR_INVALID_ARG, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
@@ -452,6 +451,15 @@ __device__ void wk_solve(const WkArgs& a, WkLds<T>* L) {
                 const int32_t t = TRANS ? n - 1 - r : r;
                 xv[u] = (t < t0 && t >= ring_lo) ? L->xr[t & (WK_W - 1)] : T(1);
                 far = far || t < ring_lo;
+            }
+            // slice u's mask to LDS as soon as it is formed (one live mask)
+#pragma unroll
+            for (int u = 0; u < WK_U; ++u) {
+                if (u * WAVE >= E) break;
+                const int32_t e = lane + u * WAVE;
+                const int32_t t = TRANS ? n - 1 - st.j[u] : st.j[u];
+                const uint64_t m = __ballot(e < E && (TRANS ? t < t0 : t >= t0));
+                if (lane == 0) L->sm[u] = m;
             }
 #pragma unroll
             for (int u = 0; u < WK_U; ++u) {
