@@ -516,6 +516,7 @@ struct WkLvlLds {
     int32_t lr[WK_W];               // level at position t in lr[t & (WK_W - 1)]
     int32_t ej[WK_ECAP];            // the chunk's dependency rows
     int32_t el[WK_ECAP];            // their levels when before the chunk
+    uint64_t sm[WK_U];              // entry e's bit: its dependency is in the chunk
     int32_t rp[WAVE + 1];
 };
 
@@ -650,6 +651,13 @@ __device__ void wk_levels(const WkLvlArgs& a, WkLvlLds* L) {
                 const int32_t e = lane + u * WAVE;
                 if (e < E) L->el[e] = lv[u];
             }
+            // slice masks of in-chunk dependencies, one live at a time
+#pragma unroll
+            for (int u = 0; u < WK_U; ++u) {
+                if (u * WAVE >= E) break;
+                const uint64_t m = __ballot(lane + u * WAVE < E && rv[u] >= lo);
+                if (lane == 0) L->sm[u] = m;
+            }
             if (__ballot(far) != 0)
                 for (int32_t e = lane; e < E; e += WAVE) {
                     const int32_t r = ej[e];
@@ -689,12 +697,27 @@ __device__ void wk_levels(const WkLvlArgs& a, WkLvlLds* L) {
             }
         }
         if (!staged) wk_wait_vm();   // as in the row walk: the same loads in flight on both paths
-        if (act && !rw && !coop)
-            for (int32_t e = eb; e < ee; ++e) {
-                const int32_t r = ej[e];
-                if (r < lo) best = max(best, L->el[e]);
-                else dep |= 1ull << (r - lo);
+        if (act && !rw && !coop) {
+            // dependencies before the chunk [eb, split), in it [split, ee)
+            int32_t split = ee;
+            for (int32_t w = eb >> 6; (w << 6) < ee; ++w) {
+                uint64_t m = L->sm[w];
+                if ((w << 6) < eb) m &= ~0ull << (eb & 63);
+                if (m != 0) {
+                    split = min((w << 6) + (int32_t)__builtin_ctzll(m), ee);
+                    break;
+                }
             }
+            constexpr int U4 = 4;
+            for (int32_t e0 = eb; e0 < split; e0 += U4) {
+                int32_t v[U4];
+#pragma unroll
+                for (int u = 0; u < U4; ++u) v[u] = L->el[min(e0 + u, split - 1)];
+#pragma unroll
+                for (int u = 0; u < U4; ++u) best = max(best, v[u]);
+            }
+            for (int32_t e = split; e < ee; ++e) dep |= 1ull << ((ej[e] - lo) & (WAVE - 1));
+        }
         // rounds as in the row walk: the levels of the first WK_KREG in-chunk
         // dependencies from their lanes, any others from the ring
         int32_t dl[WK_KREG];
