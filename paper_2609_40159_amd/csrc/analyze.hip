@@ -241,21 +241,7 @@ __device__ bool pace_barrier(Ctrl* c, uint32_t& gen, int64_t ticks, int32_t* sna
             drain();
             __hip_atomic_exchange(&c->bar_gen, gen + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            int64_t t0 = wall_clock64();
-            uint32_t hb = ld_relaxed(&c->heartbeat);
-            while (ld_relaxed(&c->bar_gen) <= gen) {
-                __builtin_amdgcn_s_sleep(1);
-                if (ld_relaxed(&c->err) != 0) { ok = 0; break; }
-                int64_t now = wall_clock64();
-                uint32_t h2 = ld_relaxed(&c->heartbeat);
-                if (h2 != hb) { hb = h2; t0 = now; }
-                if (now - t0 > ticks) {
-                    __hip_atomic_store(&c->err, (int32_t)RWT_ERR_DEADLOCK, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                    ok = 0;
-                    break;
-                }
-            }
+            ok = wait_generation(c, gen, ticks) ? 1 : 0;
         }
         s_ok = ok;
     }

@@ -159,6 +159,36 @@ struct Ctrl {
     int64_t l0, l1;
 };
 
+// Wait (bounded) until a grid barrier's generation passes gen.  Each poll
+// loads the generation and the error flag together (one memory round
+// trip: a poll that also waited for the clock and the heartbeat in turn
+// took three, which is what a barrier's last waiter pays after the
+// release); the clock and the heartbeat (progress elsewhere restarts the
+// bound) are read every 16th poll.  False when a wait expired somewhere.
+__device__ inline bool wait_generation(Ctrl* c, uint32_t gen, int64_t ticks) {
+    int64_t t0 = wall_clock64();
+    uint32_t hb = ld_relaxed(&c->heartbeat);
+    for (uint32_t polls = 1;; ++polls) {
+        const uint32_t g = ld_relaxed(&c->bar_gen);
+        const int32_t e = ld_relaxed(&c->err);
+        if (g > gen) return true;
+        if (e != 0) return false;
+        if ((polls & 15u) == 0u) {
+            const int64_t now = wall_clock64();
+            const uint32_t h2 = ld_relaxed(&c->heartbeat);
+            if (h2 != hb) {
+                hb = h2;
+                t0 = now;
+            }
+            if (now - t0 > ticks) {
+                __hip_atomic_store(&c->err, (int32_t)RWT_ERR_DEADLOCK, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                return false;
+            }
+        }
+    }
+}
+
 // Readiness carried by the value itself: X is pre-filled with a signalling
 // NaN payload that no arithmetic result can equal (arithmetic quiets NaNs).
 template <typename T> struct Sentinel;

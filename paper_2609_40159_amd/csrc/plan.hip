@@ -164,6 +164,7 @@ struct PlanPtrs {
     int32_t* seg;
     int32_t *bperm, *step_pos, *blk_step;
     int4 *desc_f, *desc_t;
+    int4 *ldesc_f, *ldesc_t;
     void* xtmp;
     void* xtmp2;
     void* vt;
@@ -195,6 +196,8 @@ size_t carve_plan(void* base, const rwt_csr& L, int kmax, PlanPtrs* p) {
     p->blk_step = cv.take<int32_t>(nblocks + 1);
     p->desc_f = cv.take<int4>(n);
     p->desc_t = cv.take<int4>(n);
+    p->ldesc_f = cv.take<int4>(n);
+    p->ldesc_t = cv.take<int4>(n);
     p->xtmp = cv.take<char>((size_t)n * kmax * s);
     p->xtmp2 = cv.take<char>((size_t)n * std::min(kmax, TUNE_COLS) * s);
     p->vt = cv.take<char>((size_t)noff * s);
@@ -253,6 +256,8 @@ SolveArgs make_args(const rwt_plan* p) {
     a.cmap = p->csc.map;
     a.perm = p->perm;
     a.level_ptr = p->level_ptr;
+    a.nlev = p->D;
+    a.ldesc = p->ldesc_f;
     a.seg = p->seg;
     a.nseg = p->nseg;
     a.block_rows = p->R;
@@ -302,6 +307,7 @@ rwt_status run_solve(const rwt_plan* p, bool transposed, Algo algo, const void* 
         return walk_launch(a, p->L.dt, transposed, s);
     }
     RWT_TRY(solve_prepare(a, p->L.dt, s));
+    a.ldesc = transposed ? p->ldesc_t : p->ldesc_f;
     size_t lds = 0;
     int kg = k;
     if (algo == Algo::SyncFree) {
@@ -422,6 +428,8 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
     p->blk_step = pp.blk_step;
     p->desc_f = pp.desc_f;
     p->desc_t = pp.desc_t;
+    p->ldesc_f = pp.ldesc_f;
+    p->ldesc_t = pp.ldesc_t;
     p->xtmp = pp.xtmp;
     p->xtmp2 = pp.xtmp2;
     p->vt = pp.vt;
@@ -450,6 +458,12 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
     if ((st = compute_levels(*L, p->csc, lo, pp.actrl, pp.scratch, s, opts->watchdog_ms)) != RWT_OK)
         return fail(st);
     if ((st = chunk_rounds(L->rowptr, L->colidx, n, pp.span, s)) != RWT_OK) return fail(st);
+    hipLaunchKernelGGL(k_row_desc, dim3(blocks_for((size_t)n, 256, 4096)), dim3(256), 0, s, pp.perm,
+                       L->rowptr, p->csc.ptr, n, pp.ldesc_f, pp.ldesc_t);
+    if (hipError_t e = hipGetLastError(); e != hipSuccess) {
+        set_hip_error(e, "level-order row descriptors");
+        return fail(RWT_ERR_HIP);
+    }
     Ctrl hc;
     unsigned long long span_sum = 0;
     if (hipMemcpyAsync(&span_sum, pp.span, sizeof span_sum, hipMemcpyDeviceToHost, s) != hipSuccess ||

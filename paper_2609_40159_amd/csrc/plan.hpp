@@ -23,6 +23,8 @@ struct rwt_plan {
     int32_t* blk_step = nullptr;
     int4* desc_f = nullptr;   // forward row descriptors in block order
     int4* desc_t = nullptr;   // transposed row descriptors in block order
+    int4* ldesc_f = nullptr;  // forward row descriptors in level order
+    int4* ldesc_t = nullptr;  // transposed row descriptors in level order
     void* xtmp = nullptr;     // n * kmax values
     void* xtmp2 = nullptr;    // n * min(kmax, 64) values (autotuning)
     int32_t kc = 1;           // sync-free right-hand sides per chain

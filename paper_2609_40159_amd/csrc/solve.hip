@@ -9,11 +9,17 @@
 // (bounded) until the sentinel is gone.  No device-scope fences are used.
 //
 // Two schedules:
-//   level-scheduled  (k_solve_level): one level after another.  Wide levels
-//       spread over the whole grid with a pacing barrier after each;
-//       consecutive narrow levels are one segment handled by workgroup 0
-//       alone with workgroup barriers (Section 2.1; the level-set method of
-//       Section 7).
+//   level-scheduled  (k_solve_level): one level after another, each spread
+//       over the whole grid, every wave taking the same share of each level
+//       in turn (Section 2.1; the level-set method of Section 7).  No grid
+//       barrier between levels: a row reads its dependencies with the
+//       sentinel wait, so a wave starts its share of the next level as soon
+//       as its own share of this one is done, and waits only for the values
+//       it needs.  Its first group of rows of each level is loaded ahead
+//       (bounds, descriptors, first entries: three, two and one levels
+//       ahead), so that a level's critical path is the dependencies' values
+//       alone.  Deadlock-free: every workgroup is resident (one per compute
+//       unit) and waits only on earlier levels.
 //   sync-free        (k_solve_sf): blocks of consecutive rows are claimed
 //       in row order from a ticket counter (deadlock-free: a block waits
 //       only on rows of earlier tickets).  Inside a block the rows go level
@@ -116,40 +122,18 @@ __global__ void __launch_bounds__(256) k_prefill(T* X, int64_t ldx, int32_t n, i
     }
 }
 
-// wave-uniform pacing barrier (see analyze.hip): data is never ordered by it
-__device__ bool solve_barrier(Ctrl* c, uint32_t& gen, int64_t ticks) {
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    __shared__ int s_ok;
-    if (threadIdx.x == 0) {
-        const uint32_t nb = gridDim.x;
-        uint32_t prev = fetch_add(&c->bar_count, 1u);
-        int ok = 1;
-        if (prev == nb * (gen + 1) - 1) {
-            __hip_atomic_exchange(&c->bar_gen, gen + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            int64_t t0 = wall_clock64();
-            uint32_t hb = ld_relaxed(&c->heartbeat);
-            while (ld_relaxed(&c->bar_gen) <= gen) {
-                __builtin_amdgcn_s_sleep(1);
-                if (ld_relaxed(&c->err) != 0) { ok = 0; break; }
-                int64_t now = wall_clock64();
-                uint32_t h2 = ld_relaxed(&c->heartbeat);
-                if (h2 != hb) { hb = h2; t0 = now; }
-                if (now - t0 > ticks) {
-                    __hip_atomic_store(&c->err, (int32_t)RWT_ERR_DEADLOCK, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                    ok = 0;
-                    break;
-                }
-            }
-        }
-        s_ok = ok;
-    }
-    __syncthreads();
-    gen += 1;
-    return s_ok != 0;
-}
+// A wave's first group of rows of one level, loaded ahead of the level in
+// three stages: the level's bounds (three levels ahead), the rows'
+// descriptors (two ahead), each lane's first entry and the diagonal (one
+// ahead).  Forward descriptors {row, first entry, last off-diagonal entry,
+// diagonal}; transposed {row, successor-list start, end, diagonal}.
+template <typename T>
+struct LvlAhead {
+    int32_t beg, end;   // level bounds in level order
+    int4 d;             // this lane's row (d.x < 0: no row)
+    int32_t j, m;       // first entry: dependency row; transposed: value position
+    T v, diag;
+};
 
 template <typename T, bool TRANS, int KT>
 __global__ void __launch_bounds__(SV_THREADS) k_solve_level(SolveArgs a) {
@@ -159,42 +143,108 @@ __global__ void __launch_bounds__(SV_THREADS) k_solve_level(SolveArgs a) {
     const int groups_per_wave = WAVE / G;
     const int wave_in_block = threadIdx.x / WAVE;
     const int waves_per_block = blockDim.x / WAVE;
-    uint32_t gen = 0;
-    for (int32_t si = 0; si < a.nseg; ++si) {
-        const int32_t sidx = TRANS ? a.nseg - 1 - si : si;
-        const int32_t lb = a.seg[3 * sidx], le = a.seg[3 * sidx + 1];
-        const bool narrow = a.seg[3 * sidx + 2] != 0;
-        if (narrow) {
-            if (blockIdx.x == 0) {
-                for (int32_t t = 0; t < le - lb; ++t) {
-                    const int32_t l = TRANS ? le - 1 - t : lb + t;
-                    const int32_t beg = a.level_ptr[l], end = a.level_ptr[l + 1];
-                    const int32_t stride = waves_per_block * groups_per_wave;
-                    for (int32_t base = beg + wave_in_block * groups_per_wave; base < end;
-                         base += stride) {
-                        const int32_t q = base + lane / G;
-                        const bool act = q < end;
-                        solve_row<T, TRANS, KT, false>(a, act, act ? a.perm[q] : 0, gl, G, nullptr,
-                                                       0, 0);
-                    }
-                    __builtin_amdgcn_s_waitcnt(0);
-                    __syncthreads();
-                    if (threadIdx.x == 0)
-                        __hip_atomic_fetch_add(&a.ctrl->heartbeat, 1u, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
+    const int32_t gwave = blockIdx.x * waves_per_block + wave_in_block;
+    const int32_t stride = gridDim.x * waves_per_block * groups_per_wave;
+    const int32_t first = gwave * groups_per_wave + lane / G;   // offset of this lane's row in a level
+    const int32_t D = a.nlev;
+    const T* vals = static_cast<const T*>(a.vals);
+    const T* B = static_cast<const T*>(a.B);
+    T* X = static_cast<T*>(a.X);
+    int32_t* err = &a.ctrl->err;
+    // level of the li-th step (levels past the last repeat it; never used)
+    auto lvl = [&](int32_t li) { li = min(li, D - 1); return TRANS ? D - 1 - li : li; };
+    auto stage_bounds = [&](LvlAhead<T>& s, int32_t li) {
+        const int32_t l = lvl(li);
+        s.beg = a.level_ptr[l];
+        s.end = a.level_ptr[l + 1];
+    };
+    auto stage_desc = [&](LvlAhead<T>& s) {
+        const int32_t q = s.beg + first;
+        s.d = q < s.end ? a.ldesc[q] : make_int4(-1, 0, 0, 0);
+    };
+    auto stage_entry = [&](LvlAhead<T>& s) {
+        const bool act = s.d.x >= 0;
+        const int32_t p0 = s.d.y + gl;
+        const bool has = act && p0 < s.d.z;
+        s.j = 0;
+        s.m = 0;
+        s.v = T(0);
+        if (has) {
+            s.j = TRANS ? a.crow[p0] : a.colidx[p0];
+            if (TRANS) s.m = a.cmap[p0];
+            else s.v = vals[p0];
+        }
+        s.diag = act ? vals[s.d.w] : T(1);
+    };
+    // one group of rows: the lane's first entry from the stage, the others
+    // loaded here; the same order of terms as solve_row
+    auto run_group = [&](const LvlAhead<T>& s) {
+        const bool act = s.d.x >= 0;
+        const int32_t i = s.d.x, pb = s.d.y, pe = s.d.z;
+        const bool has = act && pb + gl < pe;
+        const T v0 = TRANS ? (has ? vals[s.m] : T(0)) : s.v;
+        for (int q0 = 0; q0 < a.k; q0 += KT) {
+            T acc[KT];
+#pragma unroll
+            for (int t = 0; t < KT; ++t) acc[t] = T(0);
+            if (has) {
+#pragma unroll
+                for (int t = 0; t < KT; ++t) {
+                    const int q = q0 + t;
+                    if (KT == 1 || q < a.k)
+                        acc[t] += v0 * wait_value(&X[s.j + (int64_t)q * a.ldx], err, a.ticks);
                 }
             }
-        } else {
-            const int32_t beg = a.level_ptr[lb], end = a.level_ptr[lb + 1];
-            const int32_t gwave = blockIdx.x * waves_per_block + wave_in_block;
-            const int32_t stride = gridDim.x * waves_per_block * groups_per_wave;
-            for (int32_t base = beg + gwave * groups_per_wave; base < end; base += stride) {
-                const int32_t q = base + lane / G;
-                const bool act = q < end;
-                solve_row<T, TRANS, KT, false>(a, act, act ? a.perm[q] : 0, gl, G, nullptr, 0, 0);
+            for (int32_t p = pb + gl + G; act && p < pe; p += G) {
+                const int32_t j = TRANS ? a.crow[p] : a.colidx[p];
+                const T v = TRANS ? vals[a.cmap[p]] : vals[p];
+#pragma unroll
+                for (int t = 0; t < KT; ++t) {
+                    const int q = q0 + t;
+                    if (KT == 1 || q < a.k) acc[t] += v * wait_value(&X[j + (int64_t)q * a.ldx], err, a.ticks);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < KT; ++t) acc[t] = group_sum(acc[t], G);
+            if (act && gl == 0) {
+#pragma unroll
+                for (int t = 0; t < KT; ++t) {
+                    const int q = q0 + t;
+                    if (KT == 1 || q < a.k) {
+                        const T xi = (B[i + (int64_t)q * a.ldb] - acc[t]) / s.diag;
+                        if (i != a.hold_row) st_relaxed(&X[i + (int64_t)q * a.ldx], xi);
+                    }
+                }
             }
         }
-        if (!solve_barrier(a.ctrl, gen, a.ticks)) return;
+    };
+    if (D <= 0) return;
+    // the pipeline: s0 = this level, s1 = next (descriptor and entry
+    // loaded), s2 = the one after (descriptor), s3 = bounds only
+    LvlAhead<T> s0, s1, s2, s3;
+    stage_bounds(s0, 0);
+    stage_bounds(s1, 1);
+    stage_bounds(s2, 2);
+    stage_desc(s0);
+    stage_desc(s1);
+    stage_entry(s0);
+    for (int32_t li = 0; li < D; ++li) {
+        // the next levels' loads first: nothing below waits for them
+        stage_bounds(s3, li + 3);
+        stage_desc(s2);
+        stage_entry(s1);
+        run_group(s0);
+        // rows of this level past the wave's first group (levels wider
+        // than the grid's groups): loaded as they come
+        for (int32_t base = s0.beg + gwave * groups_per_wave + stride; base < s0.end;
+             base += stride) {
+            const int32_t q = base + lane / G;
+            const bool act = q < s0.end;
+            solve_row<T, TRANS, KT, false>(a, act, act ? a.perm[q] : 0, gl, G, nullptr, 0, 0);
+        }
+        s0 = s1;
+        s1 = s2;
+        s2 = s3;
     }
 }
 

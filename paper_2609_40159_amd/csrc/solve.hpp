@@ -16,6 +16,8 @@ struct SolveArgs {
     const int32_t* cmap;
     const int32_t* perm;       // level order
     const int32_t* level_ptr;
+    int32_t nlev;              // levels
+    const int4* ldesc;         // level-scheduled: per row in level order {row, first, end, diagonal}
     // level-scheduled: segments of levels (begin, end, narrow flag)
     const int32_t* seg;
     int32_t nseg;
