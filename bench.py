@@ -50,7 +50,7 @@ PEAK_HBM_GBS = 8000.0
 # committed counter measurements)
 SOLVE_SOURCES = ["paper_2609_40159_amd/csrc/solve.hip", "paper_2609_40159_amd/csrc/solve.hpp",
                  "paper_2609_40159_amd/csrc/sf_block.hpp", "paper_2609_40159_amd/csrc/sf_staged.hpp",
-                 "paper_2609_40159_amd/csrc/common.hpp",
+                 "paper_2609_40159_amd/csrc/common.hpp", "paper_2609_40159_amd/csrc/walk.hpp",
                  "paper_2609_40159_amd/csrc/plan.hip"]
 # sources of the batched persistent kernel
 BATCH_SOURCES = SOLVE_SOURCES + ["paper_2609_40159_amd/csrc/batch.hip",
@@ -74,7 +74,7 @@ def parse():
                     help="approximate single-core budget of the 128^3 oracle step")
     ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1),
                     help="oracle worker threads of the batched CPU baseline")
-    ap.add_argument("--cpu-batch-stride", type=int, default=4,
+    ap.add_argument("--cpu-batch-stride", type=int, default=2,
                     help="the batched CPU baseline runs every this many matrices of the batch")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the comparison runs (original DAG, forced schedules, per-matrix batch)")
@@ -89,7 +89,7 @@ def parse():
     ap.add_argument("--env-steps", type=int, default=200, help="timed environment steps")
     ap.add_argument("--ppo-n", type=int, default=20000, help="rows of the PPO training matrix")
     ap.add_argument("--ppo-envs", type=int, default=4, help="environments PPO trains with")
-    ap.add_argument("--ppo-updates", type=int, default=6, help="PPO rollout iterations")
+    ap.add_argument("--ppo-updates", type=int, default=10, help="PPO rollout iterations")
     ap.add_argument("--ppo-seconds", type=float, default=60.0, help="PPO training time limit")
     ap.add_argument("--batch-count", type=int, default=256, help="matrices in the batch")
     ap.add_argument("--gen-workers", type=int, default=min(16, os.cpu_count() or 1),
@@ -393,8 +393,8 @@ def cpu_batched(args, man, gen, cpu_in):
     wall = time.perf_counter() - t0
     return {"value": nb / wall / 1e9, "unit": "GB/s", "cores": args.cpu_threads, "kind": "oracle",
             "cpu_model": cpu_model(), "wall_s": wall,
-            "sample": f"{len(ms)} of the batch's {len(man)} matrices (every "
-                      f"{args.cpu_batch_stride}th): each solved for all its right-hand sides and "
+            "sample": f"{len(ms)} of the batch's {len(man)} matrices (one in every "
+                      f"{args.cpu_batch_stride}): each solved for all its right-hand sides and "
                       f"its 32 candidates rewritten and analysed (levels, costs, CV) by the FP64 "
                       f"oracle, one matrix per thread on {args.cpu_threads} threads; the same "
                       f"algorithmic bytes per matrix as the GPU step (the oracle's rewrite also "
