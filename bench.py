@@ -769,7 +769,7 @@ def run_generator(args, L, Lh, info, dev):
     log("generator timed")
     # scoring: every list as a batch candidate (L' is not formed)
     total = int(ptr[-1])
-    pcap = 16 * max(1, total) + (1 << 20)
+    pcap = 48 * max(1, total) + (1 << 20)   # one-pass patterns
     bt = None
     for _ in range(4):
         try:

@@ -658,7 +658,7 @@ extern "C" rwt_status rwt_plan_get_info(const rwt_plan* p, rwt_plan_info* h) {
                                       ? syncfree_lds_bytes(p->R, p->kc, p->L.dt, p->lanes)
                                       : 0,
                                   p->cus);
-    if (p->fwd == Algo::Walk) h->grid = (p->opts.kmax + 3) / 4;
+    if (p->fwd == Algo::Walk) h->grid = p->opts.kmax;   // one workgroup (two waves) per column
     h->tuned_ms_level = p->tuned_level;
     h->tuned_ms_syncfree = p->tuned_sf;
     h->tuned_ms_walk = p->tuned_walk;

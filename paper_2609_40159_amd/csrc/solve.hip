@@ -296,17 +296,15 @@ __global__ void __launch_bounds__(SV_THREADS) k_solve_sf(SolveArgs a) {
     }
 }
 
-// One wave per right-hand-side column, each walking the rows in order
-// (walk.hpp); waves past the last column return at once (the walk uses no
-// workgroup barrier).
-constexpr int WALK_WAVES = 2;   // two walks per workgroup: 2 x 28 KB of LDS (FP64)
+// One column per workgroup of two waves (walk.hpp, the two-wave walk: one
+// wave stages and sums each chunk's older terms while the other finishes
+// the chunk before).
 template <typename T, bool TRANS>
-__global__ void __launch_bounds__(WAVE * WALK_WAVES) k_solve_walk(SolveArgs a) {
+__global__ void __launch_bounds__(2 * WAVE) k_solve_walk(SolveArgs a) {
     extern __shared__ __align__(16) unsigned char s_raw[];
-    const int w = threadIdx.x / WAVE;
-    const int32_t q = blockIdx.x * WALK_WAVES + w;
+    const int32_t q = blockIdx.x;
     if (q >= a.k) return;
-    WkLds<T>* L = reinterpret_cast<WkLds<T>*>(s_raw + (size_t)w * wk_lds_bytes<T>());
+    WkLds2<T>* L = reinterpret_cast<WkLds2<T>*>(s_raw);
     WkArgs wa;
     wa.n = a.n;
     wa.ptr = TRANS ? a.cptr : a.rowptr;
@@ -317,7 +315,7 @@ __global__ void __launch_bounds__(WAVE * WALK_WAVES) k_solve_walk(SolveArgs a) {
     wa.b = static_cast<const T*>(a.B) + (int64_t)q * a.ldb;
     wa.x = static_cast<T*>(a.X) + (int64_t)q * a.ldx;
     wa.err = &a.ctrl->err;
-    wk_solve<T, TRANS>(wa, L);
+    wk_solve2<T, TRANS>(wa, L);
 }
 
 template <typename T>
@@ -425,17 +423,15 @@ rwt_status solve_prepare(const SolveArgs& a, rwt_dtype dt, hipStream_t s) {
 
 rwt_status walk_launch(const SolveArgs& a, rwt_dtype dt, bool transposed, hipStream_t s) {
     if (a.n == 0 || a.k == 0) return RWT_OK;
-    const int waves = a.k < WALK_WAVES ? a.k : WALK_WAVES;
-    const unsigned grid = (unsigned)((a.k + WALK_WAVES - 1) / WALK_WAVES);
-    const dim3 blk(WAVE * waves);
+    const dim3 grid((unsigned)a.k), blk(2 * WAVE);
     if (dt == RWT_F64) {
-        const size_t lds = (size_t)waves * wk_lds_bytes<double>();
-        if (transposed) hipLaunchKernelGGL((k_solve_walk<double, true>), dim3(grid), blk, lds, s, a);
-        else hipLaunchKernelGGL((k_solve_walk<double, false>), dim3(grid), blk, lds, s, a);
+        const size_t lds = (size_t)wk2_lds_bytes<double>();
+        if (transposed) hipLaunchKernelGGL((k_solve_walk<double, true>), grid, blk, lds, s, a);
+        else hipLaunchKernelGGL((k_solve_walk<double, false>), grid, blk, lds, s, a);
     } else {
-        const size_t lds = (size_t)waves * wk_lds_bytes<float>();
-        if (transposed) hipLaunchKernelGGL((k_solve_walk<float, true>), dim3(grid), blk, lds, s, a);
-        else hipLaunchKernelGGL((k_solve_walk<float, false>), dim3(grid), blk, lds, s, a);
+        const size_t lds = (size_t)wk2_lds_bytes<float>();
+        if (transposed) hipLaunchKernelGGL((k_solve_walk<float, true>), grid, blk, lds, s, a);
+        else hipLaunchKernelGGL((k_solve_walk<float, false>), grid, blk, lds, s, a);
     }
     RWT_LAUNCHED();
     return RWT_OK;

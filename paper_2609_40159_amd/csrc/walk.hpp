@@ -229,6 +229,90 @@ __device__ __forceinline__ void wk_stage_entries(const WkArgs& a, const WkPtr& p
     wk_fetch<T>(static_cast<const T*>(a.vals) + base, cnt, a.ptr, st.v);
 }
 
+constexpr int WK_LONG = 24;
+constexpr int WK_KREG = 4;   // in-chunk dependencies a lane keeps in registers for the rounds
+
+// The in-chunk part of a chunk's rows (both walks of values): each row's
+// sum of the terms before the chunk is acc, its in-chunk entries are
+// forward [split, oe), transposed [eb, split]; dep holds the lanes of its
+// in-chunk dependencies (need_dep: only from the first WK_KREG entries,
+// the rest are added here).  Returns the row's x, also left in the ring.
+template <typename T, bool TRANS, bool STAGED>
+__device__ __forceinline__ T wk_rounds(const WkArgs& a, T* xr, const int32_t* ej, const T* ev,
+                                       int32_t base, int32_t lo, int32_t cnt, int32_t t0,
+                                       int32_t eb, int32_t oe, int32_t split, T acc, uint64_t dep,
+                                       bool need_dep, T b_i, T diag) {
+    const int lane = lane_id();
+    const int32_t n = a.n;
+    const int32_t hi = lo + cnt - 1;
+    const T* vals = static_cast<const T*>(a.vals);
+    auto pos_of = [&](int32_t r) { return TRANS ? n - 1 - r : r; };
+    auto lane_of = [&](int32_t r) { return TRANS ? hi - r : r - lo; };
+    auto J = [&](int32_t e) -> int32_t { return STAGED ? ej[e] : a.idx[base + e]; };
+    auto V = [&](int32_t e) -> T { return STAGED ? ev[e] : vals[base + e]; };
+    const bool act = lane < cnt;
+    // the in-chunk terms: the first WK_KREG of each row in registers, in
+    // walk order (value and the lane holding the dependency's x), and the
+    // mask of in-chunk dependencies (long rows have it already)
+    const int32_t nk = act ? (TRANS ? split - eb + 1 : oe - split) : 0;
+    T dv[WK_KREG];
+    int32_t dl[WK_KREG];
+#pragma unroll
+    for (int k = 0; k < WK_KREG; ++k) {
+        dv[k] = T(0);
+        dl[k] = lane;
+        if (k < nk) {
+            const int32_t e = TRANS ? split - k : split + k;
+            dv[k] = V(e);
+            dl[k] = lane_of(J(e)) & (WAVE - 1);
+            dep |= 1ull << dl[k];
+        }
+    }
+    if (need_dep)
+        for (int32_t k = WK_KREG; k < nk; ++k)
+            dep |= 1ull << (lane_of(ej[TRANS ? split - k : split + k]) & (WAVE - 1));
+    const bool kused[WK_KREG] = {__ballot(nk > 0) != 0, __ballot(nk > 1) != 0,
+                                 __ballot(nk > 2) != 0, __ballot(nk > 3) != 0};
+    // rounds: each solves at least the lowest unsolved position of a valid
+    // (lower triangular) system, so at most WAVE of them.  The x of an
+    // in-chunk dependency comes from its lane (solved in an earlier round);
+    // terms past the first WK_KREG from the ring, which then takes each x
+    // as it is solved (else once, after the rounds).
+    const bool ring_rounds = __ballot(nk > WK_KREG) != 0;
+    uint64_t done = __ballot(!act);
+    T xi = T(0);
+    for (int round = 0; done != ~0ull && round < WAVE; ++round) {
+        const bool ready = act && !((done >> lane) & 1ull) && (dep & ~done) == 0;
+        T xk[WK_KREG];
+#pragma unroll
+        for (int k = 0; k < WK_KREG; ++k) xk[k] = kused[k] ? __shfl(xi, dl[k]) : T(0);
+        if (ready) {
+            T s = acc;
+#pragma unroll
+            for (int k = 0; k < WK_KREG; ++k)
+                if (k < nk) s += dv[k] * xk[k];
+            if (nk > WK_KREG) {
+                if (!TRANS) {
+                    for (int32_t e = split + WK_KREG; e < oe; ++e)
+                        s += V(e) * xr[pos_of(J(e)) & (WK_W - 1)];
+                } else {
+                    for (int32_t e = split - WK_KREG; e >= eb; --e)
+                        s += V(e) * xr[pos_of(J(e)) & (WK_W - 1)];
+                }
+            }
+            xi = (b_i - s) / diag;
+            if (ring_rounds) xr[(t0 + lane) & (WK_W - 1)] = xi;
+        }
+        if (ring_rounds) asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        done |= __ballot(ready);
+    }
+    if (!ring_rounds && act) xr[(t0 + lane) & (WK_W - 1)] = xi;
+    if (done != ~0ull && lane == 0)   // a dependency on or after its own row
+        __hip_atomic_store(a.err, (int32_t)RWT_ERR_INVALID_ARG, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    return xi;
+}
+
 // One chunk's rows once the products of the dependencies before the chunk
 // are known: each row's sum, then the rounds over the in-chunk
 // dependencies.  STAGED: entries from LDS, products already formed; else
@@ -236,13 +320,10 @@ __device__ __forceinline__ void wk_stage_entries(const WkArgs& a, const WkPtr& p
 // dependencies, and every row of an unstaged chunk, is summed by the whole
 // wave (64 entries a step, then a fixed-order reduction); the others by
 // their own lane, in walk order.
-constexpr int WK_LONG = 24;
-constexpr int WK_KREG = 4;   // in-chunk dependencies a lane keeps in registers for the rounds
-
 template <typename T, bool TRANS, bool STAGED>
-__device__ __forceinline__ T wk_rows(const WkArgs& a, WkLds<T>* L, const int32_t* ej, const T* ev,
-                                     int32_t base, int32_t lo, int32_t cnt, int32_t t0, T b_i,
-                                     T diag) {
+__device__ __forceinline__ T wk_rows(const WkArgs& a, T* xr, const int32_t* rp, const uint64_t* sm,
+                                     const int32_t* ej, const T* ev, int32_t base, int32_t lo,
+                                     int32_t cnt, int32_t t0, T b_i, T diag) {
     const int lane = lane_id();
     const int32_t n = a.n;
     const int32_t hi = lo + cnt - 1;
@@ -257,15 +338,15 @@ __device__ __forceinline__ T wk_rows(const WkArgs& a, WkLds<T>* L, const int32_t
     auto term = [&](int32_t e, int32_t r) -> T {
         if (STAGED) return ev[e];
         const int32_t t = pos_of(r);
-        const T x = t >= t0 + WAVE - WK_W ? L->xr[t & (WK_W - 1)] : ld_relaxed(&X[r]);
+        const T x = t >= t0 + WAVE - WK_W ? xr[t & (WK_W - 1)] : ld_relaxed(&X[r]);
         return vals[base + e] * x;
     };
     const bool act = lane < cnt;
     const int32_t li = TRANS ? cnt - 1 - lane : lane;
     int32_t eb = 0, ee = 0;
     if (act) {
-        eb = L->rp[li];
-        ee = L->rp[li + 1];
+        eb = rp[li];
+        ee = rp[li + 1];
     }
     // off-diagonal entries [eb, oe); forward rows end with their diagonal
     const int32_t oe = TRANS ? ee : ee - 1;
@@ -307,7 +388,7 @@ __device__ __forceinline__ T wk_rows(const WkArgs& a, WkLds<T>* L, const int32_t
         // transposed: in-chunk [eb, split], outside (split, oe))
         int32_t first = oe;
         for (int32_t w = eb >> 6; (w << 6) < oe; ++w) {
-            uint64_t m = L->sm[w];
+            uint64_t m = sm[w];
             if ((w << 6) < eb) m &= ~0ull << (eb & 63);
             if (m != 0) {
                 first = min((w << 6) + (int32_t)__builtin_ctzll(m), oe);
@@ -338,66 +419,8 @@ __device__ __forceinline__ T wk_rows(const WkArgs& a, WkLds<T>* L, const int32_t
             }
         }
     }
-    // the in-chunk terms: the first WK_KREG of each row in registers, in
-    // walk order (value and the lane holding the dependency's x), and the
-    // mask of in-chunk dependencies (long rows have it already)
-    const int32_t nk = act ? (TRANS ? split - eb + 1 : oe - split) : 0;
-    T dv[WK_KREG];
-    int32_t dl[WK_KREG];
-#pragma unroll
-    for (int k = 0; k < WK_KREG; ++k) {
-        dv[k] = T(0);
-        dl[k] = lane;
-        if (k < nk) {
-            const int32_t e = TRANS ? split - k : split + k;
-            dv[k] = V(e);
-            dl[k] = lane_of(J(e)) & (WAVE - 1);
-            dep |= 1ull << dl[k];
-        }
-    }
-    if (STAGED && act && !coop)
-        for (int32_t k = WK_KREG; k < nk; ++k)
-            dep |= 1ull << (lane_of(ej[TRANS ? split - k : split + k]) & (WAVE - 1));
-    const bool kused[WK_KREG] = {__ballot(nk > 0) != 0, __ballot(nk > 1) != 0,
-                                 __ballot(nk > 2) != 0, __ballot(nk > 3) != 0};
-    // rounds: each solves at least the lowest unsolved position of a valid
-    // (lower triangular) system, so at most WAVE of them.  The x of an
-    // in-chunk dependency comes from its lane (solved in an earlier round);
-    // terms past the first WK_KREG from the ring, which then takes each x
-    // as it is solved (else once, after the rounds).
-    const bool ring_rounds = __ballot(nk > WK_KREG) != 0;
-    uint64_t done = __ballot(!act);
-    T xi = T(0);
-    for (int round = 0; done != ~0ull && round < WAVE; ++round) {
-        const bool ready = act && !((done >> lane) & 1ull) && (dep & ~done) == 0;
-        T xk[WK_KREG];
-#pragma unroll
-        for (int k = 0; k < WK_KREG; ++k) xk[k] = kused[k] ? __shfl(xi, dl[k]) : T(0);
-        if (ready) {
-            T s = acc;
-#pragma unroll
-            for (int k = 0; k < WK_KREG; ++k)
-                if (k < nk) s += dv[k] * xk[k];
-            if (nk > WK_KREG) {
-                if (!TRANS) {
-                    for (int32_t e = split + WK_KREG; e < oe; ++e)
-                        s += V(e) * L->xr[pos_of(J(e)) & (WK_W - 1)];
-                } else {
-                    for (int32_t e = split - WK_KREG; e >= eb; --e)
-                        s += V(e) * L->xr[pos_of(J(e)) & (WK_W - 1)];
-                }
-            }
-            xi = (b_i - s) / diag;
-            if (ring_rounds) L->xr[(t0 + lane) & (WK_W - 1)] = xi;
-        }
-        if (ring_rounds) asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-        done |= __ballot(ready);
-    }
-    if (!ring_rounds && act) L->xr[(t0 + lane) & (WK_W - 1)] = xi;
-    if (done != ~0ull && lane == 0)   // a dependency on or after its own row
-        __hip_atomic_store(a.err, (int32_t)RWT_ERR_INVALID_ARG, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    return xi;
+    return wk_rounds<T, TRANS, STAGED>(a, xr, ej, ev, base, lo, cnt, t0, eb, oe, split, acc, dep,
+                                       STAGED && act && !coop, b_i, diag);
 }
 
 // Solve one column: rows in walk order, chunk by chunk.  Every lane of the
@@ -489,9 +512,11 @@ __device__ void wk_solve(const WkArgs& a, WkLds<T>* L) {
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
         T xi;
         if (staged) {
-            xi = wk_rows<T, TRANS, true>(a, L, ej, ev, base, lo, cnt, t0, r_cur.b, r_cur.diag);
+            xi = wk_rows<T, TRANS, true>(a, L->xr, L->rp, L->sm, ej, ev, base, lo, cnt, t0, r_cur.b,
+                                         r_cur.diag);
         } else {
-            xi = wk_rows<T, TRANS, false>(a, L, ej, ev, base, lo, cnt, t0, r_cur.b, r_cur.diag);
+            xi = wk_rows<T, TRANS, false>(a, L->xr, L->rp, L->sm, ej, ev, base, lo, cnt, t0, r_cur.b,
+                                          r_cur.diag);
             wk_wait_vm();   // its own loads, so that both paths end with the same loads in flight
         }
         // rows contiguous: one coalesced store (issued with the next loads)
@@ -501,6 +526,280 @@ __device__ void wk_solve(const WkArgs& a, WkLds<T>* L) {
         p_nxt = p_n2;
     }
     if (at_prev >= 0) X[at_prev] = x_prev;
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
+// ---------------------------------------------------------------------------
+// The walk of one column split over two waves of a workgroup, pipelined by
+// chunk: while wave 1 (the solver) finishes chunk c -- the terms of its
+// rows' dependencies in chunk c - 1, then the rounds -- wave 0 (the stager)
+// prepares chunk c + 1: stages its entries in LDS, forms the products of
+// every dependency older than chunk c and sums them per row.  One workgroup
+// barrier per chunk.  A row's entries fall in three runs by the position of
+// their dependency: older than the previous chunk, in the previous chunk
+// ("late"), in the chunk; forward they come in that order along the row,
+// transposed in the reverse one, and each run is added in walk order with
+// every product rounded on its own, so the arithmetic is the one-wave
+// walk's, bit for bit (a long row's terms outside the chunk are summed by
+// the solver in the one-wave walk's single wave-wide pass).  A chunk with
+// more entries than the stage is solved by the solver alone from HBM.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct WkLds2 {
+    T xr[WK_W];                     // x at position t in xr[t & (WK_W - 1)]
+    T ev[2][WK_ECAP];               // per chunk parity: values; products of older dependencies
+    int32_t ej[2][WK_ECAP];
+    uint64_t m1[2][WK_U];           // forward: dependency late or in the chunk; transposed: before the chunk
+    uint64_t m2[2][WK_U];           // forward: in the chunk; transposed: older than the previous chunk
+    int32_t rp[2][WAVE + 1];
+    T acc[2][WAVE];                 // per lane: its row's sum of older terms (rows up to WK_LONG)
+    int32_t b1[2][WAVE], b2[2][WAVE];   // per lane: first entries of the second and third runs
+    int32_t base[2], E[2];
+};
+
+template <typename T>
+__host__ __device__ constexpr int wk2_lds_bytes() {
+    return (int)((sizeof(WkLds2<T>) + 15) & ~size_t(15));
+}
+
+// first set bit of the per-64-entry masks m at or after entry eb, before oe (else oe)
+__device__ __forceinline__ int32_t wk_first_set(const uint64_t* m, int32_t eb, int32_t oe) {
+    for (int32_t w = eb >> 6; (w << 6) < oe; ++w) {
+        uint64_t v = m[w];
+        if ((w << 6) < eb) v &= ~0ull << (eb & 63);
+        if (v != 0) return min((w << 6) + (int32_t)__builtin_ctzll(v), oe);
+    }
+    return oe;
+}
+
+template <typename T, bool TRANS>
+__device__ void wk_solve2(const WkArgs& a, WkLds2<T>* L) {
+    const int lane = lane_id();
+    const bool stager = threadIdx.x < WAVE;
+    const int32_t n = a.n;
+    if (n <= 0) return;
+    const int32_t nchunks = (n + WAVE - 1) / WAVE;
+    T* X = static_cast<T*>(a.x);
+    auto pos_of = [&](int32_t r) { return TRANS ? n - 1 - r : r; };
+    // stager state: pointers two chunks ahead, entries one ahead
+    WkPtr p_cur, p_nxt;
+    WkStage<T> st;
+    // solver state: right-hand sides one chunk ahead (transposed: their
+    // diagonals need the pointers, loaded two chunks ahead)
+    WkRhs<T> r_nxt;
+    WkPtr q_nxt;
+    if (stager) {
+        p_cur = wk_load_ptr<TRANS>(a, 0, nchunks);
+        p_nxt = wk_load_ptr<TRANS>(a, 1, nchunks);
+        wk_stage_entries<T>(a, p_cur, st);
+    } else {
+        const WkPtr q0 = wk_load_ptr<TRANS>(a, 0, nchunks);
+        q_nxt = wk_load_ptr<TRANS>(a, 1, nchunks);
+        r_nxt = wk_load_rhs<T, TRANS>(a, 0, nchunks, q0);
+    }
+    // the stager prepares chunk c (older dependencies: before chunk c - 1)
+    auto prepare = [&](int32_t c) {
+        const int b = c & 1;
+        const WkChunk ch = wk_chunk<TRANS>(n, c);
+        const int32_t lo = ch.lo, cnt = ch.cnt, hi = lo + cnt - 1;
+        const int32_t t0 = c * WAVE;
+        const int32_t tl = t0 - WAVE;   // first position of the previous chunk
+        const int32_t base = wk_lane_val(p_cur.rpv, 0);
+        const int32_t E = p_cur.endv - base;
+        L->rp[b][lane] = p_cur.rpv - base;
+        if (lane == 0) {
+            L->rp[b][cnt] = E;
+            L->base[b] = base;
+            L->E[b] = E;
+        }
+        const bool staged = E <= WK_ECAP;
+        const int32_t ring_lo = t0 + WAVE - WK_W;
+        if (!staged) {
+            wk_wait_vm();
+        } else {
+            bool far = false;
+            T xv[WK_U];
+#pragma unroll
+            for (int u = 0; u < WK_U; ++u) {
+                const int32_t e = lane + u * WAVE;
+                const int32_t r = e < E ? st.j[u] : (TRANS ? hi : lo);
+                const int32_t t = pos_of(r);
+                xv[u] = (t < tl && t >= ring_lo) ? L->xr[t & (WK_W - 1)] : T(1);
+                far = far || t < ring_lo;
+            }
+#pragma unroll
+            for (int u = 0; u < WK_U; ++u) {
+                const int32_t e = lane + u * WAVE;
+                if (e < E) {
+                    L->ej[b][e] = st.j[u];
+                    L->ev[b][e] = st.v[u] * xv[u];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < WK_U; ++u) {
+                if (u * WAVE >= E) break;
+                const int32_t e = lane + u * WAVE;
+                const int32_t t = pos_of(st.j[u]);
+                const uint64_t m1 = __ballot(e < E && (TRANS ? t < t0 : t >= tl));
+                const uint64_t m2 = __ballot(e < E && (TRANS ? t < tl : t >= t0));
+                if (lane == 0) {
+                    L->m1[b][u] = m1;
+                    L->m2[b][u] = m2;
+                }
+            }
+            if (__ballot(far) != 0) {
+                for (int32_t e = lane; e < E; e += WAVE) {
+                    const int32_t r = L->ej[b][e];
+                    if (pos_of(r) < ring_lo) L->ev[b][e] = L->ev[b][e] * ld_relaxed(&X[r]);
+                }
+            }
+        }
+        // the next chunks' loads; nothing below waits for them (the
+        // pointers rotate at the end, after the sums)
+        const WkPtr p_n2 = wk_load_ptr<TRANS>(a, c + 2, nchunks);
+        wk_stage_entries<T>(a, p_nxt, st);
+        if (!staged) {
+            p_cur = p_nxt;
+            p_nxt = p_n2;
+            return;
+        }
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        // per row: the runs, the sum of the older terms, long rows' masks
+        const bool act = lane < cnt;
+        const int32_t li = TRANS ? cnt - 1 - lane : lane;
+        int32_t eb = 0, ee = 0;
+        if (act) {
+            eb = L->rp[b][li];
+            ee = L->rp[b][li + 1];
+        }
+        const int32_t oe = TRANS ? ee : ee - 1;
+        const int32_t* ej = L->ej[b];
+        const T* ev = L->ev[b];
+        int32_t b1 = act ? wk_first_set(L->m1[b], eb, oe) : 0;
+        int32_t b2 = act ? wk_first_set(L->m2[b], eb, oe) : 0;
+        // older run: forward [eb, b1), transposed [b2, oe)
+        const int32_t ob = TRANS ? b2 : eb, oe2 = TRANS ? oe : b1;
+        T acc = T(0);
+        // long rows are summed by the solver in one pass (the one-wave
+        // walk's order); the stager only marks their runs
+        const bool coop = act && oe - eb > WK_LONG;
+        if (act && !coop) {
+            constexpr int U4 = 4;
+            if (!TRANS) {
+                for (int32_t e0 = ob; e0 < oe2; e0 += U4) {
+                    T v[U4];
+#pragma unroll
+                    for (int u = 0; u < U4; ++u) v[u] = ev[min(e0 + u, oe2 - 1)];
+#pragma unroll
+                    for (int u = 0; u < U4; ++u)
+                        if (e0 + u < oe2) acc += v[u];
+                }
+            } else {
+                for (int32_t e0 = oe2 - 1; e0 >= ob; e0 -= U4) {
+                    T v[U4];
+#pragma unroll
+                    for (int u = 0; u < U4; ++u) v[u] = ev[max(e0 - u, ob)];
+#pragma unroll
+                    for (int u = 0; u < U4; ++u)
+                        if (e0 - u >= ob) acc += v[u];
+                }
+            }
+        }
+        L->acc[b][lane] = acc;
+        L->b1[b][lane] = b1;
+        L->b2[b][lane] = b2;
+        p_cur = p_nxt;
+        p_nxt = p_n2;
+    };
+    if (stager) prepare(0);
+    __syncthreads();
+    T x_prev = T(0);
+    int32_t at_prev = -1;
+    for (int32_t c = 0; c < nchunks; ++c) {
+        if (stager) {
+            if (c + 1 < nchunks) prepare(c + 1);
+        } else {
+            // the solver finishes chunk c
+            const int b = c & 1;
+            const WkChunk ch = wk_chunk<TRANS>(n, c);
+            const int32_t lo = ch.lo, cnt = ch.cnt, hi = lo + cnt - 1;
+            const int32_t t0 = c * WAVE;
+            const WkRhs<T> r_cur = r_nxt;
+            const int32_t base = L->base[b], E = L->E[b];
+            {   // right-hand sides of the next chunk
+                const WkPtr q_n2 = wk_load_ptr<TRANS>(a, c + 2, nchunks);
+                r_nxt = wk_load_rhs<T, TRANS>(a, c + 1, nchunks, q_nxt);
+                q_nxt = q_n2;
+            }
+            if (at_prev >= 0) X[at_prev] = x_prev;
+            T xi;
+            if (E > WK_ECAP) {
+                xi = wk_rows<T, TRANS, false>(a, L->xr, L->rp[b], nullptr, nullptr, nullptr, base, lo,
+                                              cnt, t0, r_cur.b, r_cur.diag);
+                wk_wait_vm();
+            } else {
+                const bool act = lane < cnt;
+                const int32_t li = TRANS ? cnt - 1 - lane : lane;
+                int32_t eb = 0, ee = 0;
+                if (act) {
+                    eb = L->rp[b][li];
+                    ee = L->rp[b][li + 1];
+                }
+                const int32_t oe = TRANS ? ee : ee - 1;
+                const int32_t* ej = L->ej[b];
+                const T* ev = L->ev[b];
+                T diag = r_cur.diag;
+                if (act && !TRANS) diag = ev[ee - 1];
+                T acc = L->acc[b][lane];
+                const int32_t b1 = L->b1[b][lane], b2 = L->b2[b][lane];
+                uint64_t dep = 0;
+                // late run: forward [b1, b2), transposed [b1, b2) added from
+                // its end; each product rounded on its own, as the one-wave
+                // walk forms it in its flat pass.  Long rows: every term
+                // outside the chunk in one wave-wide pass from the row's
+                // start, as the one-wave walk sums them.
+                const int32_t lb = b1, le = b2;
+                const int32_t tl = t0 - WAVE;
+                auto lane_of = [&](int32_t r) { return TRANS ? hi - r : r - lo; };
+                const bool coop = act && oe - eb > WK_LONG;
+                for (uint64_t m = __ballot(coop); m != 0; m &= m - 1) {
+                    const int o = __builtin_ctzll(m);
+                    const int32_t cb = wk_lane_val(eb, o), ce = wk_lane_val(oe, o);
+                    T part = T(0);
+                    uint64_t dm = 0;
+                    for (int32_t e = cb + lane; e < ce; e += WAVE) {
+                        const int32_t r = ej[e];
+                        const int32_t t = pos_of(r);
+                        if (t < t0) part += t >= tl ? mul_rn(ev[e], L->xr[t & (WK_W - 1)]) : ev[e];
+                        else dm |= 1ull << (lane_of(r) & (WAVE - 1));
+                    }
+                    part = wk_sum(part);
+                    dm = wk_or(dm);
+                    if (lane == o) {
+                        acc = part;
+                        dep = dm;
+                    }
+                }
+                if (act && !coop) {
+                    if (!TRANS) {
+                        for (int32_t e = lb; e < le; ++e)
+                            acc += mul_rn(ev[e], L->xr[pos_of(ej[e]) & (WK_W - 1)]);
+                    } else {
+                        for (int32_t e = le - 1; e >= lb; --e)
+                            acc += mul_rn(ev[e], L->xr[pos_of(ej[e]) & (WK_W - 1)]);
+                    }
+                }
+                // in-chunk run: forward [b2, oe), transposed [eb, b1)
+                const int32_t split = TRANS ? b1 - 1 : b2;
+                xi = wk_rounds<T, TRANS, true>(a, L->xr, ej, ev, base, lo, cnt, t0, eb, oe, split,
+                                               acc, dep, act && !coop, r_cur.b, diag);
+            }
+            x_prev = xi;
+            at_prev = lane < cnt ? (TRANS ? hi - lane : lo + lane) : -1;
+        }
+        __syncthreads();
+    }
+    if (!stager && at_prev >= 0) X[at_prev] = x_prev;
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
