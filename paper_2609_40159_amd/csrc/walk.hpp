@@ -575,7 +575,10 @@ __device__ __forceinline__ int32_t wk_first_set(const uint64_t* m, int32_t eb, i
 template <typename T, bool TRANS>
 __device__ void wk_solve2(const WkArgs& a, WkLds2<T>* L) {
     const int lane = lane_id();
-    const bool stager = threadIdx.x < WAVE;
+    // wave 0 stages, wave 1 solves; further waves of the workgroup only
+    // take part in the barriers
+    const int wv = threadIdx.x / WAVE;
+    const bool stager = wv == 0, solver = wv == 1;
     const int32_t n = a.n;
     if (n <= 0) return;
     const int32_t nchunks = (n + WAVE - 1) / WAVE;
@@ -592,7 +595,7 @@ __device__ void wk_solve2(const WkArgs& a, WkLds2<T>* L) {
         p_cur = wk_load_ptr<TRANS>(a, 0, nchunks);
         p_nxt = wk_load_ptr<TRANS>(a, 1, nchunks);
         wk_stage_entries<T>(a, p_cur, st);
-    } else {
+    } else if (solver) {
         const WkPtr q0 = wk_load_ptr<TRANS>(a, 0, nchunks);
         q_nxt = wk_load_ptr<TRANS>(a, 1, nchunks);
         r_nxt = wk_load_rhs<T, TRANS>(a, 0, nchunks, q0);
@@ -718,7 +721,7 @@ __device__ void wk_solve2(const WkArgs& a, WkLds2<T>* L) {
     for (int32_t c = 0; c < nchunks; ++c) {
         if (stager) {
             if (c + 1 < nchunks) prepare(c + 1);
-        } else {
+        } else if (solver) {
             // the solver finishes chunk c
             const int b = c & 1;
             const WkChunk ch = wk_chunk<TRANS>(n, c);
@@ -799,7 +802,7 @@ __device__ void wk_solve2(const WkArgs& a, WkLds2<T>* L) {
         }
         __syncthreads();
     }
-    if (!stager && at_prev >= 0) X[at_prev] = x_prev;
+    if (solver && at_prev >= 0) X[at_prev] = x_prev;
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
 
