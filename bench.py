@@ -20,9 +20,9 @@ Beside it (not part of value), each with its bandwidth and latency floors:
             level-scheduled vs sync-free;
   fp32      the same factor in FP32, forward + transposed, rewritten vs
             original;
-  config3   power-law n = 1M, 64 right-hand sides, 0.8% rewritten: forward
+  powerlaw1m power-law n = 1M, 64 right-hand sides, 0.8% rewritten: forward
             and adjoint, rewritten vs original;
-  config5   torch.autograd over the solve, 64^3 factor and power-law 262k,
+  autograd  torch.autograd over the solve, 64^3 factor and power-law 262k,
             32 right-hand sides, forward on the 1% rewrite + backward;
   generator / pair / env: the rewrite-list generator, the L-then-U pair
             and the environment step on the 128^3 factor;
@@ -58,7 +58,7 @@ BATCH_SOURCES = SOLVE_SOURCES + ["paper_2609_40159_amd/csrc/batch.hip",
                                  "paper_2609_40159_amd/csrc/rewrite.hip",
                                  "paper_2609_40159_amd/csrc/u128.hpp"]
 METRIC = "SpTRSV HBM GB/s & solves/s, rewritten vs original DAG, fwd+adjoint, batched"
-SECTIONS = ["batch", "step128", "fp32", "config3", "config5", "generator", "pair", "env", "ppo"]
+SECTIONS = ["batch", "step128", "fp32", "powerlaw1m", "autograd", "generator", "pair", "env", "ppo"]
 
 
 def parse():
@@ -192,6 +192,16 @@ def roof(bytes_per_launch, avg_ms, kernel, levels=None, hop_ns=None, traffic=Non
         r["handoff_ns"] = hop_ns
         r["latency_floor_ms"] = levels * hop_ns * 1e-6
     return r
+
+
+def solve_kernel(algo: str, tname: str, trans: bool, k: int, rhs_chunk: int) -> str:
+    """Name of the kernel a plan launches for one solve (as the profiler shows it)."""
+    t = str(trans).lower()
+    if algo == "walk":
+        return f"k_solve_walk<{tname}, {t}>"
+    if algo == "syncfree":
+        return f"k_solve_sf<{tname}, {t}, {4 if rhs_chunk > 1 else 1}>"
+    return f"k_solve_level<{tname}, {t}, {4 if k > 1 else 1}>"
 
 
 def timed_events(fn, reps, warm=2, stream=None):
@@ -521,7 +531,7 @@ def run_step128(args, dev, dtype, hop_ns, steps):
     roofs = {}
     for ph, trans, nbytes in (("fwd", False, b_fwd), ("bwd", True, b_bwd)):
         algo = pinfo["algo_fwd"] if not trans else pinfo["algo_bwd"]
-        kname = f"k_solve_{'sf' if algo == 'syncfree' else 'level'}<{tname}, {str(trans).lower()}, 1>"
+        kname = solve_kernel(algo, tname, trans, k, pinfo["rhs_chunk"])
         tr = load_traffic(f"lap3d_128:{'f64' if s == 8 else 'f32'}:{kname}", srch,
                           pinfo["stage_outside"], pinfo["block_rows"])
         roofs[ph] = roof(nbytes, ms[ph], kname, Dp, hop_ns, tr)
@@ -587,8 +597,8 @@ def run_fp32(args, dev, hop_ns):
                 torch.as_tensor(P["xs"]).abs().max())
     n, nnzp = L.n, rw.nnz
     Dp = plan.info["stats"]["num_levels"]
-    kf = f"k_solve_{'sf' if plan.info['algo_fwd'] == 'syncfree' else 'level'}<float, false, 1>"
-    kb = f"k_solve_{'sf' if plan.info['algo_bwd'] == 'syncfree' else 'level'}<float, true, 1>"
+    kf = solve_kernel(plan.info["algo_fwd"], "float", False, 1, plan.info["rhs_chunk"])
+    kb = solve_kernel(plan.info["algo_bwd"], "float", True, 1, plan.info["rhs_chunk"])
     return {"workload": "128^3 Laplacian factor, FP32, k = 1, 1% rows rewritten",
             "fwd_ms": f, "bwd_ms": t, "orig_fwd_ms": fo, "orig_bwd_ms": to,
             "speedup_rewritten_vs_original_fwd": fo / f,
@@ -599,7 +609,7 @@ def run_fp32(args, dev, hop_ns):
             "roofline_bwd": roof(bytes_solve_t(n, nnzp, 1, 4), t, kb, Dp, hop_ns)}
 
 
-def run_config3(args, dev, hop_ns):
+def run_powerlaw1m(args, dev, hop_ns):
     """Power-law n = 1M, 64 right-hand sides, 0.8% of rows rewritten:
     forward solve and adjoint (transposed solve, M^T, grad_vals), rewritten
     vs original DAG."""
@@ -619,7 +629,7 @@ def run_config3(args, dev, hop_ns):
     plan = Plan(rw.Lp, algo="auto", kmax=k)
     plan_o = Plan(L, algo="auto", kmax=k)
     prep_s = time.perf_counter() - t0
-    log(f"config 3 prepared in {prep_s:.1f} s")
+    log(f"power-law 1M system prepared in {prep_s:.1f} s")
     f = timed_events(lambda: plan.solve(Bp), 3, warm=1)
     t = timed_events(lambda: plan.solve_transpose(G), 3, warm=1)
     X = plan.solve(Bp)
@@ -635,8 +645,8 @@ def run_config3(args, dev, hop_ns):
     n, nnz, nnzp = L.n, L.nnz, rw.nnz
     Dp, D0 = plan.info["stats"]["num_levels"], info.num_levels
     adj = t + mt + gv
-    kf = f"k_solve_{'sf' if plan.info['algo_fwd'] == 'syncfree' else 'level'}<double, false, 4>"
-    kb = f"k_solve_{'sf' if plan.info['algo_bwd'] == 'syncfree' else 'level'}<double, true, 4>"
+    kf = solve_kernel(plan.info["algo_fwd"], "double", False, k, plan.info["rhs_chunk"])
+    kb = solve_kernel(plan.info["algo_bwd"], "double", True, k, plan.info["rhs_chunk"])
     return {"workload": f"power-law n={n}, nnz={nnz}, k={k} RHS column-major, 0.8% rows "
                         f"rewritten (thin-first whole levels), FP64",
             "levels_original": D0, "levels_rewritten": Dp, "nnz_rewritten": nnzp,
@@ -658,7 +668,7 @@ def run_config3(args, dev, hop_ns):
                             + bytes_grad_vals(n, nnz, k, 8)) / adj / 1e6}
 
 
-def run_config5(args, dev, hop_ns):
+def run_autograd(args, dev, hop_ns):
     """torch.autograd.Function over the solve: forward on the thin-first 1%
     rewrite, backward = transposed solve, M^T and grad_vals, 32 RHS."""
     import numpy as np
@@ -1116,11 +1126,11 @@ def main():
     if "fp32" in secs:
         extras["fp32"] = run_fp32(args, dev, hop_ns)
         log("128^3 FP32 timed")
-    if "config3" in secs:
-        extras["config3"] = run_config3(args, dev, hop_ns)
+    if "powerlaw1m" in secs:
+        extras["powerlaw1m"] = run_powerlaw1m(args, dev, hop_ns)
         log("power-law 1M x 64 timed")
-    if "config5" in secs:
-        extras["config5"] = run_config5(args, dev, hop_ns)
+    if "autograd" in secs:
+        extras["autograd"] = run_autograd(args, dev, hop_ns)
         log("autograd workloads timed")
     if "ppo" in secs:
         extras["ppo"] = run_ppo(args, dev)

@@ -242,7 +242,10 @@ typedef struct {
     int32_t grid;             /* workgroups of the persistent launches */
     int32_t rhs_chunk;        /* sync-free right-hand-side columns per chain */
     int32_t stage_outside;    /* 1 or 2, as in rwt_plan_opts: what the plan uses */
-    double tuned_ms_level;    /* autotuner measurements (0 when not tuned) */
+    double tuned_ms_level;    /* autotuner measurements (0 when not tuned); the
+                                 level-scheduled figure is its warm-up run alone
+                                 when that run took over four times the best of
+                                 the other two */
     double tuned_ms_syncfree;
     double tuned_ms_walk;
     double chunk_rounds;      /* mean over 64-row chunks of the rounds the walk needs */

@@ -336,8 +336,10 @@ double time_solve(rwt_plan* p, Algo algo, int kt, hipStream_t s, int reps);
 double time_solve_full(rwt_plan* p, int kt, hipStream_t s);
 
 // Median-free timing: best of reps - 1 runs after one warm-up, on kt
-// columns of ones.
-double time_solve_rows(rwt_plan* p, Algo algo, int kt, hipStream_t s, int reps, int32_t rows) {
+// columns of ones. A warm-up run longer than cutoff ms ends the timing and
+// its own time is returned.
+double time_solve_rows(rwt_plan* p, Algo algo, int kt, hipStream_t s, int reps, int32_t rows,
+                       double cutoff = 1e30) {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return 1e30;
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -358,7 +360,10 @@ double time_solve_rows(rwt_plan* p, Algo algo, int kt, hipStream_t s, int reps, 
             break;
         }
         if (r > 0 && ms < best) best = ms;   // the first run warms up
-        if (reps == 1) best = ms;
+        if (reps == 1 || (r == 0 && ms > cutoff)) {
+            best = ms;
+            break;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -615,18 +620,25 @@ extern "C" rwt_status rwt_plan_create(const rwt_csr* L, const rwt_plan_opts* opt
                 best_sf = time_solve_full(p, kt, s);
                 p->tuned_sf = best_sf;
             }
-            p->tuned_level = time_solve(p, Algo::Level, kt, s, 3);
-            if (p->tuned_level >= 1e30 && best_sf >= 1e30) {
+            // the row-order walk, on the whole matrix, where the model says
+            // it may win
+            const double walk_ms =
+                p->walk_ok ? time_solve_rows(p, Algo::Walk, kt, s, 3, 0) : 1e30;
+            if (p->walk_ok) p->tuned_walk = walk_ms;
+            // the level-scheduled solve: a warm-up run over four times the
+            // best time so far cannot win and is not repeated (on deep
+            // power-law matrices it takes seconds)
+            p->tuned_level = time_solve_rows(p, Algo::Level, kt, s, 3, 0,
+                                             4.0 * std::min(best_sf, walk_ms));
+            if (p->tuned_level >= 1e30 && best_sf >= 1e30 && walk_ms >= 1e30) {
                 set_error("autotuning solves failed");
                 return fail(RWT_ERR_DEADLOCK);
             }
-            p->fwd = p->bwd = p->tuned_level < best_sf ? Algo::Level : Algo::SyncFree;
-            // the row-order walk, on the whole matrix, where the model says
-            // it may win
-            if (p->walk_ok) {
-                p->tuned_walk = time_solve_rows(p, Algo::Walk, kt, s, 3, 0);
-                if (p->tuned_walk < std::min(p->tuned_level, best_sf)) p->fwd = p->bwd = Algo::Walk;
-            }
+            Algo pick = Algo::SyncFree;
+            double pick_ms = best_sf;
+            if (p->tuned_level < pick_ms) { pick = Algo::Level; pick_ms = p->tuned_level; }
+            if (walk_ms < pick_ms) pick = Algo::Walk;
+            p->fwd = p->bwd = pick;
         }
     }
     if ((st = build_blocks(R)) != RWT_OK) return fail(st);
