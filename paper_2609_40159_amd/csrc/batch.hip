@@ -45,6 +45,8 @@ constexpr int BT_THREADS = 256;
 // tasks four candidates (one per wave)
 constexpr int WK_SOLVE_WAVES = 2;
 constexpr int WK_LEVEL_WAVES = 4;
+// share of the early task claims that go to walk tasks: one in this many
+constexpr size_t WALK_CLAIM_EVERY = 5;
 constexpr int BT_LDS = SF_LDS_BUDGET;
 // candidate rows whose rewritten pattern outgrows both LDS tiers are redone
 // in workspace slabs (one wave each, n + 1 entries per buffer), this many at
@@ -1345,7 +1347,7 @@ extern "C" rwt_status rwt_batch_create(const rwt_batch_desc* desc, void* d_ws, s
         }
     };
     // one solve chain per chunk of kc right-hand-side columns; row-order
-    // walks, which wait on nothing, go first, longest first
+    // walks, which wait on nothing, longest first (interleaved below)
     for (int32_t m = 0; m < desc->count; ++m) {
         if (b->plans[m]->fwd == Algo::Walk) {
             for (int32_t q = 0; q < b->mats[m].k; q += WK_SOLVE_WAVES)
@@ -1390,8 +1392,23 @@ extern "C" rwt_status rwt_batch_create(const rwt_batch_desc* desc, void* d_ws, s
         c += gs;
     }
     std::stable_sort(tv.begin(), tv.end(), [](const T& x, const T& y) { return x.key < y.key; });
+    // Walks (kinds 3 and 4, longest first) wait on nothing but hold their
+    // workgroup for the whole walk while using little of the compute unit;
+    // claimed all at once they would fill the grid and hold back the level
+    // chains and sweeps. They are interleaved instead, one claim in
+    // WALK_CLAIM_EVERY, for as long as both lists last; the other tasks keep
+    // their order, which is topological along every chain.
     std::vector<int4> tasks(tv.size());
-    for (size_t i = 0; i < tv.size(); ++i) tasks[i] = tv[i].t;
+    {
+        std::vector<int4> walks, rest;
+        for (const T& x : tv) (x.t.x == 3 || x.t.x == 4 ? walks : rest).push_back(x.t);
+        size_t iw = 0, ir = 0;
+        for (size_t p = 0; p < tv.size(); ++p) {
+            const bool walk = iw < walks.size() &&
+                              (ir >= rest.size() || iw * WALK_CLAIM_EVERY < p + 1);
+            tasks[p] = walk ? walks[iw++] : rest[ir++];
+        }
+    }
     b->ntasks = (int32_t)tasks.size();
     if (hipMemcpyAsync(b->d_mats, hm.data(), sizeof(BatchMatDev) * hm.size(), hipMemcpyHostToDevice,
                        s) != hipSuccess ||
