@@ -251,6 +251,9 @@ __device__ __forceinline__ T wk_rounds(const WkArgs& a, T* xr, const int32_t* ej
     auto J = [&](int32_t e) -> int32_t { return STAGED ? ej[e] : a.idx[base + e]; };
     auto V = [&](int32_t e) -> T { return STAGED ? ev[e] : vals[base + e]; };
     const bool act = lane < cnt;
+    // x = (b - sum) times the diagonal's reciprocal, formed here, off the
+    // rounds' dependent chain
+    const T rdiag = T(1) / diag;
     // the in-chunk terms: the first WK_KREG of each row in registers, in
     // walk order (value and the lane holding the dependency's x), and the
     // mask of in-chunk dependencies (long rows have it already)
@@ -300,7 +303,7 @@ __device__ __forceinline__ T wk_rounds(const WkArgs& a, T* xr, const int32_t* ej
                         s += V(e) * xr[pos_of(J(e)) & (WK_W - 1)];
                 }
             }
-            xi = (b_i - s) / diag;
+            xi = (b_i - s) * rdiag;
             if (ring_rounds) xr[(t0 + lane) & (WK_W - 1)] = xi;
         }
         if (ring_rounds) asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
