@@ -91,6 +91,29 @@ struct BatchCandDev {
     int32_t* lev;       // levels of L', tagged with the launch epoch
 };
 
+// the tables' pointers, marked global (in_global)
+__device__ __forceinline__ BatchMatDev mat_g(const BatchMatDev& m) {
+    BatchMatDev o = m;
+    o.perm = in_global(m.perm);
+    o.lptr = in_global(m.lptr);
+    o.rowptr = in_global(m.rowptr);
+    o.colidx = in_global(m.colidx);
+    o.level = in_global(m.level);
+    o.vals = in_global(m.vals);
+    o.desc = in_global(m.desc);
+    o.step_pos = in_global(m.step_pos);
+    o.blk_step = in_global(m.blk_step);
+    o.B = in_global(m.B);
+    o.X = in_global(m.X);
+    return o;
+}
+__device__ __forceinline__ BatchCandDev cand_g(const BatchCandDev& c) {
+    BatchCandDev o = c;
+    o.bitmap = in_global(c.bitmap);
+    o.lev = in_global(c.lev);
+    return o;
+}
+
 struct BatchKArgs {
     const BatchMatDev* mats;
     const BatchCandDev* cands;
@@ -200,7 +223,7 @@ __device__ __forceinline__ void sweep_group(const BatchKArgs& a, const BatchMatD
         for (int32_t s = 0; s < gs; ++s) {
             const int32_t c = c0 + s;
             if (a.cand_bad[c]) continue;
-            const BatchCandDev& Cd = a.cands[c];
+            const BatchCandDev Cd = cand_g(a.cands[c]);
             const int32_t qb = a.cand_ptr[c], qe = a.cand_ptr[c + 1];
             for (int32_t q = qb + threadIdx.x; q < qe; q += blockDim.x) {
                 const int32_t r = a.rows[q];
@@ -219,7 +242,7 @@ __device__ __forceinline__ void sweep_group(const BatchKArgs& a, const BatchMatD
 #pragma unroll
             for (int s = 0; s < SG; ++s) {
                 if (s >= gs) break;
-                const BatchCandDev& Cd = a.cands[c0 + s];
+                const BatchCandDev Cd = cand_g(a.cands[c0 + s]);
                 if (!a.cand_bad[c0 + s] && ((Cd.bitmap[i >> 5] >> (i & 31)) & 1u)) rw |= 1u << s;
             }
             int32_t mx[SG];
@@ -333,7 +356,7 @@ __device__ __forceinline__ void level_block_group(const BatchKArgs& a, const Bat
     }
     __syncthreads();
     for (int32_t s = 0; s < gs; ++s) {
-        const BatchCandDev& Cd = a.cands[c0 + s];
+        const BatchCandDev Cd = cand_g(a.cands[c0 + s]);
         const int32_t qb = a.cand_ptr[c0 + s];
         for (int32_t q = qr[2 * s] + threadIdx.x; q < qr[2 * s + 1]; q += blockDim.x) {
             const int32_t r = a.rows[q];
@@ -364,7 +387,7 @@ __device__ __forceinline__ void level_block_group(const BatchKArgs& a, const Bat
 #pragma unroll
                 for (int s = 0; s < SG; ++s) {
                     if (s >= gs) break;
-                    const BatchCandDev& Cd = a.cands[c0 + s];
+                    const BatchCandDev Cd = cand_g(a.cands[c0 + s]);
                     if (!a.cand_bad[c0 + s] && ((Cd.bitmap[i >> 5] >> (i & 31)) & 1u))
                         rw |= 1u << s;
                 }
@@ -543,7 +566,7 @@ __device__ __forceinline__ void finalize_group(const BatchKArgs& a, const BatchM
         // rejected candidate's list is never read: its bounds may be invalid)
         for (int32_t s = 0; s < gs; ++s) {
             const int32_t c = c0 + s;
-            const BatchCandDev& Cd = a.cands[c];
+            const BatchCandDev Cd = cand_g(a.cands[c]);
             const int32_t qb = a.cand_ptr[c], qe = a.cand_bad[c] ? qb : a.cand_ptr[c + 1];
             for (int32_t q = qb + threadIdx.x; q < qe; q += blockDim.x) {
                 const int32_t r = a.rows[q];
@@ -597,7 +620,7 @@ __global__ void __launch_bounds__(BT_THREADS) k_batch_main(BatchKArgs a) {
         if (t >= a.ntasks) break;
         const int4 tk = a.tasks[t];
         if (tk.x == 0) {
-            const BatchMatDev& M = a.mats[tk.y];
+            const BatchMatDev M = mat_g(a.mats[tk.y]);
             const int32_t q0 = tk.w * M.kc;   // this chain's first column
             SfBlockArgs b;
             b.r0 = tk.z * M.R;
@@ -626,7 +649,7 @@ __global__ void __launch_bounds__(BT_THREADS) k_batch_main(BatchKArgs a) {
         } else if (tk.x == 3) {
             // row-order walks of columns tk.z .. tk.z + tk.w - 1 of matrix tk.y,
             // one wave each
-            const BatchMatDev& M = a.mats[tk.y];
+            const BatchMatDev M = mat_g(a.mats[tk.y]);
             const int w = threadIdx.x / WAVE;
             if (w < tk.w) {
                 const int32_t q = tk.z + w;
@@ -647,11 +670,11 @@ __global__ void __launch_bounds__(BT_THREADS) k_batch_main(BatchKArgs a) {
             // row-order walks of the levels of candidates tk.y .. tk.y + tk.z - 1
             // (one matrix), one wave each, then their statistics
             const int32_t c0 = tk.y, gs = tk.z;
-            const BatchMatDev& M = a.mats[a.cands[c0].m];
+            const BatchMatDev M = mat_g(a.mats[a.cands[c0].m]);
             const int w = threadIdx.x / WAVE;
             if (w < gs) {
                 const int32_t c = c0 + w;
-                const BatchCandDev& Cd = a.cands[c];
+                const BatchCandDev Cd = cand_g(a.cands[c]);
                 // each rewritten row's slot holds its offset in the row list
                 const int32_t qb = a.cand_ptr[c], qe = a.cand_bad[c] ? qb : a.cand_ptr[c + 1];
                 for (int32_t q = qb + lane_id(); q < qe; q += WAVE) {
@@ -677,21 +700,21 @@ __global__ void __launch_bounds__(BT_THREADS) k_batch_main(BatchKArgs a) {
             }
             __syncthreads();
             for (int32_t s = 0; s < gs; ++s)
-                finalize_group(a, M, c0 + s, 1, a.cands[c0 + s].lev, tag, true, s_raw);
+                finalize_group(a, M, c0 + s, 1, in_global(a.cands[c0 + s].lev), tag, true, s_raw);
         } else if (tk.x == 2) {
             // a sweep group: candidates tk.y .. tk.y + tk.z - 1 of one matrix,
             // levels interleaved in the first one's (and its neighbours')
             // level arrays
-            const BatchCandDev& Cd = a.cands[tk.y];
-            const BatchMatDev& M = a.mats[Cd.m];
+            const BatchCandDev Cd = cand_g(a.cands[tk.y]);
+            const BatchMatDev M = mat_g(a.mats[Cd.m]);
             sweep_group(a, M, tk.y, tk.z, Cd.lev, tag);
             __syncthreads();
             finalize_group(a, M, tk.y, tk.z, Cd.lev, tag, true, s_raw);
         } else {
             // one row block of the level chains of candidates tk.y .. tk.y + tk.w - 1
             const int32_t c0 = tk.y;
-            const BatchCandDev& Cd = a.cands[c0];
-            const BatchMatDev& M = a.mats[Cd.m];
+            const BatchCandDev Cd = cand_g(a.cands[c0]);
+            const BatchMatDev M = mat_g(a.mats[Cd.m]);
             level_block_group(a, M, c0, tk.w, Cd.lev, tk.z, tag, s_raw);
             __syncthreads();
             if (threadIdx.x == 0)
@@ -750,7 +773,7 @@ __global__ void k_batch_begin(const BatchMatDev* mats, int32_t count, uint32_t* 
         for (int64_t i = tid; i < lev_words; i += nth) levs[i] = 0;
     const double s = sentinel_value<double>();
     for (int32_t m = 0; m < count; ++m) {
-        const BatchMatDev& M = mats[m];
+        const BatchMatDev M = mat_g(mats[m]);
         const int64_t total = (int64_t)M.n * M.k;
         for (int64_t e = tid; e < total; e += nth) {
             const int64_t q = e / M.n, i = e - q * M.n;
@@ -804,8 +827,8 @@ __global__ void k_batch_bitmap(const BatchMatDev* mats, const BatchCandDev* cand
     const int lane = lane_id();
     const bool list_ok = ld_relaxed(&rwctrl[6]) == 0;
     for (int64_t c = wave; c < C; c += nw) {
-        const BatchCandDev& Cd = cands[c];
-        const BatchMatDev& M = mats[Cd.m];
+        const BatchCandDev Cd = cand_g(cands[c]);
+        const BatchMatDev M = mat_g(mats[Cd.m]);
         const int32_t qb = cand_ptr[c], qe = cand_ptr[c + 1];
         bool bad = !list_ok || qe < qb || qb < 0 || qe > qcap;
         if (!bad) {

@@ -127,6 +127,19 @@ __device__ __forceinline__ T group_sum(T v, int G) {
 }
 
 // agent-scope (device-wide) atomics
+// A pointer read from memory (a table of matrices, say) has no known address
+// space, so the compiler accesses its data with flat instructions, which
+// count against the LDS wait counter too: every LDS wait then also waits
+// for the global loads in flight (and the walks and row blocks keep loads in
+// flight on purpose). Passed through an opaque value in the global address
+// space, every access derived from it becomes a global one.
+template <typename T>
+__device__ __forceinline__ T* in_global(T* p) {
+    __attribute__((address_space(1))) T* g = (__attribute__((address_space(1))) T*)p;
+    asm("" : "+v"(g));
+    return (T*)g;
+}
+
 template <typename T>
 __device__ __forceinline__ T ld_relaxed(const T* p) {
     return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -611,9 +611,9 @@ __device__ inline RwArgs batch_row_args(const BatchRwArgsDev& ba, int32_t q) {
     a.cand_bad_out = ba.cand_bad;
     a.cand_index = c;
     a.n = M.n;
-    a.rowptr = M.rowptr;
-    a.colidx = M.colidx;
-    a.level = M.level;
+    a.rowptr = in_global(M.rowptr);
+    a.colidx = in_global(M.colidx);
+    a.level = in_global(M.level);
     a.set_rows = ba.rows;
     a.targets = ba.targets;
     a.ctrl = ba.ctrl;

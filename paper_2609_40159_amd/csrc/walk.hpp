@@ -231,6 +231,7 @@ __device__ __forceinline__ void wk_stage_entries(const WkArgs& a, const WkPtr& p
 
 constexpr int WK_LONG = 24;
 constexpr int WK_KREG = 4;   // in-chunk dependencies a lane keeps in registers for the rounds
+constexpr int WK_RWU = 4;    // list entries per lane a level walk requests at once for a rewritten row
 
 // The in-chunk part of a chunk's rows (both walks of values): each row's
 // sum of the terms before the chunk is acc, its in-chunk entries are
@@ -429,7 +430,7 @@ __device__ __forceinline__ T wk_rows(const WkArgs& a, T* xr, const int32_t* rp, 
 // Solve one column: rows in walk order, chunk by chunk.  Every lane of the
 // wave calls it.
 template <typename T, bool TRANS>
-__device__ void wk_solve(const WkArgs& a, WkLds<T>* L) {
+__device__ __forceinline__ void wk_solve(const WkArgs& a, WkLds<T>* L) {
     const int lane = lane_id();
     const int32_t n = a.n;
     if (n <= 0) return;
@@ -576,7 +577,7 @@ __device__ __forceinline__ int32_t wk_first_set(const uint64_t* m, int32_t eb, i
 }
 
 template <typename T, bool TRANS>
-__device__ void wk_solve2(const WkArgs& a, WkLds2<T>* L) {
+__device__ __forceinline__ void wk_solve2(const WkArgs& a, WkLds2<T>* L) {
     const int lane = lane_id();
     // wave 0 stages, wave 1 solves; further waves of the workgroup only
     // take part in the barriers
@@ -846,7 +847,7 @@ __device__ __forceinline__ bool wk_marked(int32_t v, uint32_t tag, uint32_t mark
     return ((uint32_t)v >> 24) == tag && ((uint32_t)v & mark);
 }
 
-__device__ void wk_levels(const WkLvlArgs& a, WkLvlLds* L) {
+__device__ __forceinline__ void wk_levels(const WkLvlArgs& a, WkLvlLds* L) {
     const int lane = lane_id();
     const int32_t n = a.n;
     if (n <= 0) return;
@@ -898,31 +899,24 @@ __device__ void wk_levels(const WkLvlArgs& a, WkLvlLds* L) {
         };
         int32_t best = -1;       // largest level of the dependencies before the chunk
         uint64_t dep = 0;        // dependencies in the chunk, by lane
-        // rewritten rows first (their lists come from HBM), one at a time by
-        // the whole wave
+        // rewritten rows take their lists from HBM: the first WK_RWU * WAVE
+        // entries of the chunk's first such row are requested now (a fixed
+        // number of loads, a dummy address past the list), so that they
+        // arrive while the chunk's entries are staged below
         const bool rw = act && q_cur.ne >= q_cur.nb;
-        for (uint64_t m = __ballot(rw); m != 0; m &= m - 1) {
-            const int owner = __builtin_ctzll(m);
-            const int32_t nb = wk_lane_val(q_cur.nb, owner), ne = wk_lane_val(q_cur.ne, owner);
-            const int32_t io = lo + owner;
-            int32_t mx = -1;
-            uint64_t dm = 0;
-            for (int32_t p0 = nb; p0 < ne; p0 += WAVE) {
-                const int32_t pp = p0 + lane;
-                int32_t r = pp < ne ? a.pat[pp] : -1;
-                if (pp < ne && (r < 0 || r >= io)) {
-                    __hip_atomic_store(a.err, (int32_t)RWT_ERR_INVALID_ARG, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                    r = -1;
-                }
-                if (r >= 0 && r < lo) mx = max(mx, lvl_out(r));
-                if (r >= lo) dm |= 1ull << (r - lo);
+        const uint64_t rwm = __ballot(rw);
+        int32_t pre[WK_RWU];
+        {
+            int32_t f_nb = 0, f_ne = 0;
+            if (rwm != 0) {
+                const int o = __builtin_ctzll(rwm);
+                f_nb = wk_lane_val(q_cur.nb, o);
+                f_ne = wk_lane_val(q_cur.ne, o);
             }
-            mx = wk_max(mx);
-            dm = wk_or(dm);   // OR of the lanes' in-chunk masks
-            if (lane == owner) {
-                best = mx;
-                dep = dm;
+#pragma unroll
+            for (int u = 0; u < WK_RWU; ++u) {
+                const int32_t pp = f_nb + u * WAVE + lane;
+                pre[u] = *(pp < f_ne ? a.pat + pp : a.pat_ptr);
             }
         }
         L->rp[lane] = p_cur.rpv - base;
@@ -969,6 +963,49 @@ __device__ void wk_levels(const WkLvlArgs& a, WkLvlLds* L) {
                     if (r < ring_lo) L->el[e] = ld_relaxed(&a.lev[r]) & lmask;
                 }
         }
+        // the rewritten rows, one at a time by the whole wave: the first
+        // one's head from the registers above, the rest WK_RWU * WAVE entries
+        // per request (before the next chunk's loads are issued, so that
+        // waiting for these does not wait for those)
+        for (uint64_t m = rwm; m != 0; m &= m - 1) {
+            const int owner = __builtin_ctzll(m);
+            const int32_t nb = wk_lane_val(q_cur.nb, owner), ne = wk_lane_val(q_cur.ne, owner);
+            const int32_t io = lo + owner;
+            int32_t mx = -1;
+            uint64_t dm = 0;
+            auto take = [&](int32_t pp, int32_t r) {
+                if (pp >= ne) return;
+                if (r < 0 || r >= io) {
+                    __hip_atomic_store(a.err, (int32_t)RWT_ERR_INVALID_ARG, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    return;
+                }
+                if (r < lo) mx = max(mx, lvl_out(r));
+                else dm |= 1ull << (r - lo);
+            };
+            int32_t p0 = nb;
+            if (m == rwm) {
+#pragma unroll
+                for (int u = 0; u < WK_RWU; ++u) take(nb + u * WAVE + lane, pre[u]);
+                p0 += WK_RWU * WAVE;
+            }
+            for (; p0 < ne; p0 += WK_RWU * WAVE) {
+                int32_t rr[WK_RWU];
+#pragma unroll
+                for (int u = 0; u < WK_RWU; ++u) {
+                    const int32_t pp = p0 + u * WAVE + lane;
+                    rr[u] = pp < ne ? a.pat[pp] : -1;
+                }
+#pragma unroll
+                for (int u = 0; u < WK_RWU; ++u) take(p0 + u * WAVE + lane, rr[u]);
+            }
+            mx = wk_max(mx);
+            dm = wk_or(dm);   // OR of the lanes' in-chunk masks
+            if (lane == owner) {
+                best = mx;
+                dep = dm;
+            }
+        }
         // the next chunks' loads (the staging registers are free again):
         // pointers and list bounds first, since the copies at the end of the
         // chunk wait for them (loads complete in order), then the entries
@@ -986,11 +1023,17 @@ __device__ void wk_levels(const WkLvlArgs& a, WkLvlLds* L) {
             const int32_t cb = wk_lane_val(eb, o), ce = wk_lane_val(ee, o);
             int32_t mx = -1;
             uint64_t dm = 0;
-            for (int32_t e0 = cb; e0 < ce; e0 += WAVE) {
-                const int32_t e = e0 + lane;
-                if (e < ce) {
-                    const int32_t r = staged ? ej[e] : a.colidx[base + e];
-                    if (r < lo) mx = max(mx, staged ? L->el[e] : lvl_out(r));
+            // (two loops, so that no pointer selects between LDS and HBM)
+            if (staged) {
+                for (int32_t e = cb + lane; e < ce; e += WAVE) {
+                    const int32_t r = ej[e];
+                    if (r < lo) mx = max(mx, L->el[e]);
+                    else dm |= 1ull << (r - lo);
+                }
+            } else {
+                for (int32_t e = cb + lane; e < ce; e += WAVE) {
+                    const int32_t r = a.colidx[base + e];
+                    if (r < lo) mx = max(mx, lvl_out(r));
                     else dm |= 1ull << (r - lo);
                 }
             }
