@@ -470,31 +470,34 @@ __device__ __forceinline__ void wk_solve(const WkArgs& a, WkLds<T>* L) {
             // dependencies older than the ring in a second pass (rare: it
             // waits for HBM)
             bool far = false;
+            // every slot's ring value read and every slot written, the
+            // padding past E included (no reader goes past E): no branches,
+            // which would each save and restore the lane mask
             T xv[WK_U];
 #pragma unroll
             for (int u = 0; u < WK_U; ++u) {
                 const int32_t e = lane + u * WAVE;
                 const int32_t r = e < E ? st.j[u] : (TRANS ? hi : lo);   // padding: in the chunk
                 const int32_t t = TRANS ? n - 1 - r : r;
-                xv[u] = (t < t0 && t >= ring_lo) ? L->xr[t & (WK_W - 1)] : T(1);
+                const T xo = L->xr[t & (WK_W - 1)];
+                xv[u] = (t < t0 && t >= ring_lo) ? xo : T(1);
                 far = far || t < ring_lo;
             }
-            // slice u's mask to LDS as soon as it is formed (one live mask)
+            // slice masks: lane u keeps slice u's
+            uint64_t smv = 0;
 #pragma unroll
             for (int u = 0; u < WK_U; ++u) {
-                if (u * WAVE >= E) break;
                 const int32_t e = lane + u * WAVE;
                 const int32_t t = TRANS ? n - 1 - st.j[u] : st.j[u];
                 const uint64_t m = __ballot(e < E && (TRANS ? t < t0 : t >= t0));
-                if (lane == 0) L->sm[u] = m;
+                smv = lane == u ? m : smv;
             }
+            if (lane < WK_U) L->sm[lane] = smv;
 #pragma unroll
             for (int u = 0; u < WK_U; ++u) {
                 const int32_t e = lane + u * WAVE;
-                if (e < E) {
-                    ej[e] = st.j[u];
-                    ev[e] = st.v[u] * xv[u];
-                }
+                ej[e] = st.j[u];
+                ev[e] = st.v[u] * xv[u];
             }
             if (__ballot(far) != 0) {
                 for (int32_t e = lane; e < E; e += WAVE) {
@@ -930,6 +933,9 @@ __device__ __forceinline__ void wk_levels(const WkLvlArgs& a, WkLvlLds* L) {
             // the staged entries into LDS with the levels of the dependencies
             // before the chunk: ring, then (rare) older ones from HBM in a
             // second pass
+            // Every slot is written and every ring slot read, the padding
+            // past E included (no reader goes past E): no branches, which
+            // would each save and restore the lane mask
             const int32_t ring_lo = lo + WAVE - WK_W;
             bool far = false;
             int32_t rv[WK_U];
@@ -937,26 +943,25 @@ __device__ __forceinline__ void wk_levels(const WkLvlArgs& a, WkLvlLds* L) {
             for (int u = 0; u < WK_U; ++u) {
                 const int32_t e = lane + u * WAVE;
                 rv[u] = e < E ? sj[u] : lo;   // padding: an in-chunk row
-                if (e < E) ej[e] = rv[u];
+                ej[e] = rv[u];
             }
             int32_t lv[WK_U];
 #pragma unroll
             for (int u = 0; u < WK_U; ++u) {
-                lv[u] = (rv[u] < lo && rv[u] >= ring_lo) ? L->lr[rv[u] & (WK_W - 1)] : -1;
+                lv[u] = L->lr[rv[u] & (WK_W - 1)];
                 far = far || rv[u] < ring_lo;
             }
 #pragma unroll
-            for (int u = 0; u < WK_U; ++u) {
-                const int32_t e = lane + u * WAVE;
-                if (e < E) L->el[e] = lv[u];
-            }
-            // slice masks of in-chunk dependencies, one live at a time
+            for (int u = 0; u < WK_U; ++u)
+                L->el[lane + u * WAVE] = (rv[u] < lo && rv[u] >= ring_lo) ? lv[u] : -1;
+            // slice masks of in-chunk dependencies: lane u keeps slice u's
+            uint64_t smv = 0;
 #pragma unroll
             for (int u = 0; u < WK_U; ++u) {
-                if (u * WAVE >= E) break;
                 const uint64_t m = __ballot(lane + u * WAVE < E && rv[u] >= lo);
-                if (lane == 0) L->sm[u] = m;
+                smv = lane == u ? m : smv;
             }
+            if (lane < WK_U) L->sm[lane] = smv;
             if (__ballot(far) != 0)
                 for (int32_t e = lane; e < E; e += WAVE) {
                     const int32_t r = ej[e];
