@@ -77,3 +77,22 @@ def test_traffic_is_reported_only_for_the_profiled_configuration(tmp_path, monke
     tj.write_text("not json")
     assert bench.load_traffic(key, "abc", "off", 4096) is None
 
+
+
+def test_roofline_kernel_names_follow_the_schedule():
+    # the names the profiler reports for the kernel a plan launches: the
+    # walk has no column-count parameter; sync-free blocks take four
+    # columns per chain when the chain has more than one, the level-by-level
+    # solve when the solve has more than one column
+    assert bench.solve_kernel("walk", "double", False, 64, 1) == "k_solve_walk<double, false>"
+    assert bench.solve_kernel("walk", "float", True, 1, 1) == "k_solve_walk<float, true>"
+    assert bench.solve_kernel("syncfree", "double", False, 64, 1) == "k_solve_sf<double, false, 1>"
+    assert bench.solve_kernel("syncfree", "double", True, 64, 4) == "k_solve_sf<double, true, 4>"
+    assert bench.solve_kernel("level", "double", False, 1, 1) == "k_solve_level<double, false, 1>"
+    assert bench.solve_kernel("level", "float", True, 32, 1) == "k_solve_level<float, true, 4>"
+    # the names appear in the library's own launch code
+    src = open(os.path.join(ROOT, "paper_2609_40159_amd", "csrc", "solve.hip")).read()
+    for frag in ("k_solve_walk<double, false>", "k_solve_walk<float, true>",
+                 "k_solve_sf<T, TRANS, 4>", "k_solve_sf<T, TRANS, 1>",
+                 "k_solve_level<T, TRANS, 4>", "k_solve_level<T, TRANS, 1>"):
+        assert frag in src, frag
