@@ -862,6 +862,10 @@ def tall_block_order(rowptr, colidx, a: int = 0, b: int = 0) -> np.ndarray:
     n = rp.shape[0] - 1
     if n < 0:
         raise ValueError("rowptr needs n + 1 entries")
+    if n > 0 and (rp[0] != 0 or np.any(np.diff(rp) < 0)):
+        raise ValueError("rowptr must start at 0 and be non-decreasing")
+    if ci.shape[0] < (int(rp[-1]) if n > 0 else 0):
+        raise ValueError(f"colidx has {ci.shape[0]} entries, rowptr[n] = {int(rp[-1])}")
     perm = np.empty(n, dtype=np.int32)
     check(lib.rwt_tall_block_order(n, rp.ctypes.data, ci.ctypes.data, a, b, perm.ctypes.data))
     return perm

@@ -57,6 +57,13 @@ def test_malformed_patterns_are_refused():
     with pytest.raises(RwtError):                                  # negative tile shape
         tall_block_order(np.array([0, 1]), np.array([0]), -1, 0)
     assert tall_block_order(np.array([0]), np.array([], dtype=np.int32)).size == 0
+    # arrays that disagree in length are refused before the library reads them
+    with pytest.raises(ValueError):                                # colidx shorter than rowptr[n]
+        tall_block_order(np.array([0, 1, 3]), np.array([0, 0]))
+    with pytest.raises(ValueError):                                # rowptr decreasing
+        tall_block_order(np.array([0, 2, 1]), np.array([0, 0, 1]))
+    with pytest.raises(ValueError):                                # rowptr not starting at 0
+        tall_block_order(np.array([1, 2]), np.array([0, 0]))
 
 
 def test_order_of_L_stays_topological_for_the_rewritten_factor():
